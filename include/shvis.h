@@ -1,0 +1,149 @@
+/*
+ * shvis.h - C ABI of the MI355X (gfx950) SH soft-shadow library.
+ *
+ * Method: "Efficient and Differentiable Shadow Computation for Inverse
+ * Problems" (Lyu et al., ICCV 2021).  Occluders are spheres (c_i, r_i); for a
+ * receiver x with normal n(x) and albedo a(x), under lighting SH vector L:
+ *
+ *   visibility  V(x) = exp*( sum_i f_i(x) )                    Sec. 3.3.2
+ *       f_i = log-visibility of sphere i: -eps on the cone of half-angle
+ *             asin(r_i / |c_i - x|) around (c_i - x)/|c_i - x|, 0 elsewhere
+ *             (Eq. 13, eps = 3), projected about z analytically and rotated
+ *             to that direction; exp* is the SH exponential by DC isolation,
+ *             scaling by 2^-k, optimal linear approximation and k truncated
+ *             squarings with the triple product of Eqs. 6-7;
+ *   radiance    B(x) = a(x) * ( L . (V(x) * H(x)) )            Eq. 8
+ *       H(x) = rotated clamped cosine max(n . w, 0) (Eqs. 10-11).
+ *
+ * Conventions shared by every entry point
+ *   - SH vectors have N = n_bands^2 coefficients, index i = l*l + l + m
+ *     (Sec. 3.2), real orthonormal basis without Condon-Shortley phase
+ *     (y_lm ~ cos(m phi) for m > 0, sin(|m| phi) for m < 0).
+ *   - Every array pointer is a DEVICE pointer owned by the caller; FP32.
+ *     Per-receiver arrays are structure-of-arrays: points / normals are
+ *     [3][P] (all x, then all y, then all z), SH arrays are [N][P]
+ *     (coefficient-major), albedo and radiance are [P].  Spheres are [S][4]
+ *     (cx, cy, cz, r), 16-byte aligned.  Lighting is [N].
+ *   - Outputs are overwritten, never accumulated.  An optional output may
+ *     be NULL; it is then not computed.
+ *   - Work is enqueued on `stream` (0 = the null stream); no entry point
+ *     allocates device memory, frees it, or synchronises the host.  Scratch
+ *     memory comes from the caller's workspace `ws` of `ws_bytes` bytes
+ *     (256-byte aligned), sized by shv_workspace_bytes().
+ *   - P = 0 is a valid no-op; S = 0 means "no occluders" (V = sqrt(4 pi) e_0).
+ *   - Errors: validation failures return before any launch; a failed launch
+ *     returns SHV_ERR_HIP.  shv_last_error() gives the thread's last message.
+ *     No C++ exception crosses this boundary.
+ *   - Results are deterministic: reductions run in a fixed order, so two
+ *     identical calls give bit-identical outputs.
+ */
+#ifndef SHVIS_H
+#define SHVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t shv_status;
+#define SHV_OK 0
+#define SHV_ERR_INVALID_ARG (-1)     /* NULL required pointer, negative size, misalignment */
+#define SHV_ERR_UNSUPPORTED (-2)     /* n_bands outside [1, 8], n_squarings outside [0, 12] */
+#define SHV_ERR_WORKSPACE (-3)       /* ws_bytes smaller than shv_workspace_bytes() */
+#define SHV_ERR_NOT_INITIALIZED (-4) /* shv_init() not called for the current device */
+#define SHV_ERR_HIP (-5)             /* a HIP runtime call or kernel launch failed */
+
+#define SHV_MAX_BANDS_API 8
+#define SHV_MAX_SQUARINGS 12
+
+/* Method parameters.  n_bands: number of SH bands n (l < n), the paper uses
+ * n = 8 (Sec. 3.2).  n_squarings: k, the number of squarings of the SH
+ * exponential (fixed per call; 4 by default).  eps: depth of the log-blocker,
+ * log V' = -eps inside a sphere's cone (Eq. 13; the paper uses 3).  flags:
+ * reserved, must be 0. */
+typedef struct shv_params {
+  int32_t n_bands;
+  int32_t n_squarings;
+  float eps;
+  uint32_t flags;
+} shv_params;
+
+/* Makes `device` current and prepares the library for it.  Idempotent and
+ * thread-safe.  Returns SHV_ERR_HIP if the device is unusable. */
+shv_status shv_init(int device);
+
+/* Human-readable text of a status code (static storage). */
+const char* shv_status_string(shv_status s);
+
+/* The calling thread's last error message ("" if none; thread-local storage). */
+const char* shv_last_error(void);
+
+/* Number of FP32 values the forward saves for the backward, per call:
+ * (1 + k * N) * P  (the DC value c and E_0 .. E_{k-1} of the exponential). */
+int64_t shv_saved_floats(int64_t P, const shv_params* prm);
+
+/* Workspace bytes that every entry point below needs for P receivers and S
+ * spheres (the maximum over all of them, so one buffer serves a whole
+ * forward + backward).  Returns 0 for invalid parameters. */
+size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm);
+
+/* Visibility in SH space (Sec. 3.3.2: per-sphere log-cap projected about z
+ * and rotated to the sphere direction, summed, exponentiated).
+ *   points  [3][P]  receiver positions x
+ *   spheres [S][4]  occluders (cx, cy, cz, r), r >= 0
+ *   vis     [N][P]  out: V(x)
+ *   saved   [(1 + k N)][P]  out: state for sh_visibility_backward (may be
+ *                   NULL when no backward will follow)
+ * A receiver inside a sphere (r >= |c - x|) sees a hemisphere cap; a sphere
+ * centred exactly on the receiver contributes nothing. */
+shv_status sh_visibility_forward(const float* points, int64_t P, const float* spheres, int64_t S,
+                                 const shv_params* prm, float* vis, float* saved, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* Diffuse SH shading B = a (L . (V * H)) (Eq. 8), H the clamped cosine
+ * rotated to n / |n| (Eqs. 10-11).
+ *   vis [N][P], normals [3][P] (need not be unit), albedo [P], light [N]
+ *   radiance [P] out. */
+shv_status sh_shade(const float* vis, const float* normals, const float* albedo, const float* light,
+                    int64_t P, const shv_params* prm, float* radiance, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* Adjoint of sh_shade for the cotangent grad_radiance [P] (the gradients of
+ * Sec. 3.5's objective with respect to L and a, and through H to n):
+ *   grad_vis [N][P], grad_normals [3][P], grad_albedo [P], grad_light [N]
+ * (any may be NULL).  grad_light is summed over all receivers. */
+shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const float* normals,
+                             const float* albedo, const float* light, int64_t P,
+                             const shv_params* prm, float* grad_vis, float* grad_normals,
+                             float* grad_albedo, float* grad_light, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Adjoint of sh_visibility_forward for the cotangent grad_vis [N][P]:
+ *   vis, saved  the forward's outputs for the same inputs and parameters
+ *   grad_points [3][P], grad_spheres [S][4] (d/d(cx, cy, cz, r), summed over
+ *   receivers); either may be NULL.  Per-pair terms are recomputed, not
+ *   stored. */
+shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const float* points,
+                                  int64_t P, const float* spheres, int64_t S,
+                                  const shv_params* prm, const float* saved, float* grad_points,
+                                  float* grad_spheres, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* Per-kernel timing with HIP events recorded around every launch on the
+ * launch stream.  shv_profile_enable(1) starts a new collection (at most
+ * `capacity` launches are recorded; later ones are counted but not timed);
+ * shv_profile_enable(0) stops recording.  shv_profile_report() must be called
+ * after the stream has drained: it writes "name count total_ms\n" lines into
+ * buf (NUL-terminated, truncated to len) and returns the number of bytes
+ * needed. */
+shv_status shv_profile_enable(int enable, int32_t capacity);
+int64_t shv_profile_report(char* buf, int64_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHVIS_H */

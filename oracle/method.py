@@ -98,7 +98,7 @@ def sh_exponential(F: torch.Tensor, C: torch.Tensor, n_squarings: int):
     """V = exp*(F) by DC isolation, scaling, optimal linear approximation and
     truncated squaring.  Returns (V, c, [E_0, ..., E_k])."""
     N = F.shape[-1]
-    e0 = torch.zeros(N, dtype=DT)
+    e0 = torch.zeros(N, dtype=F.dtype)
     e0[0] = 1.0
     c = F[..., 0] / SQRT_4PI                       # constant value of the DC part
     G = torch.cat([torch.zeros_like(F[..., :1]), F[..., 1:]], dim=-1) * (2.0 ** -n_squarings)
@@ -118,7 +118,7 @@ def transfer(normals: torch.Tensor, n_bands: int) -> torch.Tensor:
     """H(x)_lm = A_l y_lm(n / |n|), A_l the clamped-cosine Funk-Hecke
     eigenvalues (Eqs. 10-11)  -> [P, n^2]."""
     nh = normals / torch.linalg.norm(normals, dim=-1, keepdim=True)
-    A = torch.tensor([sh.clamped_cosine_coeff(l) for l in range(n_bands)], dtype=DT)
+    A = torch.tensor([sh.clamped_cosine_coeff(l) for l in range(n_bands)], dtype=normals.dtype)
     return A[band_of_index(n_bands)] * sh.real_sh(nh, n_bands)
 
 
@@ -133,8 +133,10 @@ def shade(V, H, albedo, light, C):
 
 def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0,
             n_squarings: int = 4, keep=False):
-    """Whole forward path on one chunk of receivers (all FP64 tensors)."""
-    C = sh.gaunt_tensor(n_bands)
+    """Whole forward path on one chunk of receivers (FP64 tensors; FP32
+    tensors give the oracle's FP32 twin, used only to measure how much error
+    FP32 arithmetic alone introduces)."""
+    C = sh.gaunt_tensor(n_bands).to(points.dtype)
     F = log_visibility(points, spheres, n_bands, eps)
     V, c, Es = sh_exponential(F, C, n_squarings)
     H = transfer(normals, n_bands)
@@ -145,16 +147,14 @@ def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 
     return out
 
 
-def scene_tensors(scene):
+def scene_tensors(scene, dtype=DT):
     """FP32 scene arrays -> FP64 tensors (bit-identical inputs)."""
-    return dict(points=_t(scene["points"]), normals=_t(scene["normals"]),
-                albedo=_t(scene["albedo"]), spheres=_t(scene["spheres"]),
-                light=_t(scene["light"]))
+    return {k: torch.as_tensor(scene[k]).to(dtype) for k in ("points", "normals", "albedo", "spheres", "light")}
 
 
-def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None):
+def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None, dtype=DT):
     """Forward over a scene (optionally a subset of receivers), chunked."""
-    T = scene_tensors(scene)
+    T = scene_tensors(scene, dtype)
     n = int(scene["n_bands"])
     P = T["points"].shape[0]
     sel = torch.arange(P) if idx is None else torch.as_tensor(idx)
@@ -167,11 +167,11 @@ def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None):
             for k in outs:
                 outs[k].append(o[k])
     N = n * n
-    return {k: (torch.cat(v) if v else torch.zeros((0, N) if k != "B" else (0,), dtype=DT))
+    return {k: (torch.cat(v) if v else torch.zeros((0, N) if k != "B" else (0,), dtype=dtype))
             for k, v in outs.items()}
 
 
-def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=None):
+def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=None, dtype=DT):
     """Forward plus gradients of sum_p grad_B[p] * B[p].
 
     ``idx`` restricts the receivers to a subset (grad_B then has that
@@ -179,11 +179,11 @@ def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=N
     subset only.  Returns numpy-free FP64 tensors:
     B [P'], V [P', N], grad_points [P', 3], grad_normals [P', 3],
     grad_albedo [P'], grad_spheres [S, 4], grad_light [N]."""
-    T = scene_tensors(scene)
+    T = scene_tensors(scene, dtype)
     n = int(scene["n_bands"])
     P = T["points"].shape[0]
     sel = torch.arange(P) if idx is None else torch.as_tensor(idx)
-    gB = _t(grad_B)
+    gB = torch.as_tensor(grad_B).to(dtype)
     spheres = T["spheres"].clone().requires_grad_(True)
     light = T["light"].clone().requires_grad_(True)
     gs = torch.zeros_like(spheres)
@@ -196,14 +196,15 @@ def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=N
         a = T["albedo"][j].clone().requires_grad_(True)
         o = forward(p, nrm, a, spheres, light, n, eps, n_squarings)
         loss = (o["B"] * gB[s:s + chunk]).sum()
-        g = torch.autograd.grad(loss, [p, nrm, a, spheres, light], allow_unused=True)
+        ins = [p, nrm, a, spheres, light]
+        g = torch.autograd.grad(loss, ins, allow_unused=True)
+        g = [torch.zeros_like(x) if gx is None else gx for gx, x in zip(g, ins)]  # unused: zero
         res["B"].append(o["B"].detach())
         res["V"].append(o["V"].detach())
         res["grad_points"].append(g[0])
         res["grad_normals"].append(g[1])
         res["grad_albedo"].append(g[2])
-        if g[3] is not None:
-            gs += g[3]
+        gs += g[3]
         gl += g[4]
     out = {k: torch.cat(v) for k, v in res.items()}
     out["grad_spheres"] = gs

@@ -1,0 +1,149 @@
+"""ctypes binding of libshvis.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (see
+include/shvis.h for the contract).  Tensor arguments are passed as device
+pointers; a non-zero status raises ``RuntimeError`` with the library's error
+text.  There is no fallback: if the shared library is missing the import
+fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshvis.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_2104_00359_amd/build.py` (there is no non-HIP fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SHV_OK = 0
+SHV_ERR_INVALID_ARG = -1
+SHV_ERR_UNSUPPORTED = -2
+SHV_ERR_WORKSPACE = -3
+SHV_ERR_NOT_INITIALIZED = -4
+SHV_ERR_HIP = -5
+
+EXPORTED = [
+    "shv_init", "shv_status_string", "shv_last_error", "shv_saved_floats", "shv_workspace_bytes",
+    "sh_visibility_forward", "sh_shade", "sh_shade_backward", "sh_visibility_backward",
+    "shv_profile_enable", "shv_profile_report",
+]
+
+
+class shv_params(ctypes.Structure):
+    _fields_ = [("n_bands", ctypes.c_int32), ("n_squarings", ctypes.c_int32),
+                ("eps", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_PRM = ctypes.POINTER(shv_params)
+
+_sig = {
+    "shv_init": (ctypes.c_int32, [ctypes.c_int]),
+    "shv_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "shv_last_error": (ctypes.c_char_p, []),
+    "shv_saved_floats": (_I64, [_I64, _PRM]),
+    "shv_workspace_bytes": (_SZ, [_I64, _I64, _PRM]),
+    "sh_visibility_forward": (ctypes.c_int32, [_P, _I64, _P, _I64, _PRM, _P, _P, _P, _SZ, _P]),
+    "sh_shade": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _PRM, _P, _P, _SZ, _P]),
+    "sh_shade_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _PRM, _P, _P, _P, _P, _P, _SZ, _P]),
+    "sh_visibility_backward": (ctypes.c_int32, [_P, _P, _P, _I64, _P, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
+    "shv_profile_enable": (ctypes.c_int32, [ctypes.c_int, ctypes.c_int32]),
+    "shv_profile_report": (_I64, [ctypes.c_char_p, _I64]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def params(n_bands: int, eps: float = 3.0, n_squarings: int = 4, flags: int = 0) -> shv_params:
+    return shv_params(int(n_bands), int(n_squarings), float(eps), int(flags))
+
+
+def ptr(t) -> int | None:
+    """Device pointer of a tensor (None for None); ints pass through."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _check(status: int, what: str):
+    if status != SHV_OK:
+        msg = _lib.shv_last_error().decode()
+        name = _lib.shv_status_string(status).decode()
+        raise RuntimeError(f"{what}: {name} ({status}): {msg}")
+
+
+def shv_status_string(status: int) -> str:
+    return _lib.shv_status_string(int(status)).decode()
+
+
+def shv_last_error() -> str:
+    return _lib.shv_last_error().decode()
+
+
+def shv_init(device: int) -> None:
+    _check(_lib.shv_init(int(device)), "shv_init")
+
+
+def shv_saved_floats(P: int, prm: shv_params) -> int:
+    return int(_lib.shv_saved_floats(int(P), ctypes.byref(prm)))
+
+
+def shv_workspace_bytes(P: int, S: int, prm: shv_params) -> int:
+    return int(_lib.shv_workspace_bytes(int(P), int(S), ctypes.byref(prm)))
+
+
+def raw(name: str):
+    """The raw ctypes function (returns the status; used by error-path tests)."""
+    return getattr(_lib, name)
+
+
+def sh_visibility_forward(points, P, spheres, S, prm, vis, saved, ws, ws_bytes, stream):
+    _check(_lib.sh_visibility_forward(ptr(points), int(P), ptr(spheres), int(S), ctypes.byref(prm), ptr(vis),
+                                      ptr(saved), ptr(ws), int(ws_bytes), stream), "sh_visibility_forward")
+
+
+def sh_shade(vis, normals, albedo, light, P, prm, radiance, ws, ws_bytes, stream):
+    _check(_lib.sh_shade(ptr(vis), ptr(normals), ptr(albedo), ptr(light), int(P), ctypes.byref(prm),
+                         ptr(radiance), ptr(ws), int(ws_bytes), stream), "sh_shade")
+
+
+def sh_shade_backward(grad_radiance, vis, normals, albedo, light, P, prm, grad_vis, grad_normals, grad_albedo,
+                      grad_light, ws, ws_bytes, stream):
+    _check(_lib.sh_shade_backward(ptr(grad_radiance), ptr(vis), ptr(normals), ptr(albedo), ptr(light), int(P),
+                                  ctypes.byref(prm), ptr(grad_vis), ptr(grad_normals), ptr(grad_albedo),
+                                  ptr(grad_light), ptr(ws), int(ws_bytes), stream), "sh_shade_backward")
+
+
+def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, grad_points, grad_spheres, ws,
+                           ws_bytes, stream):
+    _check(_lib.sh_visibility_backward(ptr(grad_vis), ptr(vis), ptr(points), int(P), ptr(spheres), int(S),
+                                       ctypes.byref(prm), ptr(saved), ptr(grad_points), ptr(grad_spheres),
+                                       ptr(ws), int(ws_bytes), stream), "sh_visibility_backward")
+
+
+def shv_profile_enable(enable: bool, capacity: int = 4096) -> None:
+    _check(_lib.shv_profile_enable(1 if enable else 0, int(capacity)), "shv_profile_enable")
+
+
+def shv_profile_report() -> dict:
+    """{kernel name: (launches, total milliseconds)} after the stream drained."""
+    need = _lib.shv_profile_report(None, 0)
+    buf = ctypes.create_string_buffer(int(need))
+    _lib.shv_profile_report(buf, int(need))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -1,0 +1,402 @@
+// C ABI: validation, workspace carving, launch sequencing and per-launch timing.
+// Declarations and the contract of every entry point are in include/shvis.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "shvis.h"
+#include "shv_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+shv_status set_error(shv_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+std::mutex g_init_mu;
+bool g_init[64] = {false};
+
+shv_status check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(SHV_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  if (dev < 0 || dev >= 64 || !g_init[dev])
+    return set_error(SHV_ERR_NOT_INITIALIZED, "shv_init() has not been called for device %d", dev);
+  return SHV_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;      // event pool
+int64_t g_prof_used = 0;          // records filled
+std::map<std::string, int64_t> g_prof_untimed;
+
+struct ProfScope {
+  ProfRec* rec = nullptr;
+  hipStream_t st;
+  ProfScope(const char* name, hipStream_t s) : st(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (g_prof_used < (int64_t)g_prof.size()) {
+      rec = &g_prof[g_prof_used++];
+      rec->name = name;
+      hipEventRecord(rec->a, st);
+    } else {
+      g_prof_untimed[name] += 1;
+    }
+  }
+  ~ProfScope() {
+    if (rec) hipEventRecord(rec->b, st);
+  }
+};
+
+template <class F>
+shv_status launch(const char* name, hipStream_t st, F&& f) {
+  hipError_t e;
+  {
+    ProfScope ps(name, st);
+    e = f();
+  }
+  if (e != hipSuccess) return set_error(SHV_ERR_HIP, "%s launch failed: %s", name, hipGetErrorString(e));
+  return SHV_OK;
+}
+
+// ------------------------------------------------------------------ validation
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+shv_status check_params(const shv_params* prm) {
+  if (!prm) return set_error(SHV_ERR_INVALID_ARG, "params is NULL");
+  if (prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API)
+    return set_error(SHV_ERR_UNSUPPORTED, "n_bands=%d outside [1, %d]", prm->n_bands, SHV_MAX_BANDS_API);
+  if (prm->n_squarings < 0 || prm->n_squarings > SHV_MAX_SQUARINGS)
+    return set_error(SHV_ERR_UNSUPPORTED, "n_squarings=%d outside [0, %d]", prm->n_squarings, SHV_MAX_SQUARINGS);
+  if (!(prm->eps == prm->eps) || prm->eps < 0.0f)
+    return set_error(SHV_ERR_INVALID_ARG, "eps must be a non-negative number");
+  if (prm->flags != 0) return set_error(SHV_ERR_INVALID_ARG, "flags must be 0");
+  return SHV_OK;
+}
+
+shv_status check_sizes(int64_t P, int64_t S) {
+  if (P < 0 || S < 0) return set_error(SHV_ERR_INVALID_ARG, "negative size (P=%lld, S=%lld)", (long long)P, (long long)S);
+  if (P > ((int64_t)1 << 31) - 256 || S > ((int64_t)1 << 24))
+    return set_error(SHV_ERR_INVALID_ARG, "size too large (P=%lld, S=%lld)", (long long)P, (long long)S);
+  return SHV_OK;
+}
+
+shv_status need(const void* p, const char* what) {
+  if (!p) return set_error(SHV_ERR_INVALID_ARG, "%s is NULL", what);
+  return SHV_OK;
+}
+
+shv_status aligned16(const void* p, const char* what) {
+  if (((uintptr_t)p) & 15u) return set_error(SHV_ERR_INVALID_ARG, "%s must be 16-byte aligned", what);
+  return SHV_OK;
+}
+
+#define SHV_TRY(x)                 \
+  do {                             \
+    shv_status _s = (x);           \
+    if (_s != SHV_OK) return _s;   \
+  } while (0)
+
+// Workspace carving, one region per phase; phases run in stream order, so
+// they reuse the same bytes.
+struct FwdWs {
+  size_t fpart;
+};
+struct ShadeWs {
+  size_t M, lpart;
+};
+struct VisBwdWs {
+  size_t W, gp, gs;
+};
+
+size_t fwd_bytes(int64_t P, int64_t S, int nb, FwdWs* o = nullptr) {
+  const shv::Split sp = shv::choose_split(P, S);
+  const size_t fpart = align_up((size_t)sp.nchunks * nb * nb * (size_t)P * 4);
+  if (o) o->fpart = 0;
+  return fpart;
+}
+size_t shade_bytes(int64_t P, int nb, ShadeWs* o = nullptr) {
+  const size_t N = (size_t)nb * nb;
+  const size_t m = align_up(N * N * 4);
+  const size_t lp = align_up((size_t)shv::shade_blocks(P) * N * 4);
+  if (o) {
+    o->M = 0;
+    o->lpart = m;
+  }
+  return m + lp;
+}
+size_t visbwd_bytes(int64_t P, int64_t S, int nb, VisBwdWs* o = nullptr) {
+  const shv::Split sp = shv::choose_split(P, S);
+  const size_t N = (size_t)nb * nb;
+  const size_t w = align_up(N * (size_t)P * 4);
+  const size_t gp = align_up((size_t)sp.nchunks * 3 * (size_t)P * 4);
+  const size_t gs = align_up((size_t)shv::point_blocks(P) * (size_t)S * 16);
+  if (o) {
+    o->W = 0;
+    o->gp = w;
+    o->gs = w + gp;
+  }
+  return w + gp + gs;
+}
+
+shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
+  if (needed == 0) return SHV_OK;
+  if (!ws) return set_error(SHV_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", needed);
+  if (((uintptr_t)ws) % kAlign) return set_error(SHV_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (ws_bytes < needed) return set_error(SHV_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, needed);
+  return SHV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shv_status shv_init(int device) {
+  if (device < 0 || device >= 64) return set_error(SHV_ERR_INVALID_ARG, "device %d out of range", device);
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return set_error(SHV_ERR_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return set_error(SHV_ERR_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(SHV_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  g_init[device] = true;
+  return SHV_OK;
+}
+
+const char* shv_status_string(shv_status s) {
+  switch (s) {
+    case SHV_OK: return "ok";
+    case SHV_ERR_INVALID_ARG: return "invalid argument";
+    case SHV_ERR_UNSUPPORTED: return "unsupported parameters";
+    case SHV_ERR_WORKSPACE: return "workspace too small";
+    case SHV_ERR_NOT_INITIALIZED: return "library not initialised for this device";
+    case SHV_ERR_HIP: return "HIP error";
+    default: return "unknown status";
+  }
+}
+
+const char* shv_last_error(void) { return g_last_error.c_str(); }
+
+int64_t shv_saved_floats(int64_t P, const shv_params* prm) {
+  if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || prm->n_squarings < 0 || P < 0) return 0;
+  return (1 + (int64_t)prm->n_squarings * prm->n_bands * prm->n_bands) * P;
+}
+
+size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm) {
+  if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || P < 0 || S < 0) return 0;
+  const int nb = prm->n_bands;
+  size_t b = fwd_bytes(P, S, nb);
+  b = std::max(b, shade_bytes(P, nb));
+  b = std::max(b, visbwd_bytes(P, S, nb));
+  return b;
+}
+
+shv_status sh_visibility_forward(const float* points, int64_t P, const float* spheres, int64_t S,
+                                 const shv_params* prm, float* vis, float* saved, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, S));
+  SHV_TRY(check_device());
+  if (P == 0) return SHV_OK;
+  SHV_TRY(need(points, "points"));
+  SHV_TRY(need(vis, "vis"));
+  if (S > 0) {
+    SHV_TRY(need(spheres, "spheres"));
+    SHV_TRY(aligned16(spheres, "spheres"));
+  }
+  const int nb = prm->n_bands;
+  const size_t needed = fwd_bytes(P, S, nb);
+  SHV_TRY(check_ws(ws, ws_bytes, needed));
+  float* Fpart = (float*)ws;
+  const shv::Split sp = shv::choose_split(P, S);
+  SHV_TRY(launch("pair_fwd", stream, [&] {
+    return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, stream);
+  }));
+  SHV_TRY(launch("exp_fwd", stream, [&] {
+    return shv::launch_exp_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, vis, saved, stream);
+  }));
+  return SHV_OK;
+}
+
+shv_status sh_shade(const float* vis, const float* normals, const float* albedo, const float* light, int64_t P,
+                    const shv_params* prm, float* radiance, void* ws, size_t ws_bytes, hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, 0));
+  SHV_TRY(check_device());
+  if (P == 0) return SHV_OK;
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(light, "light"));
+  SHV_TRY(need(radiance, "radiance"));
+  const int nb = prm->n_bands;
+  ShadeWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, shade_bytes(P, nb, &L)));
+  float* M = (float*)((char*)ws + L.M);
+  SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream); }));
+  SHV_TRY(launch("shade_fwd", stream, [&] {
+    return shv::launch_shade_fwd(nb, vis, normals, albedo, M, P, radiance, stream);
+  }));
+  return SHV_OK;
+}
+
+shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const float* normals, const float* albedo,
+                             const float* light, int64_t P, const shv_params* prm, float* grad_vis,
+                             float* grad_normals, float* grad_albedo, float* grad_light, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, 0));
+  SHV_TRY(check_device());
+  const int nb = prm->n_bands;
+  const int N = nb * nb;
+  if (P == 0) {
+    if (grad_light)
+      SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_light, N, stream); }));
+    return SHV_OK;
+  }
+  SHV_TRY(need(grad_radiance, "grad_radiance"));
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(light, "light"));
+  ShadeWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, shade_bytes(P, nb, &L)));
+  float* M = (float*)((char*)ws + L.M);
+  float* Lpart = grad_light ? (float*)((char*)ws + L.lpart) : nullptr;
+  SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream); }));
+  SHV_TRY(launch("shade_bwd", stream, [&] {
+    return shv::launch_shade_bwd(nb, grad_radiance, vis, normals, albedo, M, P, grad_vis, grad_normals, grad_albedo,
+                                 Lpart, stream);
+  }));
+  if (grad_light) {
+    SHV_TRY(launch("reduce_light", stream, [&] {
+      return shv::launch_reduce_rows(Lpart, shv::shade_blocks(P), N, grad_light, stream);
+    }));
+  }
+  return SHV_OK;
+}
+
+shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const float* points, int64_t P,
+                                  const float* spheres, int64_t S, const shv_params* prm, const float* saved,
+                                  float* grad_points, float* grad_spheres, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, S));
+  SHV_TRY(check_device());
+  if (P == 0 || (!grad_points && !grad_spheres)) {
+    if (grad_spheres && S > 0)
+      SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_spheres, 4 * S, stream); }));
+    return SHV_OK;
+  }
+  SHV_TRY(need(grad_vis, "grad_vis"));
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(points, "points"));
+  SHV_TRY(need(saved, "saved"));
+  if (S > 0) {
+    SHV_TRY(need(spheres, "spheres"));
+    SHV_TRY(aligned16(spheres, "spheres"));
+  }
+  const int nb = prm->n_bands;
+  VisBwdWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, visbwd_bytes(P, S, nb, &L)));
+  float* W = (float*)((char*)ws + L.W);
+  float* gp = (float*)((char*)ws + L.gp);
+  float* gs = (float*)((char*)ws + L.gs);
+  const shv::Split sp = shv::choose_split(P, S);
+  SHV_TRY(launch("exp_bwd", stream, [&] {
+    return shv::launch_exp_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, W, stream);
+  }));
+  SHV_TRY(launch("pair_bwd", stream, [&] {
+    return shv::launch_pair_bwd(nb, W, points, P, spheres, (int)S, sp, gp, gs, stream);
+  }));
+  if (grad_points) {
+    SHV_TRY(launch("sum_point_chunks", stream, [&] {
+      return shv::launch_sum_chunks(gp, sp.nchunks, 3 * P, grad_points, stream);
+    }));
+  }
+  if (grad_spheres && S > 0) {
+    SHV_TRY(launch("reduce_spheres", stream, [&] {
+      return shv::launch_reduce_rows(gs, (int)shv::point_blocks(P), (int)(4 * S), grad_spheres, stream);
+    }));
+  }
+  return SHV_OK;
+}
+
+shv_status shv_profile_enable(int enable, int32_t capacity) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!enable) {
+    g_prof_on = false;
+    return SHV_OK;
+  }
+  if (capacity < 0) return set_error(SHV_ERR_INVALID_ARG, "negative capacity");
+  while ((int64_t)g_prof.size() < capacity) {
+    ProfRec r{nullptr, nullptr, nullptr};
+    hipError_t e1 = hipEventCreate(&r.a);
+    hipError_t e2 = hipEventCreate(&r.b);
+    if (e1 != hipSuccess || e2 != hipSuccess) return set_error(SHV_ERR_HIP, "hipEventCreate failed");
+    g_prof.push_back(r);
+  }
+  g_prof_used = 0;
+  g_prof_untimed.clear();
+  g_prof_on = true;
+  return SHV_OK;
+}
+
+int64_t shv_profile_report(char* buf, int64_t len) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::map<std::string, std::pair<int64_t, double>> agg;
+  for (int64_t i = 0; i < g_prof_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, g_prof[i].a, g_prof[i].b) != hipSuccess) ms = -1.0f;
+    auto& a = agg[g_prof[i].name];
+    a.first += 1;
+    a.second += ms;
+  }
+  std::string out;
+  char line[256];
+  for (auto& kv : agg) {
+    snprintf(line, sizeof(line), "%s %lld %.6f\n", kv.first.c_str(), (long long)kv.second.first, kv.second.second);
+    out += line;
+  }
+  for (auto& kv : g_prof_untimed) {
+    snprintf(line, sizeof(line), "%s:untimed %lld 0\n", kv.first.c_str(), (long long)kv.second);
+    out += line;
+  }
+  if (buf && len > 0) {
+    const int64_t n = std::min<int64_t>(len - 1, (int64_t)out.size());
+    std::memcpy(buf, out.data(), (size_t)n);
+    buf[n] = '\0';
+  }
+  return (int64_t)out.size() + 1;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Device building blocks for the SH soft-shadow kernels (gfx950, wave64).
+//
+// Real SH in a polynomial form: for a unit vector (x, y, z),
+//   y_lm = LAMBDA[l][|m|] * r_l^|m|(z) * T_m(x, y),
+//   T_m = Re (x + i y)^m for m >= 0, Im (x + i y)^|m| for m < 0,
+//   r_m^m = 1, r_{m+1}^m = z, r_l^m = z r_{l-1}^m + GAMMA[l][m] r_{l-2}^m,
+//   d r_l^m / dz = RHO[l][m] r_l^{m+1}.
+// r_l^m is d^m P_l / dz^m up to a constant, so no square roots or
+// trigonometric functions are needed and every derivative stays polynomial.
+//
+// Coefficient index i = l*l + l + m (Sec. 3.2 of the paper).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "generated/shv_constants.h"
+#include "generated/shv_gaunt.h"
+
+#define SHV_BLOCK 256
+#define SHV_WAVES_PER_BLOCK (SHV_BLOCK / 64)
+#define SHV_MAX_CHUNK 512
+
+namespace shv {
+
+__device__ __forceinline__ constexpr int idx(int l, int m) { return l * l + l + m; }
+
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Re / Im of (x + i y)^m, m < NB.
+template <int NB>
+__device__ __forceinline__ void cs_powers(float x, float y, float (&C)[NB], float (&S)[NB]) {
+  C[0] = 1.0f;
+  S[0] = 0.0f;
+  if constexpr (NB > 1) {
+    C[1] = x;
+    S[1] = y;
+  }
+#pragma unroll
+  for (int m = 1; m + 1 < NB; ++m) {
+    C[m + 1] = fmaf(x, C[m], -y * S[m]);
+    S[m + 1] = fmaf(x, S[m], y * C[m]);
+  }
+}
+
+// Legendre P_0 .. P_NB at t by Bonnet's recurrence.
+template <int NB>
+__device__ __forceinline__ void legendre(float t, float (&Pl)[NB + 1]) {
+  Pl[0] = 1.0f;
+  Pl[1] = t;
+#pragma unroll
+  for (int l = 1; l < NB; ++l) Pl[l + 1] = fmaf(SHV_BONNET_A[l] * t, Pl[l], -SHV_BONNET_B[l] * Pl[l - 1]);
+}
+
+// eps-free log-cap zonal coefficients g_l(t) = -2 pi/(2l+1) (P_{l-1} - P_{l+1}),
+// P_{-1} = 1: the projection of "-1 on the cap {w . s >= t}" rotated to s,
+// divided by y_lm(s).  d g_l / dt = 2 pi P_l(t).
+template <int NB>
+__device__ __forceinline__ void cap_zonal(const float (&Pl)[NB + 1], float (&g)[NB]) {
+#pragma unroll
+  for (int l = 0; l < NB; ++l) g[l] = SHV_CAPK[l] * ((l == 0 ? 1.0f : Pl[l - 1]) - Pl[l + 1]);
+}
+
+// y_i(x, y, z) for all i < NB^2 (unit vector).
+template <int NB>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float (&Y)[NB * NB]) {
+  float C[NB], S[NB];
+  cs_powers<NB>(x, y, C, S);
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    float r2 = 0.0f, r1 = 1.0f;
+#pragma unroll
+    for (int l = m; l < NB; ++l) {
+      float r;
+      if (l == m) r = 1.0f;
+      else if (l == m + 1) r = z;
+      else r = fmaf(z, r1, SHV_GAMMA[l][m] * r2);
+      if (l > m) { r2 = r1; r1 = r; }
+      const float q = SHV_LAMBDA[l][m] * r;
+      if (m == 0) {
+        Y[idx(l, 0)] = q;
+      } else {
+        Y[idx(l, m)] = q * C[m];
+        Y[idx(l, -m)] = q * S[m];
+      }
+    }
+  }
+}
+
+// Gradient of the polynomial extension of sum_i c_i y_i at (x, y, z).
+// The tangential part of the result is the surface gradient on the sphere.
+template <int NB>
+__device__ __forceinline__ void sh_grad(float x, float y, float z, const float (&c)[NB * NB], float& gx,
+                                        float& gy, float& gz) {
+  float C[NB], S[NB];
+  cs_powers<NB>(x, y, C, S);
+  gx = 0.0f;
+  gy = 0.0f;
+  gz = 0.0f;
+  // Pass m evaluates r_l^m; it closes the x/y sums of order m and the z sums
+  // of order m - 1 (because d r_l^{m-1}/dz = RHO[l][m-1] r_l^m).
+#pragma unroll
+  for (int m = 1; m < NB; ++m) {
+    float Xc = 0.0f, Xs = 0.0f, Zc = 0.0f, Zs = 0.0f;
+    float r2 = 0.0f, r1 = 1.0f;
+#pragma unroll
+    for (int l = m; l < NB; ++l) {
+      float r;
+      if (l == m) r = 1.0f;
+      else if (l == m + 1) r = z;
+      else r = fmaf(z, r1, SHV_GAMMA[l][m] * r2);
+      if (l > m) { r2 = r1; r1 = r; }
+      Xc = fmaf(c[idx(l, m)] * SHV_LAMBDA[l][m], r, Xc);
+      Xs = fmaf(c[idx(l, -m)] * SHV_LAMBDA[l][m], r, Xs);
+      const float kz = SHV_LAMBDA[l][m - 1] * SHV_RHO[l][m - 1];
+      Zc = fmaf(c[idx(l, m - 1)] * kz, r, Zc);
+      if (m - 1 >= 1) Zs = fmaf(c[idx(l, -(m - 1))] * kz, r, Zs);
+    }
+    gz = fmaf(Zc, C[m - 1], fmaf(Zs, S[m - 1], gz));
+    const float fm = (float)m;
+    gx = fmaf(fm, fmaf(Xc, C[m - 1], Xs * S[m - 1]), gx);
+    gy = fmaf(fm, fmaf(Xs, C[m - 1], -Xc * S[m - 1]), gy);
+  }
+}
+
+// Sum over the 64 lanes of a wave; every lane receives the total.  Fixed
+// butterfly order, so the result is deterministic.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+}  // namespace shv

@@ -1,0 +1,122 @@
+"""PyTorch-facing operations over the HIP library.
+
+``shade_sh`` renders per-receiver radiance with soft shadows from sphere
+occluders (Eq. 8 with the visibility of Sec. 3.3.2) and is differentiable with
+respect to receiver positions and normals, albedo, sphere centres and radii,
+and the lighting SH vector, through hand-written adjoint kernels.  PyTorch
+only supplies device memory and the current HIP stream; every step of the
+computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import threading
+
+import torch
+
+from . import _lib
+
+_ws_lock = threading.Lock()
+_ws_cache: dict = {}
+_initialised: set = set()
+
+
+def ensure_init(device: torch.device) -> None:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if idx not in _initialised:
+        _lib.shv_init(idx)
+        _initialised.add(idx)
+
+
+def workspace(device: torch.device, nbytes: int) -> torch.Tensor:
+    """A per-device, grow-only scratch buffer (reused across calls on the
+    same stream order)."""
+    key = (device.type, device.index)
+    with _ws_lock:
+        buf = _ws_cache.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            _ws_cache[key] = buf
+        return buf
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _soa(x: torch.Tensor) -> torch.Tensor:
+    """[P, 3] -> [3, P] FP32 contiguous (layout marshalling)."""
+    return x.detach().to(torch.float32).t().contiguous()
+
+
+def _f32(x: torch.Tensor) -> torch.Tensor:
+    return x.detach().to(torch.float32).contiguous()
+
+
+class ShadeSH(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings):
+        dev = points.device
+        if dev.type != "cuda":
+            raise RuntimeError("shade_sh runs on the GPU only; move the inputs to a HIP device")
+        ensure_init(dev)
+        prm = _lib.params(n_bands, eps, n_squarings)
+        P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
+        pts, nrm = _soa(points), _soa(normals)
+        alb, sph, L = _f32(albedo), _f32(spheres), _f32(light)
+        if L.numel() != N:
+            raise ValueError(f"light has {L.numel()} coefficients, expected {N} for {n_bands} bands")
+        vis = torch.empty(N, P, dtype=torch.float32, device=dev)
+        saved = torch.empty(_lib.shv_saved_floats(P, prm), dtype=torch.float32, device=dev)
+        rad = torch.empty(P, dtype=torch.float32, device=dev)
+        nbytes = _lib.shv_workspace_bytes(P, S, prm)
+        ws = workspace(dev, nbytes)
+        st = _stream()
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), st)
+        _lib.sh_shade(vis, nrm, alb, L, P, prm, rad, ws, ws.numel(), st)
+        ctx.save_for_backward(pts, nrm, alb, sph, L, vis, saved)
+        ctx.cfg = (n_bands, eps, n_squarings)
+        return rad
+
+    @staticmethod
+    def backward(ctx, grad_rad):
+        pts, nrm, alb, sph, L, vis, saved = ctx.saved_tensors
+        n_bands, eps, n_squarings = ctx.cfg
+        prm = _lib.params(n_bands, eps, n_squarings)
+        dev = pts.device
+        P, S, N = pts.shape[1], sph.shape[0], n_bands * n_bands
+        gB = _f32(grad_rad)
+        need_p, need_n, need_a, need_s, need_l = ctx.needs_input_grad[:5]
+        gV = torch.empty(N, P, dtype=torch.float32, device=dev)
+        gN = torch.empty(3, P, dtype=torch.float32, device=dev) if need_n else None
+        gA = torch.empty(P, dtype=torch.float32, device=dev) if need_a else None
+        gL = torch.empty(N, dtype=torch.float32, device=dev) if need_l else None
+        gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
+        gS = torch.empty(S, 4, dtype=torch.float32, device=dev) if need_s else None
+        nbytes = _lib.shv_workspace_bytes(P, S, prm)
+        ws = workspace(dev, nbytes)
+        st = _stream()
+        _lib.sh_shade_backward(gB, vis, nrm, alb, L, P, prm, gV, gN, gA, gL, ws, ws.numel(), st)
+        if need_p or need_s:
+            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), st)
+        return (gP.t() if gP is not None else None, gN.t() if gN is not None else None, gA, gS, gL,
+                None, None, None)
+
+
+def shade_sh(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0, n_squarings: int = 4):
+    """Radiance [P] at receivers ``points`` [P, 3] with ``normals`` [P, 3] and
+    ``albedo`` [P], occluded by ``spheres`` [S, 4] = (cx, cy, cz, r), lit by the
+    SH vector ``light`` [n_bands^2] (index l*l + l + m, real orthonormal basis
+    without Condon-Shortley phase)."""
+    return ShadeSH.apply(points, normals, albedo, spheres, light, n_bands, eps, n_squarings)
+
+
+def visibility_sh(points, spheres, n_bands: int, eps: float = 3.0, n_squarings: int = 4):
+    """Visibility SH vectors [P, n_bands^2] (forward only)."""
+    dev = points.device
+    ensure_init(dev)
+    prm = _lib.params(n_bands, eps, n_squarings)
+    P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
+    vis = torch.empty(N, P, dtype=torch.float32, device=dev)
+    ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
+    _lib.sh_visibility_forward(_soa(points), P, _f32(spheres), S, prm, vis, None, ws, ws.numel(), _stream())
+    return vis.t()

@@ -1,0 +1,124 @@
+"""Algorithmic work per unit for each kernel (used for roofline figures).
+
+Counting rule: one floating-point add, multiply, square root, reciprocal
+square root or exponential = 1 flop; a fused multiply-add = 2 flops.  The
+counts are those of the minimal operation graph of the formulation the
+kernels implement (polynomial SH basis, sparse triple products); lane-level
+overheads (index arithmetic, cross-lane reductions, tail lanes) are not
+counted.  Units: one (receiver, sphere) pair for the pair kernels, one
+receiver for the per-receiver kernels.
+"""
+from __future__ import annotations
+
+import functools
+import os
+import sys
+
+
+def _tri(n):
+    return n * (n - 1) // 2
+
+
+def pair_fwd_flops(n: int) -> int:
+    geom = 16                                   # c - x, |v|^2, rsqrt, s, r/d, 1 - s^2, sqrt
+    leg = 4 * max(n - 1, 0)                     # Bonnet steps P_2 .. P_n
+    cap = 2 * n                                 # g_l = K_l (P_{l-1} - P_{l+1})
+    cs = 6 * max(n - 2, 0)                      # Re/Im (x + i y)^m, m = 2 .. n-1
+    rec = 3 * max(n - 2, 0) * max(n - 1, 0) // 2  # r_l^m three-term steps
+    u = _tri(n)                                 # g_l r_l^m for l > m
+    acc = n + 4 * _tri(n)                       # m = 0 adds, m > 0 two FMAs each
+    return geom + leg + cap + cs + rec + u + acc
+
+
+def pair_bwd_flops(n: int) -> int:
+    base = 16 + 4 * max(n - 1, 0) + 2 * n + 6 * max(n - 2, 0) + 3 * max(n - 2, 0) * max(n - 1, 0) // 2
+    vw = 2 * _tri(n)                            # g_l r and P_l r for l > m
+    m0 = 2 * n                                  # t-derivative sum of the m = 0 column
+    lm = 10 * _tri(n) + 2 * _tri(max(n - 1, 0))  # X, T (4 FMAs) and Z sums per (l, m >= 1)
+    comb = 4 + 18 * max(n - 1, 0)               # per-order combination into Gx, Gy, Gz, Gt
+    chain = 26 + 3 + 4                          # tangent projection, t chain, receiver / sphere sums
+    return base + vw + m0 + lm + comb + chain
+
+
+@functools.lru_cache(maxsize=None)
+def _gaunt_counts(n: int):
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    if here not in sys.path:
+        sys.path.insert(0, here)
+    import gen_tables  # the library's own table generator
+    C = gen_tables.real_gaunt(n)
+    sym = [(i, j, k) for (i, j, k) in C if j <= k]
+    pairs = {(j, k) for (_, j, k) in sym}
+    upairs = {(i, k) for (_, i, k) in C if i <= k}
+    supp = set(gen_tables.transfer_support(n))
+    vh = [(i, j, k) for (i, j, k) in C if k in supp]
+    vh_pairs = {(j, k) for (_, j, k) in vh}
+    return dict(nnz=len(C), sym=len(sym), pairs=len(pairs), upairs=len(upairs),
+                diag=sum(1 for (i, k) in upairs if i == k), vh=len(vh), vh_pairs=len(vh_pairs),
+                supp=len(supp))
+
+
+def square_flops(n: int) -> int:
+    c = _gaunt_counts(n)
+    return c["pairs"] + 2 * c["sym"]
+
+
+def square_adj_flops(n: int) -> int:
+    c = _gaunt_counts(n)
+    off = c["upairs"] - c["diag"]
+    return c["diag"] + 3 * off + 2 * c["sym"]
+
+
+def exp_fwd_flops(n: int, k: int) -> int:
+    N = n * n
+    prologue = 3 * N + 2 * N + 4                # scale, |G|^2, exp, a * G
+    return prologue + k * square_flops(n) + N + 1
+
+
+def exp_bwd_flops(n: int, k: int) -> int:
+    N = n * n
+    return 3 * N + 2 + k * square_adj_flops(n) + 2 * N + 5 * N
+
+
+def shade_fwd_flops(n: int) -> int:
+    c = _gaunt_counts(n)
+    N = n * n
+    return 12 + 3 * N + c["supp"] * (2 * N + 2) + 1
+
+
+def shade_bwd_flops(n: int) -> int:
+    c = _gaunt_counts(n)
+    N = n * n
+    h = 12 + 3 * N
+    mv = c["supp"] * (2 * N + 3)
+    vbar = N * (2 * c["supp"] + 1)
+    nbar = 10 * N + 15
+    lbar = N + c["vh_pairs"] + 2 * c["vh"]
+    return h + mv + vbar + nbar + lbar
+
+
+# Bytes each kernel must move to / from HBM per unit (FP32).
+def exp_fwd_bytes(n: int, k: int, nchunks: int) -> int:
+    N = n * n
+    return 4 * (nchunks * N + N + 1 + k * N)
+
+
+def pair_fwd_bytes_per_receiver(n: int, nchunks: int) -> int:
+    return 4 * (3 * nchunks + n * n * nchunks)
+
+
+def kernel_work(name: str, n: int, k: int, P: int, S: int):
+    """(flops, unit count) of one launch of kernel ``name``."""
+    if name == "pair_fwd":
+        return pair_fwd_flops(n) * P * S, P * S
+    if name == "pair_bwd":
+        return pair_bwd_flops(n) * P * S, P * S
+    if name == "exp_fwd":
+        return exp_fwd_flops(n, k) * P, P
+    if name == "exp_bwd":
+        return exp_bwd_flops(n, k) * P, P
+    if name == "shade_fwd":
+        return shade_fwd_flops(n) * P, P
+    if name == "shade_bwd":
+        return shade_bwd_flops(n) * P, P
+    return None, None

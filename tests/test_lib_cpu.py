@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI library that need no GPU: it loads, exports
+every entry point its header declares, sizes its buffers consistently and
+rejects invalid parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shvis.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2104_00359_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sh[v]?_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("sh_visibility_forward", "sh_visibility_backward", "sh_shade", "sh_shade_backward", "shv_init"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(L.EXPORTED)
+
+
+def test_status_strings(L):
+    assert L.shv_status_string(0) == "ok"
+    assert "workspace" in L.shv_status_string(-3)
+    assert L.shv_status_string(12345) == "unknown status"
+
+
+def test_saved_and_workspace_sizes(L):
+    for n, k in ((4, 4), (8, 4), (8, 0), (6, 7)):
+        prm = L.params(n, 3.0, k)
+        assert L.shv_saved_floats(1000, prm) == (1 + k * n * n) * 1000
+    prm = L.params(8)
+    a = L.shv_workspace_bytes(20000, 128, prm)
+    b = L.shv_workspace_bytes(20000, 256, prm)
+    c = L.shv_workspace_bytes(40000, 128, prm)
+    assert 0 < a <= b and a <= c and a % 256 == 0
+    # V-sized scratch at least (the adjoint's weights live there)
+    assert a >= 64 * 20000 * 4
+    assert L.shv_workspace_bytes(10, 10, L.params(9)) == 0
+    assert L.shv_workspace_bytes(0, 0, prm) >= 0
+
+
+def test_invalid_parameters_rejected_before_any_device_call(L):
+    f = L.raw("sh_visibility_forward")
+    st = None
+    bad_bands = L.params(9)
+    assert f(None, 10, None, 0, ctypes.byref(bad_bands), None, None, None, 0, st) == L.SHV_ERR_UNSUPPORTED
+    assert "n_bands" in L.shv_last_error()
+    bad_k = L.params(4, 3.0, 13)
+    assert f(None, 10, None, 0, ctypes.byref(bad_k), None, None, None, 0, st) == L.SHV_ERR_UNSUPPORTED
+    neg = L.params(4)
+    assert f(None, -5, None, 0, ctypes.byref(neg), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    bad_eps = L.params(4, -1.0)
+    assert f(None, 10, None, 0, ctypes.byref(bad_eps), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    flags = L.shv_params(4, 4, 3.0, 1)
+    assert f(None, 10, None, 0, ctypes.byref(flags), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    g = L.raw("sh_shade")
+    assert g(None, None, None, None, 5, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
