@@ -63,13 +63,13 @@ struct ProfScope {
     if (g_prof_used < (int64_t)g_prof.size()) {
       rec = &g_prof[g_prof_used++];
       rec->name = name;
-      hipEventRecord(rec->a, st);
+      (void)hipEventRecord(rec->a, st);
     } else {
       g_prof_untimed[name] += 1;
     }
   }
   ~ProfScope() {
-    if (rec) hipEventRecord(rec->b, st);
+    if (rec) (void)hipEventRecord(rec->b, st);
   }
 };
 

@@ -27,6 +27,7 @@ __device__ __forceinline__ constexpr int idx(int l, int m) { return l * l + l + 
 
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Re / Im of (x + i y)^m, m < NB.
 template <int NB>
@@ -44,22 +45,28 @@ __device__ __forceinline__ void cs_powers(float x, float y, float (&C)[NB], floa
   }
 }
 
-// Legendre P_0 .. P_NB at t by Bonnet's recurrence.
+// Residual Legendre values R_l = 1 - P_l(t), l = 0 .. NB, from u = 1 - t.
+// Bonnet's recurrence rewritten for R: R_0 = 0, R_1 = u,
+//   R_{l+1} = (2l+1)/(l+1) (u + t R_l) - l/(l+1) R_{l-1}.
+// For small caps (t near 1) every g_l is a difference of Legendre values
+// that all tend to 1; recurring on R keeps the leading digits.
 template <int NB>
-__device__ __forceinline__ void legendre(float t, float (&Pl)[NB + 1]) {
-  Pl[0] = 1.0f;
-  Pl[1] = t;
+__device__ __forceinline__ void legendre_resid(float t, float u, float (&R)[NB + 1]) {
+  R[0] = 0.0f;
+  R[1] = u;
 #pragma unroll
-  for (int l = 1; l < NB; ++l) Pl[l + 1] = fmaf(SHV_BONNET_A[l] * t, Pl[l], -SHV_BONNET_B[l] * Pl[l - 1]);
+  for (int l = 1; l < NB; ++l) R[l + 1] = fmaf(SHV_BONNET_A[l], fmaf(t, R[l], u), -SHV_BONNET_B[l] * R[l - 1]);
 }
 
-// eps-free log-cap zonal coefficients g_l(t) = -2 pi/(2l+1) (P_{l-1} - P_{l+1}),
-// P_{-1} = 1: the projection of "-1 on the cap {w . s >= t}" rotated to s,
-// divided by y_lm(s).  d g_l / dt = 2 pi P_l(t).
+// eps-free log-cap zonal coefficients g_l(t) = -2 pi/(2l+1) (P_{l-1} - P_{l+1})
+// with P_{-1} = 1, i.e. g_0 = -2 pi u and g_l = -2 pi/(2l+1) (R_{l+1} - R_{l-1}):
+// the projection of "-1 on the cap {w . s >= t}" rotated to s, divided by
+// y_lm(s).  d g_l / dt = 2 pi P_l(t) = 2 pi (1 - R_l).
 template <int NB>
-__device__ __forceinline__ void cap_zonal(const float (&Pl)[NB + 1], float (&g)[NB]) {
+__device__ __forceinline__ void cap_zonal(float u, const float (&R)[NB + 1], float (&g)[NB]) {
+  g[0] = SHV_CAPK[0] * u;
 #pragma unroll
-  for (int l = 0; l < NB; ++l) g[l] = SHV_CAPK[l] * ((l == 0 ? 1.0f : Pl[l - 1]) - Pl[l + 1]);
+  for (int l = 1; l < NB; ++l) g[l] = SHV_CAPK[l] * (R[l + 1] - R[l - 1]);
 }
 
 // y_i(x, y, z) for all i < NB^2 (unit vector).

@@ -32,6 +32,7 @@ struct PairGeom {
   float inv;      // 1 / |c - x| (0 for a sphere centred on the receiver)
   float rs;       // r / |c - x|
   float t;        // cos(alpha), 0 when the receiver is inside the sphere
+  float u;        // 1 - t, formed as s^2 / (1 + t) so small caps keep their digits
 };
 
 __device__ __forceinline__ PairGeom pair_geom(float px, float py, float pz, float4 q) {
@@ -44,6 +45,7 @@ __device__ __forceinline__ PairGeom pair_geom(float px, float py, float pz, floa
   g.z = vz * g.inv;
   g.rs = q.w * g.inv;
   g.t = fast_sqrt(fmaxf(fmaf(-g.rs, g.rs, 1.0f), 0.0f));
+  g.u = fminf(g.rs * g.rs * fast_rcp(1.0f + g.t), 1.0f);  // = 1 when inside (t = 0)
   return g;
 }
 
@@ -63,12 +65,15 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_pair_fwd(const float* __restrict_
   float acc[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0.0f;
+  // The DC coefficient sets V's overall scale through exp(F_0 / sqrt(4 pi)),
+  // so its sum over spheres is compensated (Kahan).
+  float dc_comp = 0.0f;
 
   for (int s = s0; s < s1; ++s) {
     const PairGeom G = pair_geom(px, py, pz, sph[s]);
-    float Pl[NB + 1], g[NB], C[NB], Sn[NB];
-    legendre<NB>(G.t, Pl);
-    cap_zonal<NB>(Pl, g);
+    float R[NB + 1], g[NB], C[NB], Sn[NB];
+    legendre_resid<NB>(G.t, G.u, R);
+    cap_zonal<NB>(G.u, R, g);
     cs_powers<NB>(G.x, G.y, C, Sn);
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -84,7 +89,12 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_pair_fwd(const float* __restrict_
           r1 = r;
           u = g[l] * r;
         }
-        if (m == 0) {
+        if (m == 0 && l == 0) {
+          const float y = u - dc_comp;
+          const float t = acc[0] + y;
+          dc_comp = (t - acc[0]) - y;
+          acc[0] = t;
+        } else if (m == 0) {
           acc[idx(l, 0)] += u;
         } else {
           acc[idx(l, m)] = fmaf(u, C[m], acc[idx(l, m)]);
@@ -132,9 +142,9 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_pair_bwd(const float* __restrict_
   float gpx = 0.0f, gpy = 0.0f, gpz = 0.0f;
   for (int s = s0; s < s1; ++s) {
     const PairGeom G = pair_geom(px, py, pz, sph[s]);
-    float Pl[NB + 1], g[NB], C[NB], Sn[NB];
-    legendre<NB>(G.t, Pl);
-    cap_zonal<NB>(Pl, g);
+    float R[NB + 1], g[NB], C[NB], Sn[NB];
+    legendre_resid<NB>(G.t, G.u, R);
+    cap_zonal<NB>(G.u, R, g);
     cs_powers<NB>(G.x, G.y, C, Sn);
     float Gx = 0.0f, Gy = 0.0f, Gz = 0.0f, Gt = 0.0f;
 #pragma unroll
@@ -149,7 +159,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_pair_bwd(const float* __restrict_
         else r = fmaf(G.z, r1, SHV_GAMMA[l][m] * r2);
         if (l > m) { r2 = r1; r1 = r; }
         const float v = g[l] * r;   // value weight of r_l^m
-        const float w = Pl[l] * r;  // t-derivative weight of r_l^m (times 1 / 2 pi)
+        const float w = fmaf(-R[l], r, r);  // P_l(t) r: t-derivative weight (times 1 / 2 pi)
         if (m == 0) {
           Tc = fmaf(W[idx(l, 0)], w, Tc);
         } else {

@@ -20,19 +20,19 @@ def _tri(n):
 
 
 def pair_fwd_flops(n: int) -> int:
-    geom = 16                                   # c - x, |v|^2, rsqrt, s, r/d, 1 - s^2, sqrt
-    leg = 4 * max(n - 1, 0)                     # Bonnet steps P_2 .. P_n
-    cap = 2 * n                                 # g_l = K_l (P_{l-1} - P_{l+1})
+    geom = 20                                   # c - x, |v|^2, rsqrt, s, r/d, 1 - s^2, sqrt, u = s^2/(1+t)
+    leg = 5 * max(n - 1, 0)                     # residual Bonnet steps R_2 .. R_n
+    cap = 2 * n - 1                             # g_0 = K_0 u, g_l = K_l (R_{l+1} - R_{l-1})
     cs = 6 * max(n - 2, 0)                      # Re/Im (x + i y)^m, m = 2 .. n-1
     rec = 3 * max(n - 2, 0) * max(n - 1, 0) // 2  # r_l^m three-term steps
     u = _tri(n)                                 # g_l r_l^m for l > m
-    acc = n + 4 * _tri(n)                       # m = 0 adds, m > 0 two FMAs each
+    acc = n + 3 + 4 * _tri(n)                   # m = 0 adds (compensated DC), m > 0 two FMAs each
     return geom + leg + cap + cs + rec + u + acc
 
 
 def pair_bwd_flops(n: int) -> int:
-    base = 16 + 4 * max(n - 1, 0) + 2 * n + 6 * max(n - 2, 0) + 3 * max(n - 2, 0) * max(n - 1, 0) // 2
-    vw = 2 * _tri(n)                            # g_l r and P_l r for l > m
+    base = 20 + 5 * max(n - 1, 0) + 2 * n - 1 + 6 * max(n - 2, 0) + 3 * max(n - 2, 0) * max(n - 1, 0) // 2
+    vw = 3 * _tri(n) + n                        # g_l r and (1 - R_l) r
     m0 = 2 * n                                  # t-derivative sum of the m = 0 column
     lm = 10 * _tri(n) + 2 * _tri(max(n - 1, 0))  # X, T (4 FMAs) and Z sums per (l, m >= 1)
     comb = 4 + 18 * max(n - 1, 0)               # per-order combination into Gx, Gy, Gz, Gt

@@ -99,45 +99,21 @@ def _gbuffer_cotangent(sc, idx):
     return w
 
 
-def test_gbuffer_scene_full_size_well_conditioned():
+def test_gbuffer_scene_full_size_sampled():
     """512 x 512 G-buffer receivers over 256 spheres, 8 bands, k = 4, at full
-    size.  Compared on sampled receivers (away from contact) whose visibility
-    stays in the regime of a function bounded by one (|V| <= 2 sqrt(4 pi)):
-    there the standard tolerances apply; the photometric-loss cotangent is
-    restricted to them so every gradient group is checked too."""
-    sc = scenegen.scene_gbuffer()
-    ok = np.flatnonzero(~sc["contact"])
-    cand = np.sort(np.random.default_rng(1).choice(ok, 2048, replace=False))
-    Vn = np.linalg.norm(run_oracle(sc, idx=cand)["V"], axis=1)
-    idx = cand[Vn <= 2.0 * np.sqrt(4 * np.pi)][:256]
-    assert len(idx) >= 32, len(idx)
-    w = _gbuffer_cotangent(sc, idx)
-    h = run_hip(sc, w)
-    o = run_oracle(sc, w[idx], idx=idx)
-    check_forward({"V": h["V"][idx], "B": h["B"][idx]}, o)
-    check_grads(h, o, tol_geom=1e-3, idx=idx)
-
-
-def test_gbuffer_scene_ill_conditioned_within_fp32_floor():
-    """Most G-buffer receivers sit under many overlapping caps (|F^| up to
-    ~70): with k = 4 the truncated squarings blow V up to ~1e7 and amplify
-    rounding.  There the bar is the oracle's own FP32 twin: the GPU error must
-    stay within 10x the error the same algorithm makes in FP32 arithmetic."""
+    size, compared on 256 sampled receivers away from contact with the
+    photometric-loss cotangent restricted to them.  Most of these receivers
+    sit under many overlapping caps (|F^| up to ~70), where the truncated
+    squarings amplify rounding; the oracle's FP32 twin (same algorithm in
+    FP32 arithmetic) is printed beside the GPU error as the inherent floor."""
+    import torch
     sc = scenegen.scene_gbuffer()
     ok = np.flatnonzero(~sc["contact"])
     idx = np.sort(np.random.default_rng(2).choice(ok, 256, replace=False))
     w = _gbuffer_cotangent(sc, idx)
     h = run_hip(sc, w)
     o = run_oracle(sc, w[idx], idx=idx)
-    t = run_oracle(sc, w[idx], idx=idx, dtype=__import__("torch").float32)
-    for key, err in (("V", rel_l2), ("B", rel_max)):
-        e_gpu = err(h[key][idx], o[key])
-        e_twin = err(t[key], o[key])
-        print(f"{key}: gpu {e_gpu:.2e} fp32-twin {e_twin:.2e}")
-        assert e_gpu <= max(TOL_V, 10 * e_twin), (key, e_gpu, e_twin)
-    for key in GRAD_KEYS:
-        a = h[key] if key in ("grad_light", "grad_spheres") else h[key][idx]
-        e_gpu = rel_l2(a, o[key])
-        e_twin = rel_l2(t[key], o[key])
-        print(f"{key}: gpu {e_gpu:.2e} fp32-twin {e_twin:.2e}")
-        assert e_gpu <= max(TOL_G, 10 * e_twin), (key, e_gpu, e_twin)
+    t = run_oracle(sc, w[idx], idx=idx, dtype=torch.float32)
+    print("fp32 twin: V %.2e B %.2e" % (rel_l2(t["V"], o["V"]), rel_max(t["B"], o["B"])))
+    check_forward({"V": h["V"][idx], "B": h["B"][idx]}, o)
+    check_grads(h, o, tol_geom=1e-3, idx=idx)
