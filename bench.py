@@ -1,9 +1,10 @@
 """Benchmark: point-sphere pair evaluations per second, forward + backward.
 
-One step = the whole differentiable path on one scene resident in HBM:
-sh_visibility_forward -> sh_shade -> sh_shade_backward ->
-sh_visibility_backward (gradients for receivers, normals, albedo, spheres and
-lighting), through the C ABI.  Default workload: the body-like scene (20,000
+One step = the whole differentiable path on one scene resident in HBM: the
+fused sh_render_forward (visibility + shading) and sh_render_backward
+(gradients for receivers, normals, albedo, spheres and lighting), through the
+C ABI (``--path separate`` uses the four separate entry points instead; the
+results are bit-identical).  Default workload: the body-like scene (20,000
 receivers on 24 capsules, 128 spheres, 8 bands, k = 4), synthetic and seeded.
 
 Prints one JSON line with the throughput, a roofline entry for the dominant
@@ -36,6 +37,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--path", default="render", choices=["render", "separate"])
+    ap.add_argument("--flags", type=int, default=0, help="shv_params.flags (kernel-variant selection)")
     return ap.parse_args()
 
 
@@ -100,7 +103,7 @@ def main():
     P = sc["points"].shape[0]
     S = sc["spheres"].shape[0]
     k = args.k
-    prm = _lib.params(n, 3.0, k)
+    prm = _lib.params(n, 3.0, k, args.flags)
 
     def t(a):
         return torch.as_tensor(np.ascontiguousarray(a)).to(dev)
@@ -109,7 +112,7 @@ def main():
     alb, sph, lig = t(sc["albedo"]), t(sc["spheres"]), t(sc["light"])
     gB = t(sc["grad_radiance"])
     vis = torch.empty(N, P, device=dev)
-    saved = torch.empty(_lib.shv_saved_floats(P, prm), device=dev)
+    saved = torch.empty(_lib.shv_render_saved_floats(P, prm), device=dev)
     rad = torch.empty(P, device=dev)
     gV = torch.empty(N, P, device=dev)
     gN = torch.empty(3, P, device=dev)
@@ -122,11 +125,16 @@ def main():
     stream = torch.cuda.Stream(device=dev)   # default priority
     st = stream.cuda_stream
 
-    def step():
-        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
-        _lib.sh_shade(vis, nrm, alb, lig, P, prm, rad, ws, nb, st)
-        _lib.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, gN, gA, gL, ws, nb, st)
-        _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
+    if args.path == "render":
+        def step():
+            _lib.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, ws, nb, st)
+            _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, gP, gN, gA, gS, gL, ws, nb, st)
+    else:
+        def step():
+            _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+            _lib.sh_shade(vis, nrm, alb, lig, P, prm, rad, ws, nb, st)
+            _lib.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, gN, gA, gL, ws, nb, st)
+            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
@@ -180,7 +188,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0},
+        "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0,
+                   "entry_points": args.path},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,

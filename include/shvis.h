@@ -63,7 +63,10 @@ typedef int32_t shv_status;
  * n = 8 (Sec. 3.2).  n_squarings: k, the number of squarings of the SH
  * exponential (fixed per call; 4 by default).  eps: depth of the log-blocker,
  * log V' = -eps inside a sphere's cone (Eq. 13; the paper uses 3).  flags:
- * reserved, must be 0. */
+ * 0 or one of the SHV_FLAG_* values below (they select a kernel variant,
+ * never the result: both variants are bitwise identical). */
+#define SHV_FLAG_EXP_ONE_WAVE 1u   /* exponential: one receiver per lane, one wave per 64 receivers */
+#define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves */
 typedef struct shv_params {
   int32_t n_bands;
   int32_t n_squarings;
@@ -131,6 +134,86 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
                                   const shv_params* prm, const float* saved, float* grad_points,
                                   float* grad_spheres, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
+
+/* Fused render path: the same results as sh_visibility_forward followed by
+ * sh_shade (bit-identical), in two launches.  `saved` holds
+ * shv_render_saved_floats() values: the visibility state followed by the lit
+ * transfer matrix M(L) (N x N); it may be NULL when no backward follows. */
+int64_t shv_render_saved_floats(int64_t P, const shv_params* prm);
+shv_status sh_render_forward(const float* points, const float* normals, const float* albedo,
+                             const float* spheres, const float* light, int64_t P, int64_t S,
+                             const shv_params* prm, float* vis, float* radiance, float* saved,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Fused adjoint of sh_render_forward for the cotangent grad_radiance [P]: the
+ * same results as sh_shade_backward followed by sh_visibility_backward
+ * (bit-identical), in three launches.  vis and saved come from
+ * sh_render_forward with the same inputs; every gradient output may be NULL. */
+shv_status sh_render_backward(const float* grad_radiance, const float* points, const float* normals,
+                              const float* albedo, const float* spheres, int64_t P, int64_t S,
+                              const shv_params* prm, const float* vis, const float* saved,
+                              float* grad_points, float* grad_normals, float* grad_albedo,
+                              float* grad_spheres, float* grad_light, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* Batched render path: many independent scenes (each with its own P, S,
+ * n_bands and k) forward and backward in a few persistent launches, every
+ * scene bit-identical to single-scene sh_render_forward / sh_render_backward.
+ *
+ * Scene description (host structure; every pointer is a device pointer as in
+ * the single-scene calls).  ws must hold shv_workspace_bytes(P, S, &params)
+ * bytes and saved shv_render_saved_floats(P, &params) floats; grad_* may be
+ * NULL; grad_radiance is read by the backward only. */
+typedef struct shv_scene {
+  const float* points;        /* [3][P] */
+  const float* normals;       /* [3][P] */
+  const float* albedo;        /* [P] */
+  const float* spheres;       /* [S][4], 16-byte aligned */
+  const float* light;         /* [N] */
+  const float* grad_radiance; /* [P] */
+  float* vis;                 /* [N][P] out */
+  float* radiance;            /* [P] out */
+  float* saved;               /* shv_render_saved_floats() out / in */
+  float* grad_points;         /* [3][P] out or NULL */
+  float* grad_normals;        /* [3][P] out or NULL */
+  float* grad_albedo;         /* [P] out or NULL */
+  float* grad_spheres;        /* [S][4] out or NULL */
+  float* grad_light;          /* [N] out or NULL */
+  void* ws;                   /* per-scene workspace, 256-byte aligned */
+  size_t ws_bytes;
+  int64_t P;
+  int64_t S;
+  shv_params params;
+} shv_scene;
+
+/* Bytes of the work table for n_scenes scenes. */
+size_t shv_batch_table_bytes(int32_t n_scenes);
+
+/* Host-side: validates every scene (errors name the scene index) and packs
+ * the work table into `table` (HOST memory, table_bytes bytes).  The caller
+ * copies the table verbatim to device memory and passes the device copy to
+ * the batched calls; the device copy may be rewritten between calls (a
+ * captured graph of the batched calls can be replayed for new batches, since
+ * the launch grids do not depend on the table's contents). */
+shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void* table,
+                                 size_t table_bytes);
+
+/* Launch mask of a built (host) table: bit n set when some scene with n bands
+ * uses the four-wave exponential layout, bit 16 + n when one uses the
+ * one-wave layout (the single-scene calls pick the layout from P and flags). */
+uint32_t shv_batch_table_launch_mask(const void* table_host);
+
+/* Forward of every scene of the batch: persistent launches, one per band
+ * count for the pair stage and one per (layout, band count) for the
+ * exponential and shading stage, as selected by launch_mask (pass the table's
+ * mask or a superset of it: launches for absent groups find no work).  The
+ * table itself stays on the device. */
+shv_status sh_render_batched_forward(const void* table_device, uint32_t launch_mask, hipStream_t stream);
+
+/* Backward of every scene of the batch (the same launch groups in reverse,
+ * then one launch for the closing reductions of all scenes); reads each
+ * scene's grad_radiance, vis and saved. */
+shv_status sh_render_batched_backward(const void* table_device, uint32_t launch_mask, hipStream_t stream);
 
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream.  shv_profile_enable(1) starts a new collection (at most

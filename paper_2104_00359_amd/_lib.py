@@ -31,13 +31,27 @@ SHV_ERR_HIP = -5
 EXPORTED = [
     "shv_init", "shv_status_string", "shv_last_error", "shv_saved_floats", "shv_workspace_bytes",
     "sh_visibility_forward", "sh_shade", "sh_shade_backward", "sh_visibility_backward",
+    "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
+    "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_launch_mask",
+    "sh_render_batched_forward", "sh_render_batched_backward",
     "shv_profile_enable", "shv_profile_report",
 ]
+
+SHV_FLAG_EXP_ONE_WAVE = 1
+SHV_FLAG_EXP_FOUR_WAVES = 2
 
 
 class shv_params(ctypes.Structure):
     _fields_ = [("n_bands", ctypes.c_int32), ("n_squarings", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class shv_scene(ctypes.Structure):
+    """One scene of a batched render (field order and types as in the C struct)."""
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved",
+        "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light", "ws")] + [
+        ("ws_bytes", ctypes.c_size_t), ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("params", shv_params)]
 
 
 _P = ctypes.c_void_p
@@ -55,6 +69,15 @@ _sig = {
     "sh_shade": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _PRM, _P, _P, _SZ, _P]),
     "sh_shade_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _PRM, _P, _P, _P, _P, _P, _SZ, _P]),
     "sh_visibility_backward": (ctypes.c_int32, [_P, _P, _P, _I64, _P, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
+    "shv_render_saved_floats": (_I64, [_I64, _PRM]),
+    "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
+    "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _P, _P, _P, _P,
+                                            _SZ, _P]),
+    "shv_batch_table_bytes": (_SZ, [ctypes.c_int32]),
+    "shv_batch_table_build": (ctypes.c_int32, [ctypes.POINTER(shv_scene), ctypes.c_int32, _P, _SZ]),
+    "shv_batch_table_launch_mask": (ctypes.c_uint32, [_P]),
+    "sh_render_batched_forward": (ctypes.c_int32, [_P, ctypes.c_uint32, _P]),
+    "sh_render_batched_backward": (ctypes.c_int32, [_P, ctypes.c_uint32, _P]),
     "shv_profile_enable": (ctypes.c_int32, [ctypes.c_int, ctypes.c_int32]),
     "shv_profile_report": (_I64, [ctypes.c_char_p, _I64]),
 }
@@ -131,6 +154,56 @@ def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, gra
     _check(_lib.sh_visibility_backward(ptr(grad_vis), ptr(vis), ptr(points), int(P), ptr(spheres), int(S),
                                        ctypes.byref(prm), ptr(saved), ptr(grad_points), ptr(grad_spheres),
                                        ptr(ws), int(ws_bytes), stream), "sh_visibility_backward")
+
+
+def shv_render_saved_floats(P: int, prm: shv_params) -> int:
+    return int(_lib.shv_render_saved_floats(int(P), ctypes.byref(prm)))
+
+
+def sh_render_forward(points, normals, albedo, spheres, light, P, S, prm, vis, radiance, saved, ws, ws_bytes,
+                      stream):
+    _check(_lib.sh_render_forward(ptr(points), ptr(normals), ptr(albedo), ptr(spheres), ptr(light), int(P), int(S),
+                                  ctypes.byref(prm), ptr(vis), ptr(radiance), ptr(saved), ptr(ws), int(ws_bytes),
+                                  stream), "sh_render_forward")
+
+
+def sh_render_backward(grad_radiance, points, normals, albedo, spheres, P, S, prm, vis, saved, grad_points,
+                       grad_normals, grad_albedo, grad_spheres, grad_light, ws, ws_bytes, stream):
+    _check(_lib.sh_render_backward(ptr(grad_radiance), ptr(points), ptr(normals), ptr(albedo), ptr(spheres), int(P),
+                                   int(S), ctypes.byref(prm), ptr(vis), ptr(saved), ptr(grad_points),
+                                   ptr(grad_normals), ptr(grad_albedo), ptr(grad_spheres), ptr(grad_light), ptr(ws),
+                                   int(ws_bytes), stream), "sh_render_backward")
+
+
+def shv_batch_table_bytes(n_scenes: int) -> int:
+    return int(_lib.shv_batch_table_bytes(int(n_scenes)))
+
+
+def shv_batch_table_build(scenes, table_host) -> None:
+    """Pack the work table of ``scenes`` (a sequence of shv_scene) into the
+    host buffer ``table_host`` (a writable ctypes buffer or bytearray-backed
+    object exposing the buffer protocol, or a CPU tensor of uint8)."""
+    n = len(scenes)
+    arr = (shv_scene * max(n, 1))(*scenes)
+    if hasattr(table_host, "data_ptr"):
+        addr, size = table_host.data_ptr(), table_host.numel() * table_host.element_size()
+    else:
+        addr, size = ctypes.addressof(table_host), ctypes.sizeof(table_host)
+    _check(_lib.shv_batch_table_build(arr, n, addr, size), "shv_batch_table_build")
+
+
+def shv_batch_table_launch_mask(table_host) -> int:
+    addr = table_host.data_ptr() if hasattr(table_host, "data_ptr") else ctypes.addressof(table_host)
+    return int(_lib.shv_batch_table_launch_mask(addr))
+
+
+def sh_render_batched_forward(table_device, launch_mask, stream):
+    _check(_lib.sh_render_batched_forward(ptr(table_device), int(launch_mask), stream), "sh_render_batched_forward")
+
+
+def sh_render_batched_backward(table_device, launch_mask, stream):
+    _check(_lib.sh_render_batched_backward(ptr(table_device), int(launch_mask), stream),
+           "sh_render_batched_backward")
 
 
 def shv_profile_enable(enable: bool, capacity: int = 4096) -> None:

@@ -16,7 +16,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libshvis.so")
-SOURCES = ["shv_api.hip", "shv_pair.hip", "shv_exp.hip", "shv_shade.hip"]
+# (source, extra flags, object name): the band-count-dependent kernels are
+# compiled once per band count.
+SOURCES = [("shv_nb.hip", [f"-DSHV_NB={n}", f"-DSHV_PART={part}"], f"shv_nb{n}_p{part}.o")
+           for n in range(8, 0, -1) for part in (3, 2, 5, 4, 1, 0)] + [
+    ("shv_api.hip", [], "shv_api.o"), ("shv_common.hip", [], "shv_common.o")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled on purpose (see the design notes).
@@ -35,14 +39,32 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def _newest_input():
+    names = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h"))]
+    names += [os.path.join(CSRC, "generated", f) for f in os.listdir(os.path.join(CSRC, "generated"))]
+    names += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    names.append(os.path.abspath(__file__))
+    return max(os.path.getmtime(n) for n in names)
+
+
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile everything (``incremental`` skips objects newer than every
+    source and header; meant for development only)."""
     os.makedirs(BUILD, exist_ok=True)
-    _run([sys.executable, os.path.join(CSRC, "gen_tables.py"), os.path.join(CSRC, "generated")])
+    gen_dir = os.path.join(CSRC, "generated")
+    gen_stamp = os.path.join(gen_dir, "shv_gaunt.h")
+    if not (incremental and os.path.exists(gen_stamp)
+            and os.path.getmtime(gen_stamp) >= os.path.getmtime(os.path.join(CSRC, "gen_tables.py"))):
+        _run([sys.executable, os.path.join(CSRC, "gen_tables.py"), gen_dir])
+    newest = _newest_input()
     objs = []
 
-    def compile_one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(entry):
+        src, extra, name = entry
+        obj = os.path.join(BUILD, name)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
+            return obj
+        cmd = [HIPCC, *HIPFLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         out = _run(cmd)
         if verbose and out.strip():
             print(out)
@@ -57,4 +79,4 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

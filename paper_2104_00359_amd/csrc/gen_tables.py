@@ -162,6 +162,36 @@ def clamped_cosine(l):
     return 2 * PI * (-1) ** (l // 2 - 1) / ((l + 2) * (l - 1)) * _f(l) / (2 ** l * _f(l // 2) ** 2)
 
 
+N_GROUPS = 4
+
+
+def output_groups(n, ng=N_GROUPS):
+    """Partition of the N output coefficients of a squaring into ``ng`` groups
+    with balanced cost (FMAs plus the distinct products each group needs),
+    greedy over outputs in decreasing term count.  Deterministic."""
+    N = n * n
+    C = real_gaunt(n)
+    terms = {i: set() for i in range(N)}
+    for (i, j, k) in C:
+        if j <= k:
+            terms[i].add((j, k))
+    order = sorted(range(N), key=lambda i: (-len(terms[i]), i))
+    groups = [[] for _ in range(ng)]
+    pairs = [set() for _ in range(ng)]
+    fm = [0] * ng
+    for i in order:
+        best = None
+        for g in range(ng):
+            c = fm[g] + len(terms[i]) + len(pairs[g] | terms[i])
+            if best is None or c < best[0]:
+                best = (c, g)
+        g = best[1]
+        groups[g].append(i)
+        pairs[g] |= terms[i]
+        fm[g] += len(terms[i])
+    return [sorted(x) for x in groups]
+
+
 # ----------------------------------------------------------------- emission
 
 def flit(x: float) -> str:
@@ -271,19 +301,58 @@ def emit_gaunt(path):
                 L.append(f"  eb[{j}] = 0.0f;")
         L.append("}")
 
-        # acc += v * h with h supported on the transfer support (lighting gradient)
-        supp = set(transfer_support(n))
-        L.append(f"__device__ __forceinline__ void shv_vh_acc_{n}(const float* __restrict__ v, const float* __restrict__ h, float* __restrict__ acc) {{")
-        vh = {}
-        for (i, j, k) in C:
-            if k in supp:
-                vh.setdefault((j, k), []).append(i)
-        for (j, k) in sorted(vh):
-            L.append(f"  {{ const float t = v[{j}] * h[{k}];")
-            for i in sorted(vh[(j, k)]):
-                L.append(f"    acc[{i}] = fmaf({flit(C[(i, j, k)])}, t, acc[{i}]);")
-            L.append("  }")
-        L.append("}")
+        # Per-group variants for kernels that split one receiver's squaring
+        # over several waves: group g computes only its outputs, with exactly
+        # the per-output term order of the full functions above.
+        groups = output_groups(n)
+        gid = [0] * N
+        for g, members in enumerate(groups):
+            for i in members:
+                gid[i] = g
+        L.append(f"static constexpr unsigned char SHV_GRP_{n}[{N}] = {{" + ",".join(map(str, gid)) + "};")
+        for g, members in enumerate(groups):
+            mem = set(members)
+            L.append(f"__device__ __forceinline__ void shv_square_{n}_g{g}(const float* __restrict__ e, float* __restrict__ o) {{")
+            touched = set()
+            for (j, k) in sorted(pairs):
+                outs = [i for i in pairs[(j, k)] if i in mem]
+                if not outs:
+                    continue
+                L.append(f"  {{ const float t = e[{j}] * e[{k}];")
+                for i in outs:
+                    c = C[(i, j, k)] * (2.0 if j < k else 1.0)
+                    if i in touched:
+                        L.append(f"    o[{i}] = fmaf({flit(c)}, t, o[{i}]);")
+                    else:
+                        L.append(f"    o[{i}] = {flit(c)} * t;")
+                        touched.add(i)
+                L.append("  }")
+            for i in members:
+                if i not in touched:
+                    L.append(f"  o[{i}] = 0.0f;")
+            L.append("}")
+            L.append(f"__device__ __forceinline__ void shv_square_adj_{n}_g{g}(const float* __restrict__ ob, const float* __restrict__ e, float* __restrict__ eb) {{")
+            touched = set()
+            for (i, k) in sorted(upairs):
+                outs = [j for j in sorted(upairs[(i, k)]) if j in mem]
+                if not outs:
+                    continue
+                if i == k:
+                    L.append(f"  {{ const float u = ob[{i}] * e[{i}];")
+                else:
+                    L.append(f"  {{ const float u = fmaf(ob[{i}], e[{k}], ob[{k}] * e[{i}]);")
+                for j in outs:
+                    c = 2.0 * C[(j, i, k)]
+                    if j in touched:
+                        L.append(f"    eb[{j}] = fmaf({flit(c)}, u, eb[{j}]);")
+                    else:
+                        L.append(f"    eb[{j}] = {flit(c)} * u;")
+                        touched.add(j)
+                L.append("  }")
+            for j in members:
+                if j not in touched:
+                    L.append(f"  eb[{j}] = 0.0f;")
+            L.append("}")
 
         # sparse table grouped by (j, k) for building M(L)_jk = sum_i L_i C_ijk
         rows = [[] for _ in range(N * N)]
@@ -305,9 +374,31 @@ def emit_gaunt(path):
         L.append(f"__device__ const unsigned char shv_mtab_idx_{n}[{max(len(ei), 1)}] = {{" + ",".join(map(str, ei or [0])) + "};")
         L.append(f"__device__ const float shv_mtab_val_{n}[{max(len(ec), 1)}] = {{" + ",".join(flit(c) for c in (ec or [0.0])) + "};")
     L.append("")
+    L.append("// Lighting-gradient contraction Lbar_i = sum_{j, kk} C_{i j k(kk)} Q[j][kk],")
+    L.append("// Q over the transfer support (kk indexes the support); CSR over i, entries j * 32 + kk.")
+    for n in range(1, MAX_BANDS + 1):
+        N = n * n
+        C = real_gaunt(n)
+        supp = transfer_support(n)
+        pos = {k: kk for kk, k in enumerate(supp)}
+        rows = [[] for _ in range(N)]
+        for (i, j, k), c in C.items():
+            if k in pos:
+                rows[i].append((j * 32 + pos[k], c))
+        ptr, ent, val = [0], [], []
+        for r in rows:
+            for e, c in sorted(r):
+                ent.append(e)
+                val.append(c)
+            ptr.append(len(ent))
+        L.append(f"__device__ const int shv_ltab_ptr_{n}[{len(ptr)}] = {{" + ",".join(map(str, ptr)) + "};")
+        L.append(f"__device__ const unsigned short shv_ltab_ent_{n}[{max(len(ent), 1)}] = {{" + ",".join(map(str, ent or [0])) + "};")
+        L.append(f"__device__ const float shv_ltab_val_{n}[{max(len(val), 1)}] = {{" + ",".join(flit(c) for c in (val or [0.0])) + "};")
+    L.append("")
     for n in range(1, MAX_BANDS + 1):
         supp = transfer_support(n)
         L.append(f"static constexpr int SHV_HSUPP_COUNT_{n} = {len(supp)};")
+        L.append(f"static constexpr int SHV_HSUPP_{n}[{len(supp)}] = {{" + ",".join(map(str, supp)) + "};")
     open(path, "w").write("\n".join(L) + "\n")
 
 

@@ -13,6 +13,8 @@
 #include <vector>
 
 #include "shvis.h"
+#include "shv_batch.h"
+#include "shv_config.h"
 #include "shv_launch.h"
 
 namespace {
@@ -97,7 +99,10 @@ shv_status check_params(const shv_params* prm) {
     return set_error(SHV_ERR_UNSUPPORTED, "n_squarings=%d outside [0, %d]", prm->n_squarings, SHV_MAX_SQUARINGS);
   if (!(prm->eps == prm->eps) || prm->eps < 0.0f)
     return set_error(SHV_ERR_INVALID_ARG, "eps must be a non-negative number");
-  if (prm->flags != 0) return set_error(SHV_ERR_INVALID_ARG, "flags must be 0");
+  const uint32_t known = SHV_FLAG_EXP_ONE_WAVE | SHV_FLAG_EXP_FOUR_WAVES;
+  if (prm->flags & ~known) return set_error(SHV_ERR_INVALID_ARG, "unknown flags 0x%x", prm->flags);
+  if ((prm->flags & known) == known)
+    return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_ONE_WAVE and SHV_FLAG_EXP_FOUR_WAVES are exclusive");
   return SHV_OK;
 }
 
@@ -145,7 +150,7 @@ size_t fwd_bytes(int64_t P, int64_t S, int nb, FwdWs* o = nullptr) {
 size_t shade_bytes(int64_t P, int nb, ShadeWs* o = nullptr) {
   const size_t N = (size_t)nb * nb;
   const size_t m = align_up(N * N * 4);
-  const size_t lp = align_up((size_t)shv::shade_blocks(P) * N * 4);
+  const size_t lp = align_up((size_t)shv::pair_blocks(P) * N * 4);
   if (o) {
     o->M = 0;
     o->lpart = m;
@@ -157,13 +162,36 @@ size_t visbwd_bytes(int64_t P, int64_t S, int nb, VisBwdWs* o = nullptr) {
   const size_t N = (size_t)nb * nb;
   const size_t w = align_up(N * (size_t)P * 4);
   const size_t gp = align_up((size_t)sp.nchunks * 3 * (size_t)P * 4);
-  const size_t gs = align_up((size_t)shv::point_blocks(P) * (size_t)S * 16);
+  const size_t gs = align_up((size_t)shv::pair_blocks(P) * (size_t)S * 16);
   if (o) {
     o->W = 0;
     o->gp = w;
     o->gs = w + gp;
   }
   return w + gp + gs;
+}
+
+struct RenderBwdWs {
+  size_t W, gp, gs, lp;
+};
+size_t render_bwd_bytes(int64_t P, int64_t S, int nb, RenderBwdWs* o = nullptr) {
+  const shv::Split sp = shv::choose_split(P, S);
+  const size_t N = (size_t)nb * nb;
+  const size_t w = align_up(N * (size_t)P * 4);
+  const size_t gp = align_up((size_t)sp.nchunks * 3 * (size_t)P * 4);
+  const size_t gs = align_up((size_t)shv::pair_blocks(P) * (size_t)S * 16);
+  const size_t lp = align_up((size_t)shv::pair_blocks(P) * N * 4);
+  if (o) {
+    o->W = 0;
+    o->gp = w;
+    o->gs = w + gp;
+    o->lp = w + gp + gs;
+  }
+  return w + gp + gs + lp;
+}
+// Forward: the F' partials, then M(L) when it is not kept in `saved`.
+size_t render_fwd_bytes(int64_t P, int64_t S, int nb) {
+  return fwd_bytes(P, S, nb) + align_up((size_t)nb * nb * nb * nb * 4);
 }
 
 shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
@@ -217,7 +245,103 @@ size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm) {
   size_t b = fwd_bytes(P, S, nb);
   b = std::max(b, shade_bytes(P, nb));
   b = std::max(b, visbwd_bytes(P, S, nb));
+  b = std::max(b, render_fwd_bytes(P, S, nb));
+  b = std::max(b, render_bwd_bytes(P, S, nb));
   return b;
+}
+
+int64_t shv_render_saved_floats(int64_t P, const shv_params* prm) {
+  if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || prm->n_squarings < 0 || P < 0) return 0;
+  const int64_t N = (int64_t)prm->n_bands * prm->n_bands;
+  return (1 + (int64_t)prm->n_squarings * N) * P + N * N;
+}
+
+shv_status sh_render_forward(const float* points, const float* normals, const float* albedo, const float* spheres,
+                             const float* light, int64_t P, int64_t S, const shv_params* prm, float* vis,
+                             float* radiance, float* saved, void* ws, size_t ws_bytes, hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, S));
+  SHV_TRY(check_device());
+  if (P == 0) return SHV_OK;
+  SHV_TRY(need(points, "points"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(light, "light"));
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(radiance, "radiance"));
+  if (S > 0) {
+    SHV_TRY(need(spheres, "spheres"));
+    SHV_TRY(aligned16(spheres, "spheres"));
+  }
+  const int nb = prm->n_bands;
+  SHV_TRY(check_ws(ws, ws_bytes, render_fwd_bytes(P, S, nb)));
+  float* Fpart = (float*)ws;
+  const int64_t N = (int64_t)nb * nb;
+  float* M = saved ? saved + (1 + (int64_t)prm->n_squarings * N) * P : (float*)((char*)ws + fwd_bytes(P, S, nb));
+  const shv::Split sp = shv::choose_split(P, S);
+  SHV_TRY(launch("pair_fwd", stream, [&] {
+    return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, light, M, stream);
+  }));
+  SHV_TRY(launch("exp_shade_fwd", stream, [&] {
+    return shv::launch_render_exp_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, vis, saved, normals,
+                                      albedo, M, radiance, prm->flags, stream);
+  }));
+  return SHV_OK;
+}
+
+shv_status sh_render_backward(const float* grad_radiance, const float* points, const float* normals,
+                              const float* albedo, const float* spheres, int64_t P, int64_t S, const shv_params* prm,
+                              const float* vis, const float* saved, float* grad_points, float* grad_normals,
+                              float* grad_albedo, float* grad_spheres, float* grad_light, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, S));
+  SHV_TRY(check_device());
+  const int nb = prm->n_bands;
+  const int N = nb * nb;
+  if (P == 0) {
+    if (grad_light)
+      SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_light, N, stream); }));
+    if (grad_spheres && S > 0)
+      SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_spheres, 4 * S, stream); }));
+    return SHV_OK;
+  }
+  SHV_TRY(need(grad_radiance, "grad_radiance"));
+  SHV_TRY(need(points, "points"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(saved, "saved"));
+  if (S > 0) {
+    SHV_TRY(need(spheres, "spheres"));
+    SHV_TRY(aligned16(spheres, "spheres"));
+  }
+  RenderBwdWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, render_bwd_bytes(P, S, nb, &L)));
+  float* W = (float*)((char*)ws + L.W);
+  float* gp = (float*)((char*)ws + L.gp);
+  float* gs = (float*)((char*)ws + L.gs);
+  float* lp = (float*)((char*)ws + L.lp);
+  const float* M = saved + (1 + (int64_t)prm->n_squarings * N) * P;
+  const shv::Split sp = shv::choose_split(P, S);
+  SHV_TRY(launch("exp_shade_bwd", stream, [&] {
+    return shv::launch_render_exp_bwd(nb, grad_radiance, vis, saved, P, prm->eps, prm->n_squarings, W, normals,
+                                      albedo, M, grad_normals, grad_albedo, grad_light ? lp : nullptr, prm->flags,
+                                      stream);
+  }));
+  const bool need_pair = grad_points || (grad_spheres && S > 0);
+  if (need_pair) {
+    SHV_TRY(launch("pair_bwd", stream, [&] {
+      return shv::launch_pair_bwd(nb, W, points, P, spheres, (int)S, sp, gp, gs, stream);
+    }));
+  }
+  if (grad_spheres && S == 0) grad_spheres = nullptr;
+  SHV_TRY(launch("finalize", stream, [&] {
+    return shv::launch_finalize(gp, sp.nchunks, P, need_pair ? grad_points : nullptr, gs,
+                                (int)shv::pair_blocks(P), S, grad_spheres, lp, (int)shv::pair_blocks(P), N, grad_light,
+                                stream);
+  }));
+  return SHV_OK;
 }
 
 shv_status sh_visibility_forward(const float* points, int64_t P, const float* spheres, int64_t S,
@@ -239,10 +363,11 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
   float* Fpart = (float*)ws;
   const shv::Split sp = shv::choose_split(P, S);
   SHV_TRY(launch("pair_fwd", stream, [&] {
-    return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, stream);
+    return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, nullptr, nullptr, stream);
   }));
   SHV_TRY(launch("exp_fwd", stream, [&] {
-    return shv::launch_exp_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, vis, saved, stream);
+    return shv::launch_exp_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, vis, saved, prm->flags,
+                               stream);
   }));
   return SHV_OK;
 }
@@ -299,7 +424,7 @@ shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const
   }));
   if (grad_light) {
     SHV_TRY(launch("reduce_light", stream, [&] {
-      return shv::launch_reduce_rows(Lpart, shv::shade_blocks(P), N, grad_light, stream);
+      return shv::launch_reduce_rows(Lpart, (int)shv::pair_blocks(P), N, grad_light, stream);
     }));
   }
   return SHV_OK;
@@ -333,7 +458,7 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   float* gs = (float*)((char*)ws + L.gs);
   const shv::Split sp = shv::choose_split(P, S);
   SHV_TRY(launch("exp_bwd", stream, [&] {
-    return shv::launch_exp_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, W, stream);
+    return shv::launch_exp_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, W, prm->flags, stream);
   }));
   SHV_TRY(launch("pair_bwd", stream, [&] {
     return shv::launch_pair_bwd(nb, W, points, P, spheres, (int)S, sp, gp, gs, stream);
@@ -345,9 +470,172 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   }
   if (grad_spheres && S > 0) {
     SHV_TRY(launch("reduce_spheres", stream, [&] {
-      return shv::launch_reduce_rows(gs, (int)shv::point_blocks(P), (int)(4 * S), grad_spheres, stream);
+      return shv::launch_reduce_rows(gs, (int)shv::pair_blocks(P), (int)(4 * S), grad_spheres, stream);
     }));
   }
+  return SHV_OK;
+}
+
+size_t shv_batch_table_bytes(int32_t n_scenes) {
+  if (n_scenes < 0) return 0;
+  return shv::batch_table_bytes(n_scenes);
+}
+
+shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void* table, size_t table_bytes) {
+  if (n_scenes < 0) return set_error(SHV_ERR_INVALID_ARG, "negative scene count");
+  if (n_scenes > 0 && !scenes) return set_error(SHV_ERR_INVALID_ARG, "scenes is NULL");
+  if (!table) return set_error(SHV_ERR_INVALID_ARG, "table is NULL");
+  if (table_bytes < shv_batch_table_bytes(n_scenes))
+    return set_error(SHV_ERR_WORKSPACE, "table has %zu bytes, needs %zu", table_bytes, shv_batch_table_bytes(n_scenes));
+  shv::BatchHeader h{};
+  h.n_scenes = n_scenes;
+  shv::BatchScene* out = (shv::BatchScene*)((char*)table + sizeof(shv::BatchHeader));
+  int32_t* order = (int32_t*)((char*)table + sizeof(shv::BatchHeader) + (size_t)n_scenes * sizeof(shv::BatchScene));
+  int32_t* eorder = order + n_scenes;
+  int64_t tf = 0;
+  for (int32_t i = 0; i < n_scenes; ++i) {
+    const shv_scene& in = scenes[i];
+    const shv_params* prm = &in.params;
+    shv_status st = check_params(prm);
+    if (st == SHV_OK) st = check_sizes(in.P, in.S);
+    const char* what = nullptr;
+    if (st == SHV_OK && in.P > 0) {
+      if (!in.points) what = "points";
+      else if (!in.normals) what = "normals";
+      else if (!in.albedo) what = "albedo";
+      else if (!in.light) what = "light";
+      else if (!in.vis) what = "vis";
+      else if (!in.radiance) what = "radiance";
+      else if (!in.saved) what = "saved";
+      else if (in.S > 0 && !in.spheres) what = "spheres";
+      if (what) st = set_error(SHV_ERR_INVALID_ARG, "%s is NULL", what);
+      else if (in.S > 0 && (((uintptr_t)in.spheres) & 15u)) st = set_error(SHV_ERR_INVALID_ARG, "spheres misaligned");
+    }
+    if (st == SHV_OK) st = check_ws(in.ws, in.ws_bytes, in.P > 0 ? shv_workspace_bytes(in.P, in.S, prm) : 0);
+    if (st != SHV_OK) {
+      const std::string msg = g_last_error;
+      return set_error(st, "scene %d: %s", (int)i, msg.c_str());
+    }
+    shv::BatchScene b{};
+    const int nb = prm->n_bands;
+    const int64_t N = (int64_t)nb * nb;
+    b.points = in.points;
+    b.normals = in.normals;
+    b.albedo = in.albedo;
+    b.spheres = in.spheres;
+    b.light = in.light;
+    b.grad_radiance = in.grad_radiance;
+    b.vis = in.vis;
+    b.radiance = in.radiance;
+    b.saved = in.saved;
+    b.grad_points = in.grad_points;
+    b.grad_normals = in.grad_normals;
+    b.grad_albedo = in.grad_albedo;
+    b.grad_spheres = in.S > 0 ? in.grad_spheres : nullptr;
+    b.grad_light = in.grad_light;
+    b.P = in.P;
+    b.S = in.S;
+    b.nb = nb;
+    b.k = prm->n_squarings;
+    b.eps = prm->eps;
+    b.flags = prm->flags;
+    const shv::Split sp = shv::choose_split(in.P, in.S);
+    b.nchunks = sp.nchunks;
+    b.chunk = sp.chunk;
+    b.four_waves = shv::exp_four_waves(in.P, prm->flags) ? 1 : 0;
+    b.pair_tiles = shv::pair_blocks(in.P);
+    b.exp_blocks = b.four_waves ? (in.P + 63) / 64 : shv::point_blocks(in.P);
+    // the same workspace carving as the single-scene render entry points
+    RenderBwdWs L;
+    render_bwd_bytes(in.P, in.S, nb, &L);
+    char* ws = (char*)in.ws;
+    b.Fpart = (float*)ws;
+    b.M = in.saved ? in.saved + (1 + (int64_t)prm->n_squarings * N) * in.P : nullptr;
+    b.W = (float*)(ws + L.W);
+    b.gp = (float*)(ws + L.gp);
+    b.gs = (float*)(ws + L.gs);
+    b.lp = (float*)(ws + L.lp);
+    const bool need_pair = in.P > 0 && (in.grad_points || b.grad_spheres);
+    b.fin_pts = (need_pair && in.grad_points) ? (int32_t)((3 * in.P + SHV_BLOCK - 1) / SHV_BLOCK) : 0;
+    b.fin_cols_s = b.grad_spheres ? (int32_t)(4 * in.S) : 0;
+    b.fin_cols_l = in.grad_light ? (int32_t)N : 0;
+    b.n_pair = in.P > 0 ? b.pair_tiles * sp.nchunks : 0;
+    b.n_exp = in.P > 0 ? b.exp_blocks : 0;
+    b.n_fin = (int64_t)b.fin_pts + b.fin_cols_s + b.fin_cols_l;
+    const int lay = b.four_waves;
+    b.off_pair = h.total_pair[nb];
+    b.off_exp = h.total_exp[lay][nb];
+    b.off_fin = tf;
+    h.total_pair[nb] += b.n_pair;
+    h.total_exp[lay][nb] += b.n_exp;
+    tf += b.n_fin;
+    h.grp_count[nb] += 1;
+    h.egrp_count[lay][nb] += 1;
+    if (b.n_exp > 0) h.launch_mask |= 1u << (nb + (lay ? 0 : 16));
+    out[i] = b;
+  }
+  h.total_fin = tf;
+  int32_t pos = 0, epos = 0;
+  for (int nb = 0; nb <= SHV_MAX_BANDS_API; ++nb) {
+    h.grp_begin[nb] = pos;
+    for (int32_t i = 0; i < n_scenes; ++i)
+      if (out[i].nb == nb) order[pos++] = i;
+  }
+  for (int lay = 0; lay < 2; ++lay) {
+    for (int nb = 0; nb <= SHV_MAX_BANDS_API; ++nb) {
+      h.egrp_begin[lay][nb] = epos;
+      for (int32_t i = 0; i < n_scenes; ++i)
+        if (out[i].nb == nb && out[i].four_waves == lay) eorder[epos++] = i;
+    }
+  }
+  *(shv::BatchHeader*)table = h;
+  return SHV_OK;
+}
+
+uint32_t shv_batch_table_launch_mask(const void* table) {
+  return table ? ((const shv::BatchHeader*)table)->launch_mask : 0u;
+}
+
+// Launches of one phase for every (layout, band count) group in the mask:
+// bit nb = four-wave exponential layout, bit 16 + nb = one-wave layout.
+static shv_status batched_phase(int phase, uint32_t mask, const void* table, hipStream_t stream) {
+  static const char* names[4] = {"batch_pair_fwd", "batch_exp_shade_fwd", "batch_exp_shade_bwd", "batch_pair_bwd"};
+  for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
+    const bool four = mask & (1u << nb), one = mask & (1u << (nb + 16));
+    if (phase == 0 || phase == 3) {
+      if (four || one)
+        SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, false, table, stream); }));
+      continue;
+    }
+    if (four)
+      SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, true, table, stream); }));
+    if (one)
+      SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, false, table, stream); }));
+  }
+  return SHV_OK;
+}
+
+static shv_status check_mask(uint32_t mask) {
+  if (mask & ~0x01FE01FEu) return set_error(SHV_ERR_INVALID_ARG, "launch mask 0x%x has unknown bits", mask);
+  return SHV_OK;
+}
+
+shv_status sh_render_batched_forward(const void* table, uint32_t launch_mask, hipStream_t stream) {
+  SHV_TRY(check_device());
+  SHV_TRY(need(table, "table"));
+  SHV_TRY(check_mask(launch_mask));
+  SHV_TRY(batched_phase(0, launch_mask, table, stream));
+  SHV_TRY(batched_phase(1, launch_mask, table, stream));
+  return SHV_OK;
+}
+
+shv_status sh_render_batched_backward(const void* table, uint32_t launch_mask, hipStream_t stream) {
+  SHV_TRY(check_device());
+  SHV_TRY(need(table, "table"));
+  SHV_TRY(check_mask(launch_mask));
+  SHV_TRY(batched_phase(2, launch_mask, table, stream));
+  SHV_TRY(batched_phase(3, launch_mask, table, stream));
+  SHV_TRY(launch("batch_finalize", stream, [&] { return shv::launch_batch_finalize(table, stream); }));
   return SHV_OK;
 }
 

@@ -1,0 +1,127 @@
+// Device-side work table of the batched (multi-scene) render path.
+//
+// The host packs a BatchHeader, one BatchScene record per scene and two index
+// arrays that list the scenes grouped by band count (pair phases) and by
+// exponential layout and band count (exponential phases).  Every phase of a
+// batched forward or backward runs as persistent launches, one per group
+// present, whose blocks walk that group's item space with a fixed stride
+// (item = one block's worth of work of one scene, exactly a block of the
+// single-scene kernel); the closing reductions run as one launch over all
+// scenes.  Scene
+// records carry the split decisions of the single-scene entry points, so every
+// scene's results are bit-identical to a single-scene call.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shvis.h"
+
+namespace shv {
+
+struct BatchScene {
+  // inputs
+  const float* points;         // [3][P]
+  const float* normals;        // [3][P]
+  const float* albedo;         // [P]
+  const float* spheres;        // [S][4]
+  const float* light;          // [N]
+  const float* grad_radiance;  // [P] (backward)
+  // outputs
+  float* vis;                  // [N][P]
+  float* radiance;             // [P]
+  float* saved;                // render saved state (M(L) at its end)
+  float* grad_points;          // [3][P] or NULL
+  float* grad_normals;         // [3][P] or NULL
+  float* grad_albedo;          // [P] or NULL
+  float* grad_spheres;         // [S][4] or NULL (NULL when S = 0)
+  float* grad_light;           // [N] or NULL
+  // workspace regions
+  float* Fpart;
+  float* M;
+  float* W;
+  float* gp;
+  float* gs;
+  float* lp;
+  int64_t P, S;
+  int32_t nb, k;
+  float eps;
+  uint32_t flags;
+  int32_t nchunks, chunk;      // sphere split of the pair kernels
+  int32_t four_waves;          // exponential layout
+  int32_t fin_pts, fin_cols_s, fin_cols_l;
+  int64_t pair_tiles;          // ceil(P / 64)
+  int64_t exp_blocks;          // blocks of the exponential kernels
+  int64_t n_pair, n_exp, n_fin;        // items per phase
+  int64_t off_pair;            // first pair item within the band count's item space
+  int64_t off_exp;             // first exponential item within the (layout, band count) item space
+  int64_t off_fin;             // first item of the closing reductions (all scenes)
+};
+
+struct BatchHeader {
+  int32_t n_scenes;
+  uint32_t launch_mask;                          // see shv_batch_table_launch_mask()
+  int64_t total_fin;
+  int64_t total_pair[SHV_MAX_BANDS_API + 1];     // pair items per band count
+  int32_t grp_begin[SHV_MAX_BANDS_API + 1];      // slice of `order` per band count
+  int32_t grp_count[SHV_MAX_BANDS_API + 1];
+  int64_t total_exp[2][SHV_MAX_BANDS_API + 1];   // exponential items per (layout, band count)
+  int32_t egrp_begin[2][SHV_MAX_BANDS_API + 1];  // slice of `eorder` per (layout, band count)
+  int32_t egrp_count[2][SHV_MAX_BANDS_API + 1];
+};
+
+enum BatchPhase { kPhasePair = 0, kPhaseExp = 1 };
+
+constexpr int kBatchGrid = 1024;  // persistent blocks per launch
+
+// Layout: header, n scene records, `order` (scene ids grouped by band count),
+// `eorder` (scene ids grouped by exponential layout, then band count).
+inline size_t batch_table_bytes(int32_t n) {
+  return sizeof(BatchHeader) + (size_t)n * sizeof(BatchScene) + 2 * (size_t)n * sizeof(int32_t);
+}
+
+// Read-only view of a device table.
+struct BatchView {
+  const BatchHeader* h;
+  const BatchScene* sc;
+  const int32_t* order;
+  const int32_t* eorder;
+  __device__ explicit BatchView(const char* t)
+      : h(reinterpret_cast<const BatchHeader*>(t)),
+        sc(reinterpret_cast<const BatchScene*>(t + sizeof(BatchHeader))),
+        order(reinterpret_cast<const int32_t*>(t + sizeof(BatchHeader) + h->n_scenes * sizeof(BatchScene))),
+        eorder(order + h->n_scenes) {}
+
+  // Scene of a group owning `item`: the last one whose offset is <= item.
+  template <class Off>
+  __device__ const BatchScene& find(const int32_t* g, int count, int64_t item, Off off) const {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off(sc[g[mid]]) <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    return sc[g[lo]];
+  }
+
+  __device__ const BatchScene& scene_of(int nb, int64_t item, int) const {
+    return find(order + h->grp_begin[nb], h->grp_count[nb], item, [](const BatchScene& s) { return s.off_pair; });
+  }
+
+  __device__ const BatchScene& scene_of_exp(int four, int nb, int64_t item) const {
+    return find(eorder + h->egrp_begin[four][nb], h->egrp_count[four][nb], item,
+                [](const BatchScene& s) { return s.off_exp; });
+  }
+
+  __device__ const BatchScene& scene_of_fin(int64_t item) const {
+    int lo = 0, hi = h->n_scenes - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sc[mid].off_fin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    return sc[lo];
+  }
+};
+
+}  // namespace shv

@@ -1,0 +1,272 @@
+// Host-side dispatch on the band count, kernel-variant choices, and the
+// kernels that do not depend on the band count (fills and the deterministic
+// reductions that close a backward pass, single-scene and batched).
+
+#include <hip/hip_runtime.h>
+
+#include "shv_batch.h"
+#include "shv_config.h"
+#include "shv_launch.h"
+#include "shvis.h"
+
+namespace shv {
+
+Split choose_split(int64_t P, int64_t S) {
+  Split sp{1, (int)(S > 0 ? S : 1)};
+  if (S <= 0) return sp;
+  const int64_t waves = 4 * pair_blocks(P);  // 4 waves per 64-receiver tile
+  const int64_t target_waves = 4096;  // 4 waves per SIMD on 256 CUs x 4 SIMDs
+  int64_t n = waves > 0 ? (target_waves + waves - 1) / waves : 1;
+  const int64_t max_by_size = (S + 63) / 64;  // keep >= 16 spheres per wave
+  if (n > max_by_size) n = max_by_size;
+  const int64_t min_by_lds = (S + SHV_MAX_CHUNK - 1) / SHV_MAX_CHUNK;
+  if (n < min_by_lds) n = min_by_lds;
+  if (n < 1) n = 1;
+  const int64_t chunk = (S + n - 1) / n;
+  sp.chunk = (int)chunk;
+  sp.nchunks = (int)((S + chunk - 1) / chunk);
+  return sp;
+}
+
+int64_t point_blocks(int64_t P) { return (P + SHV_BLOCK - 1) / SHV_BLOCK; }
+int64_t pair_blocks(int64_t P) { return (P + 63) / 64; }
+
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_fill_zero(float* __restrict__ p, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (j < n) p[j] = 0.0f;
+}
+
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill_zero<<<(unsigned)((n + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(p, n);
+  return hipGetLastError();
+}
+
+// out[j] = sum_c part[c * len + j], c in order.
+__device__ __forceinline__ void sum_chunks_at(const float* __restrict__ part, int nchunks, int64_t len, int64_t j,
+                                              float* __restrict__ out) {
+  if (j >= len) return;
+  float a = part[j];
+  for (int c = 1; c < nchunks; ++c) a += part[(int64_t)c * len + j];
+  out[j] = a;
+}
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_sum_chunks(const float* __restrict__ part, int nchunks, int64_t len,
+                                                          float* __restrict__ out) {
+  sum_chunks_at(part, nchunks, len, (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x, out);
+}
+
+hipError_t launch_sum_chunks(const float* part, int nchunks, int64_t len, float* out, hipStream_t st) {
+  if (len <= 0) return hipSuccess;
+  k_sum_chunks<<<(unsigned)((len + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(part, nchunks, len, out);
+  return hipGetLastError();
+}
+
+// out[c] = sum_r part[r * cols + c]: the block's threads sum a fixed stride of
+// rows (batches of independent loads), then a fixed-shape tree in LDS.
+__device__ __forceinline__ void reduce_column(const float* __restrict__ part, int rows, int cols, int c,
+                                              float* __restrict__ out, float* buf) {
+  float a = 0.0f;
+  for (int r0 = threadIdx.x; r0 < rows; r0 += 4 * SHV_BLOCK) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * SHV_BLOCK;
+      v[u] = r < rows ? part[(int64_t)r * cols + c] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a += v[u];
+  }
+  buf[threadIdx.x] = a;
+  __syncthreads();
+#pragma unroll
+  for (int w = SHV_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = buf[0];
+}
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_reduce_rows(const float* __restrict__ part, int rows, int cols,
+                                                           float* __restrict__ out) {
+  __shared__ float buf[SHV_BLOCK];
+  reduce_column(part, rows, cols, blockIdx.x, out, buf);
+}
+
+// All reductions that close a backward pass, in one launch: blocks
+// [0, nb_pts) sum the receiver-gradient chunks, the next 4S blocks reduce the
+// sphere-gradient columns, the last N blocks the lighting-gradient columns.
+__device__ __forceinline__ void finalize_item(const float* __restrict__ gp_part, int nchunks, int64_t P,
+                                              float* __restrict__ grad_points, int nb_pts,
+                                              const float* __restrict__ gs_part, int rows_s, int cols_s,
+                                              float* __restrict__ grad_spheres, const float* __restrict__ l_part,
+                                              int rows_l, int cols_l, float* __restrict__ grad_light, int b,
+                                              float* buf) {
+  if (b < nb_pts) {
+    sum_chunks_at(gp_part, nchunks, 3 * P, (int64_t)b * SHV_BLOCK + threadIdx.x, grad_points);
+  } else if (b < nb_pts + cols_s) {
+    reduce_column(gs_part, rows_s, cols_s, b - nb_pts, grad_spheres, buf);
+  } else {
+    reduce_column(l_part, rows_l, cols_l, b - nb_pts - cols_s, grad_light, buf);
+  }
+}
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_finalize(const float* __restrict__ gp_part, int nchunks, int64_t P,
+                                                        float* __restrict__ grad_points, int nb_pts,
+                                                        const float* __restrict__ gs_part, int rows_s, int cols_s,
+                                                        float* __restrict__ grad_spheres,
+                                                        const float* __restrict__ l_part, int rows_l, int cols_l,
+                                                        float* __restrict__ grad_light) {
+  __shared__ float buf[SHV_BLOCK];
+  finalize_item(gp_part, nchunks, P, grad_points, nb_pts, gs_part, rows_s, cols_s, grad_spheres, l_part, rows_l,
+                cols_l, grad_light, blockIdx.x, buf);
+}
+
+hipError_t launch_finalize(const float* gp_part, int nchunks, int64_t P, float* grad_points, const float* gs_part,
+                           int rows_s, int64_t S, float* grad_spheres, const float* l_part, int rows_l, int N,
+                           float* grad_light, hipStream_t st) {
+  const int nb_pts = grad_points ? (int)((3 * P + SHV_BLOCK - 1) / SHV_BLOCK) : 0;
+  const int cols_s = grad_spheres ? (int)(4 * S) : 0;
+  const int cols_l = grad_light ? N : 0;
+  const int grid = nb_pts + cols_s + cols_l;
+  if (grid == 0) return hipSuccess;
+  k_finalize<<<(unsigned)grid, SHV_BLOCK, 0, st>>>(gp_part, nchunks, P, grad_points, nb_pts, gs_part, rows_s, cols_s,
+                                                    grad_spheres, l_part, rows_l, cols_l, grad_light);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st) {
+  if (cols <= 0) return hipSuccess;
+  k_reduce_rows<<<(unsigned)cols, SHV_BLOCK, 0, st>>>(part, rows, cols, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched closing reductions (all scenes of a batch in one launch).
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_batch_finalize(const char* __restrict__ table) {
+  __shared__ float buf[SHV_BLOCK];
+  const BatchView v(table);
+  const int64_t total = v.h->total_fin;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const BatchScene& S = v.scene_of_fin(item);
+    const int b = (int)(item - S.off_fin);
+    finalize_item(S.gp, S.nchunks, S.P, S.fin_pts ? S.grad_points : nullptr, S.fin_pts, S.gs, (int)S.pair_tiles,
+                  S.fin_cols_s, S.grad_spheres, S.lp, (int)S.pair_tiles, S.fin_cols_l, S.grad_light, b, buf);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch_finalize(const void* table, hipStream_t st) {
+  k_batch_finalize<<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+  return hipGetLastError();
+}
+
+bool exp_four_waves(int64_t P, uint32_t flags) {
+  if (flags & SHV_FLAG_EXP_ONE_WAVE) return false;
+  if (flags & SHV_FLAG_EXP_FOUR_WAVES) return true;
+  return (P + 63) / 64 < 1024;  // fewer than 1024 receiver waves: spread each receiver over 4
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch on the band count to the per-band-count launchers.
+
+#define SHV_NB_SWITCH(nb, CALL)          \
+  switch (nb) {                          \
+    case 1: return CALL(1);              \
+    case 2: return CALL(2);              \
+    case 3: return CALL(3);              \
+    case 4: return CALL(4);              \
+    case 5: return CALL(5);              \
+    case 6: return CALL(6);              \
+    case 7: return CALL(7);              \
+    case 8: return CALL(8);              \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_pair_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, Split sp, float* Fpart,
+                           const float* light, float* M, hipStream_t st) {
+#define C(N) pair_fwd_nb<N>(pts, P, sph, S, sp, Fpart, light, M, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S, Split sp,
+                           float* gp_part, float* gs_part, hipStream_t st) {
+#define C(N) pair_bwd_nb<N>(W, pts, P, sph, S, sp, gp_part, gs_part, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_exp_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis,
+                          float* saved, uint32_t flags, hipStream_t st) {
+#define C(N) exp_fwd_nb<N, false>(Fpart, nchunks, P, eps, k, vis, saved, nullptr, nullptr, nullptr, nullptr, flags, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_render_exp_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis,
+                                 float* saved, const float* nrm, const float* alb, const float* M, float* rad,
+                                 uint32_t flags, hipStream_t st) {
+#define C(N) exp_fwd_nb<N, true>(Fpart, nchunks, P, eps, k, vis, saved, nrm, alb, M, rad, flags, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
+                          int k, float* W, uint32_t flags, hipStream_t st) {
+#define C(N) \
+  exp_bwd_nb<N, false>(gV, vis, saved, P, eps, k, W, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, flags, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_render_exp_bwd(int nb, const float* gB, const float* vis, const float* saved, int64_t P, float eps,
+                                 int k, float* W, const float* nrm, const float* alb, const float* M, float* gN,
+                                 float* gA, float* Lpart, uint32_t flags, hipStream_t st) {
+#define C(N) exp_bwd_nb<N, true>(gB, vis, saved, P, eps, k, W, nrm, alb, M, gN, gA, Lpart, flags, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st) {
+#define C(N) build_M_nb<N>(light, M, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_shade_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M, int64_t P,
+                            float* rad, hipStream_t st) {
+#define C(N) shade_fwd_nb<N>(vis, nrm, alb, M, P, rad, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
+                            const float* M, int64_t P, float* gV, float* gN, float* gA, float* Lpart,
+                            hipStream_t st) {
+#define C(N) shade_bwd_nb<N>(gB, vis, nrm, alb, M, P, gV, gN, gA, Lpart, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, hipStream_t st) {
+  switch (phase) {
+#define C(N) batch_pair_fwd_nb<N>(table, st)
+    case 0: SHV_NB_SWITCH(nb, C)
+#undef C
+#define C(N) batch_exp_fwd_nb<N>(table, four, st)
+    case 1: SHV_NB_SWITCH(nb, C)
+#undef C
+#define C(N) batch_exp_bwd_nb<N>(table, four, st)
+    case 2: SHV_NB_SWITCH(nb, C)
+#undef C
+#define C(N) batch_pair_bwd_nb<N>(table, st)
+    case 3: SHV_NB_SWITCH(nb, C)
+#undef C
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace shv

@@ -1,0 +1,6 @@
+// Launch-shape constants shared by host and device code.
+#pragma once
+
+#define SHV_BLOCK 256                              // threads per block (4 waves of 64)
+#define SHV_WAVES_PER_BLOCK (SHV_BLOCK / 64)
+#define SHV_MAX_CHUNK 512                          // spheres per block in the pair kernels (LDS bound)

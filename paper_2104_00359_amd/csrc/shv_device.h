@@ -17,9 +17,7 @@
 #include "generated/shv_constants.h"
 #include "generated/shv_gaunt.h"
 
-#define SHV_BLOCK 256
-#define SHV_WAVES_PER_BLOCK (SHV_BLOCK / 64)
-#define SHV_MAX_CHUNK 512
+#include "shv_config.h"
 
 namespace shv {
 
@@ -144,3 +142,31 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 }  // namespace shv
+
+// Template dispatch on the number of bands (1 .. 8) for kernel launches.
+#define SHV_DISPATCH(nb, KERNEL, ...)            \
+  switch (nb) {                                  \
+    case 1: KERNEL<1><<<__VA_ARGS__; break;      \
+    case 2: KERNEL<2><<<__VA_ARGS__; break;      \
+    case 3: KERNEL<3><<<__VA_ARGS__; break;      \
+    case 4: KERNEL<4><<<__VA_ARGS__; break;      \
+    case 5: KERNEL<5><<<__VA_ARGS__; break;      \
+    case 6: KERNEL<6><<<__VA_ARGS__; break;      \
+    case 7: KERNEL<7><<<__VA_ARGS__; break;      \
+    case 8: KERNEL<8><<<__VA_ARGS__; break;      \
+    default: return hipErrorInvalidValue;        \
+  }
+
+// Same, for kernels with a second (bool) template parameter.
+#define SHV_DISPATCH2(nb, KERNEL, B, ...)           \
+  switch (nb) {                                     \
+    case 1: KERNEL<1, B><<<__VA_ARGS__; break;      \
+    case 2: KERNEL<2, B><<<__VA_ARGS__; break;      \
+    case 3: KERNEL<3, B><<<__VA_ARGS__; break;      \
+    case 4: KERNEL<4, B><<<__VA_ARGS__; break;      \
+    case 5: KERNEL<5, B><<<__VA_ARGS__; break;      \
+    case 6: KERNEL<6, B><<<__VA_ARGS__; break;      \
+    case 7: KERNEL<7, B><<<__VA_ARGS__; break;      \
+    case 8: KERNEL<8, B><<<__VA_ARGS__; break;      \
+    default: return hipErrorInvalidValue;           \
+  }

@@ -1,0 +1,626 @@
+// SH exponential V = exp*(F) and its adjoint.
+//
+// The paper replaces the product of blocker vectors (Eq. 12) by the
+// exponential of the summed log-blockers and adopts Ren et al.'s scaling,
+// squaring and optimal linear approximation.  With N = n^2 coefficients:
+//   c   = F_0 / sqrt(4 pi)                 (the constant value of the DC part)
+//   G   = (F with F_0 := 0) * 2^-k
+//   E_0 = a (sqrt(4 pi) e_0 + G),  a = exp(|G|^2 / (8 pi))
+//         (least-squares line a + b g through exp(g) when g's values over the
+//          sphere are Gaussian with variance |G|^2 / (4 pi); it gives a = b)
+//   E_{j+1} = E_j * E_j  (k truncated triple-product squarings, Eqs. 6-7)
+//   V   = exp(c) E_k
+// The squaring is straight-line generated code (coefficients are literals).
+// Saved for the adjoint, coefficient-major: row 0 = c, rows 1 + j*N + i = E_j[i].
+//
+// The forward kernels also sum the sphere-chunk partials of F' in a fixed
+// order and apply F_lm = eps * LAMBDA[l][|m|] * F'_lm.  The adjoint writes
+// W = eps * LAMBDA * dLoss/dF, the weights the pair adjoint consumes.
+//
+// Two layouts, bitwise identical in their results: one receiver per lane
+// (large receiver counts), or each receiver's squarings spread over the 4
+// waves of a block, one output group per wave, exchanged through LDS (small
+// receiver counts, where one wave per 64 receivers would leave most SIMDs
+// idle).  With SHADE the kernels also run the shading step (forward) or its
+// adjoint (backward) in the same launch, for the fused render entry points.
+
+#pragma once
+
+#include "shv_batch.h"
+#include "shv_launch.h"
+#include "shv_shade_common.h"
+#include "shvis.h"
+
+namespace shv {
+
+
+template <int NB>
+__device__ __forceinline__ void square(const float* e, float* o);
+template <int NB>
+__device__ __forceinline__ void square_adj(const float* ob, const float* e, float* eb);
+
+#define SHV_SQ(n)                                                                                    \
+  template <>                                                                                        \
+  __device__ __forceinline__ void square<n>(const float* e, float* o) { shv_square_##n(e, o); }      \
+  template <>                                                                                        \
+  __device__ __forceinline__ void square_adj<n>(const float* ob, const float* e, float* eb) {        \
+    shv_square_adj_##n(ob, e, eb);                                                                   \
+  }
+SHV_SQ(1)
+SHV_SQ(2)
+SHV_SQ(3)
+SHV_SQ(4)
+SHV_SQ(5)
+SHV_SQ(6)
+SHV_SQ(7)
+SHV_SQ(8)
+#undef SHV_SQ
+
+// Group g of the output coefficients of one squaring (see the generator).
+template <int NB, int G>
+struct SqGroup;
+#define SHV_SQG(n, g)                                                                                        \
+  template <>                                                                                                \
+  struct SqGroup<n, g> {                                                                                     \
+    static __device__ __forceinline__ void square(const float* e, float* o) { shv_square_##n##_g##g(e, o); } \
+    static __device__ __forceinline__ void adj(const float* ob, const float* e, float* eb) {                 \
+      shv_square_adj_##n##_g##g(ob, e, eb);                                                                  \
+    }                                                                                                        \
+  };
+#define SHV_SQG4(n) SHV_SQG(n, 0) SHV_SQG(n, 1) SHV_SQG(n, 2) SHV_SQG(n, 3)
+SHV_SQG4(1)
+SHV_SQG4(2)
+SHV_SQG4(3)
+SHV_SQG4(4)
+SHV_SQG4(5)
+SHV_SQG4(6)
+SHV_SQG4(7)
+SHV_SQG4(8)
+#undef SHV_SQG4
+#undef SHV_SQG
+
+template <int NB>
+__device__ __forceinline__ constexpr int group_of(int i);
+#define SHV_GOF(n) \
+  template <>      \
+  __device__ __forceinline__ constexpr int group_of<n>(int i) { return SHV_GRP_##n[i]; }
+SHV_GOF(1)
+SHV_GOF(2)
+SHV_GOF(3)
+SHV_GOF(4)
+SHV_GOF(5)
+SHV_GOF(6)
+SHV_GOF(7)
+SHV_GOF(8)
+#undef SHV_GOF
+
+// LAMBDA[l][|m|] of coefficient i (constant-folded after unrolling).
+__device__ __forceinline__ float coef_lambda(int i) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= i) ++l;
+  const int m = i - l * l - l;
+  return SHV_LAMBDA[l][m < 0 ? -m : m];
+}
+
+// d loss / d c = V . Vbar, summed as four partial sums over the output groups
+// (index order within a group), then over groups 0..3: the same order in the
+// one-wave and four-wave kernels.
+template <int NB>
+__device__ __forceinline__ float cbar_canonical(const float* vb, const float* v) {
+  constexpr int N = NB * NB;
+  float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 0; i < N; ++i) part[group_of<NB>(i)] = fmaf(vb[i], v[i], part[group_of<NB>(i)]);
+  return ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// E_0 from the summed F' of one receiver (in place): returns c.
+template <int NB>
+__device__ __forceinline__ float exp_prologue(float (&E)[NB * NB], float eps, int k) {
+  constexpr int N = NB * NB;
+#pragma unroll
+  for (int i = 0; i < N; ++i) E[i] *= eps * coef_lambda(i);
+  const float c = E[0] * SHV_INV_SQRT_4PI;
+  const float scale = __builtin_ldexpf(1.0f, -k);
+  float sig = 0.0f;
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    E[i] *= scale;
+    sig = fmaf(E[i], E[i], sig);
+  }
+  const float a = expf(sig * SHV_INV_8PI);
+  E[0] = a * SHV_SQRT_4PI;
+#pragma unroll
+  for (int i = 1; i < N; ++i) E[i] *= a;
+  return c;
+}
+
+// Adjoint of the linear approximation and of the scaling; E holds E_0 and Eb
+// its cotangent.  Writes W_i = eps LAMBDA_i Fbar_i for coefficients i with
+// keep(i).
+template <int NB, class Keep>
+__device__ __forceinline__ void exp_epilogue(float (&E)[NB * NB], const float (&Eb)[NB * NB], float cbar, float eps,
+                                             int k, int64_t P, int64_t p, float* __restrict__ Wout, Keep keep) {
+  constexpr int N = NB * NB;
+  const float a = E[0] * SHV_INV_SQRT_4PI;
+  const float inva = 1.0f / a;
+  float dot = SHV_SQRT_4PI * Eb[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    E[i] *= inva;  // G_i
+    dot = fmaf(Eb[i], E[i], dot);
+  }
+  // Gbar_i = a (Ebar_i + G_i / (4 pi) (sqrt(4 pi) Ebar_0 + sum_j Ebar_j G_j))
+  const float scale = __builtin_ldexpf(1.0f, -k);
+  const float kdot = dot * SHV_INV_4PI;
+  if (keep(0)) Wout[p] = eps * SHV_LAMBDA[0][0] * cbar * SHV_INV_SQRT_4PI;
+#pragma unroll
+  for (int l = 1; l < NB; ++l) {
+#pragma unroll
+    for (int m = -l; m <= l; ++m) {
+      const int i = idx(l, m);
+      if (!keep(i)) continue;
+      const float gb = a * fmaf(E[i], kdot, Eb[i]);
+      Wout[(int64_t)i * P + p] = eps * SHV_LAMBDA[l][m < 0 ? -m : m] * scale * gb;
+    }
+  }
+}
+
+struct ShadeArgs {
+  const float* nrm;  // [3][P]
+  const float* alb;  // [P]
+  const float* M;    // [N][N]
+  float* rad;        // forward: radiance [P]
+  float* gN;         // backward: normal cotangent [3][P] (may be NULL)
+  float* gA;         // backward: albedo cotangent [P] (may be NULL)
+  float* Lpart;      // backward: per-tile lighting-gradient partials [tiles][N] (may be NULL)
+};
+
+__device__ __forceinline__ void load_normal(const float* nrm, int64_t P, int64_t p, bool ok, float& x, float& y,
+                                            float& z) {
+  x = ok ? nrm[p] : 0.0f;
+  y = ok ? nrm[P + p] : 0.0f;
+  z = ok ? nrm[2 * P + p] : 1.0f;
+}
+
+// ===========================================================================
+// One receiver per lane.
+
+template <int NB, bool SHADE>
+__device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, int nchunks, int64_t P, float eps,
+                                              int k, float* __restrict__ vis, float* __restrict__ saved,
+                                              const ShadeArgs& sa, int64_t bx) {
+  constexpr int N = NB * NB;
+  const int64_t p = bx * SHV_BLOCK + threadIdx.x;
+  if (p >= P) return;
+  float E[N], O[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) E[i] = Fpart[(int64_t)i * P + p];
+  for (int c = 1; c < nchunks; ++c) {
+    const float* src = Fpart + (int64_t)c * N * P + p;
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] += src[(int64_t)i * P];
+  }
+  const float c = exp_prologue<NB>(E, eps, k);
+  if (saved) saved[p] = c;
+  for (int j = 0; j < k; ++j) {
+    if (saved) {
+      float* dst = saved + (int64_t)(1 + j * N) * P + p;
+#pragma unroll
+      for (int i = 0; i < N; ++i) dst[(int64_t)i * P] = E[i];
+    }
+    square<NB>(E, O);
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] = O[i];
+  }
+  const float ec = expf(c);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    E[i] = ec * E[i];
+    vis[(int64_t)i * P + p] = E[i];
+  }
+  if constexpr (SHADE) {
+    float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
+    load_normal(sa.nrm, P, p, true, nx, ny, nz);
+    transfer<NB>(nx, ny, nz, H, ux, uy, uz);
+    sa.rad[p] = sa.alb[p] * shade_value<NB, false>(E, H, sa.M, 0.0f, Hb);
+  }
+}
+
+template <int NB, bool SHADE>
+__global__ __launch_bounds__(SHV_BLOCK) void k_exp_fwd(const float* __restrict__ Fpart, int nchunks, int64_t P,
+                                                       float eps, int k, float* __restrict__ vis,
+                                                       float* __restrict__ saved, ShadeArgs sa) {
+  exp_fwd1_item<NB, SHADE>(Fpart, nchunks, P, eps, k, vis, saved, sa, blockIdx.x);
+}
+
+template <int NB, bool SHADE>
+__device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, const float* __restrict__ vis,
+                                              const float* __restrict__ saved, int64_t P, float eps, int k,
+                                              float* __restrict__ Wout, const ShadeArgs& sa, int64_t bx,
+                                              LightTile* LTp) {
+  constexpr int N = NB * NB;
+  const int64_t p = bx * SHV_BLOCK + threadIdx.x;
+  const bool ok = p < P;
+  if (!SHADE && !ok) return;  // no barriers in the unfused kernel
+  float Eb[N], E[N], T[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) E[i] = ok ? vis[(int64_t)i * P + p] : 0.0f;  // V
+  if constexpr (SHADE) {
+    // gIn is the radiance cotangent: shading adjoint first (Vbar into Eb).
+    LightTile& LT = *LTp;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
+#pragma unroll
+    for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
+    load_normal(sa.nrm, P, p, ok, nx, ny, nz);
+    const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
+    const float bb = ok ? gIn[p] : 0.0f;
+    const float w = bb * (ok ? sa.alb[p] : 0.0f);
+    const float s = shade_value<NB, true>(E, H, sa.M, w, Hb);
+    if (ok && sa.gA) sa.gA[p] = bb * s;
+    if (ok && sa.gN) {
+      float gx, gy, gz;
+      normal_grad<NB>(Hb, ux, uy, uz, inv, gx, gy, gz);
+      sa.gN[p] = gx;
+      sa.gN[P + p] = gy;
+      sa.gN[2 * P + p] = gz;
+    }
+    if (sa.Lpart) {
+      for (int r = 0; r < SHV_WAVES_PER_BLOCK; ++r) {
+        const int64_t tile = bx * SHV_WAVES_PER_BLOCK + r;
+        if (tile * 64 >= P) break;  // uniform
+        if (wave == r) {
+          tile_put_v<NB>(LT, lane, E);
+          tile_put_wh<NB>(LT, lane, H, w);
+        }
+        __syncthreads();
+        tile_light_partial<NB>(LT, sa.Lpart + tile * N);
+      }
+    }
+    if (!ok) return;  // no barriers below
+#pragma unroll
+    for (int j = 0; j < N; ++j) Eb[j] = vbar_entry<NB>(j, H, sa.M, w);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) Eb[i] = gIn[(int64_t)i * P + p];
+  }
+  const float c = saved[p];
+  const float ec = expf(c);
+  const float cbar = cbar_canonical<NB>(Eb, E);  // d/dc of exp(c) E_k . Vbar = V . Vbar
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (k == 0) E[i] = E[i] / ec;  // E_0 itself when there is no squaring
+    Eb[i] = ec * Eb[i];
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    const float* src = saved + (int64_t)(1 + j * N) * P + p;
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] = src[(int64_t)i * P];
+    square_adj<NB>(Eb, E, T);  // Ebar_j = 2 (Ebar_{j+1} * E_j)
+#pragma unroll
+    for (int i = 0; i < N; ++i) Eb[i] = T[i];
+  }
+  exp_epilogue<NB>(E, Eb, cbar, eps, k, P, p, Wout, [](int) { return true; });
+}
+
+template <int NB, bool SHADE>
+__global__ __launch_bounds__(SHV_BLOCK) void k_exp_bwd(const float* __restrict__ gIn, const float* __restrict__ vis,
+                                                       const float* __restrict__ saved, int64_t P, float eps, int k,
+                                                       float* __restrict__ Wout, ShadeArgs sa) {
+  if constexpr (SHADE) {
+    __shared__ LightTile LT;
+    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, &LT);
+  } else {
+    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, nullptr);
+  }
+}
+
+// ===========================================================================
+// Four waves per 64 receivers; wave G owns output group G.
+
+template <int NB, int G, bool SHADE>
+__device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*Bx)[64], int lane, int64_t p, bool ok,
+                                              const float* __restrict__ Fpart, int nchunks, int64_t P, float eps,
+                                              int k, float* __restrict__ vis, float* __restrict__ saved,
+                                              const ShadeArgs& sa) {
+  constexpr int N = NB * NB;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (group_of<NB>(i) != G) continue;
+    float v = ok ? Fpart[(int64_t)i * P + p] : 0.0f;
+    for (int c = 1; c < nchunks; ++c) v += ok ? Fpart[((int64_t)c * N + i) * P + p] : 0.0f;
+    X[0][i][lane] = v;
+  }
+  __syncthreads();
+  float E[N], O[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) E[i] = X[0][i][lane];
+  const float c = exp_prologue<NB>(E, eps, k);
+  if (G == 0 && saved && ok) saved[p] = c;
+  for (int j = 0; j < k; ++j) {
+    if (saved && ok) {
+      float* dst = saved + (int64_t)(1 + j * N) * P + p;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (group_of<NB>(i) == G) dst[(int64_t)i * P] = E[i];
+    }
+    SqGroup<NB, G>::square(E, O);
+    const int b = (j + 1) & 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) X[b][i][lane] = O[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] = X[b][i][lane];
+  }
+  const float ec = expf(c);
+#pragma unroll
+  for (int i = 0; i < N; ++i) E[i] = ec * E[i];  // V, complete in every wave
+  if (ok) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) vis[(int64_t)i * P + p] = E[i];
+  }
+  if constexpr (SHADE) {
+    float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
+    load_normal(sa.nrm, P, p, ok, nx, ny, nz);
+    transfer<NB>(nx, ny, nz, H, ux, uy, uz);
+    Bx[G][lane] = shade_partial<NB, G, false>(E, H, sa.M, 0.0f, Hb);
+    __syncthreads();
+    if (G == 0 && ok) sa.rad[p] = sa.alb[p] * (((Bx[0][lane] + Bx[1][lane]) + Bx[2][lane]) + Bx[3][lane]);
+  }
+}
+
+template <int NB>
+struct Exp4FwdShared {
+  float X[2][NB * NB][64];
+  float Bx[4][64];
+};
+
+template <int NB, bool SHADE>
+__device__ __forceinline__ void exp_fwd4_item(const float* __restrict__ Fpart, int nchunks, int64_t P, float eps,
+                                              int k, float* __restrict__ vis, float* __restrict__ saved,
+                                              const ShadeArgs& sa, int64_t bx, Exp4FwdShared<NB>& sh) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t p = bx * 64 + lane;
+  const bool ok = p < P;
+  switch (wave) {
+    case 0: exp_fwd_group<NB, 0, SHADE>(sh.X, sh.Bx, lane, p, ok, Fpart, nchunks, P, eps, k, vis, saved, sa); break;
+    case 1: exp_fwd_group<NB, 1, SHADE>(sh.X, sh.Bx, lane, p, ok, Fpart, nchunks, P, eps, k, vis, saved, sa); break;
+    case 2: exp_fwd_group<NB, 2, SHADE>(sh.X, sh.Bx, lane, p, ok, Fpart, nchunks, P, eps, k, vis, saved, sa); break;
+    default: exp_fwd_group<NB, 3, SHADE>(sh.X, sh.Bx, lane, p, ok, Fpart, nchunks, P, eps, k, vis, saved, sa); break;
+  }
+}
+
+template <int NB, bool SHADE>
+__global__ __launch_bounds__(SHV_BLOCK) void k_exp_fwd4(const float* __restrict__ Fpart, int nchunks, int64_t P,
+                                                        float eps, int k, float* __restrict__ vis,
+                                                        float* __restrict__ saved, ShadeArgs sa) {
+  __shared__ Exp4FwdShared<NB> sh;
+  exp_fwd4_item<NB, SHADE>(Fpart, nchunks, P, eps, k, vis, saved, sa, blockIdx.x, sh);
+}
+
+struct Bwd4Shared {
+  float Cb[4][64];   // cbar partial per output group
+  float Sx[4][64];   // shading partial per support-column group
+  float HbX[32][64]; // y_k cotangents on the transfer support
+};
+
+template <int NB, int G, bool SHADE>
+__device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Shared& sh, LightTile& LT, int64_t bx,
+                                              int lane, int64_t p, bool ok, const float* __restrict__ gIn,
+                                              const float* __restrict__ vis, const float* __restrict__ saved,
+                                              int64_t P, float eps, int k, float* __restrict__ Wout,
+                                              const ShadeArgs& sa) {
+  constexpr int N = NB * NB;
+  const float c = ok ? saved[p] : 0.0f;
+  const float ec = expf(c);
+  float Eb[N], E[N], T[N];
+  if constexpr (!SHADE) {
+    // exchange Vbar (X[1]) and V (X[0]); group part of cbar in index order
+    float part = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (group_of<NB>(i) != G) continue;
+      const float vb = ok ? gIn[(int64_t)i * P + p] : 0.0f;
+      const float v = ok ? vis[(int64_t)i * P + p] : 0.0f;
+      part = fmaf(vb, v, part);
+      X[1][i][lane] = vb;
+      X[0][i][lane] = v;
+    }
+    sh.Cb[G][lane] = part;
+    __syncthreads();
+  } else {
+    // V from the group loads; then the shading adjoint split over the waves
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) X[0][i][lane] = ok ? vis[(int64_t)i * P + p] : 0.0f;
+    __syncthreads();
+    float V[N], H[N], Hb[N], nx, ny, nz, ux, uy, uz;
+#pragma unroll
+    for (int i = 0; i < N; ++i) V[i] = X[0][i][lane];
+    load_normal(sa.nrm, P, p, ok, nx, ny, nz);
+    const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
+    const float bb = ok ? gIn[p] : 0.0f;
+    const float w = bb * (ok ? sa.alb[p] : 0.0f);
+    sh.Sx[G][lane] = shade_partial<NB, G, true>(V, H, sa.M, w, Hb);
+    {
+      int kk = 0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) {
+        if (!h_support(l)) continue;
+#pragma unroll
+        for (int m = -l; m <= l; ++m) {
+          if ((kk & 3) == G) sh.HbX[kk][lane] = Hb[idx(l, m)];
+          ++kk;
+        }
+      }
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (group_of<NB>(j) != G) continue;
+      const float vb = vbar_entry<NB>(j, H, sa.M, w);
+      part = fmaf(vb, V[j], part);
+      X[1][j][lane] = vb;
+    }
+    sh.Cb[G][lane] = part;
+    if (G == 2) tile_put_v<NB>(LT, lane, V);
+    if (G == 3) tile_put_wh<NB>(LT, lane, H, w);
+    __syncthreads();
+    if (G == 0 && ok && sa.gA)
+      sa.gA[p] = bb * (((sh.Sx[0][lane] + sh.Sx[1][lane]) + sh.Sx[2][lane]) + sh.Sx[3][lane]);
+    if (G == 1 && ok && sa.gN) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
+      int kk = 0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) {
+        if (!h_support(l)) continue;
+#pragma unroll
+        for (int m = -l; m <= l; ++m) Hb[idx(l, m)] = sh.HbX[kk++][lane];
+      }
+      float gx, gy, gz;
+      normal_grad<NB>(Hb, ux, uy, uz, inv, gx, gy, gz);
+      sa.gN[p] = gx;
+      sa.gN[P + p] = gy;
+      sa.gN[2 * P + p] = gz;
+    }
+    if (sa.Lpart) tile_light_partial<NB>(LT, sa.Lpart + bx * N);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    Eb[i] = ec * X[1][i][lane];
+    E[i] = X[0][i][lane] / ec;  // E_0 when k = 0; overwritten otherwise
+  }
+  const float cbar = ((sh.Cb[0][lane] + sh.Cb[1][lane]) + sh.Cb[2][lane]) + sh.Cb[3][lane];
+  for (int j = k - 1; j >= 0; --j) {
+    __syncthreads();  // everyone has read X[0] / X[1] of the previous step
+    const float* src = saved + (int64_t)(1 + j * N) * P + p;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) X[0][i][lane] = ok ? src[(int64_t)i * P] : 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] = X[0][i][lane];
+    SqGroup<NB, G>::adj(Eb, E, T);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) X[1][i][lane] = T[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) Eb[i] = X[1][i][lane];
+  }
+  if (!ok) return;
+  exp_epilogue<NB>(E, Eb, cbar, eps, k, P, p, Wout, [](int i) { return group_of<NB>(i) == G; });
+}
+
+template <int NB>
+struct Exp4BwdShared {
+  float X[2][NB * NB][64];
+  Bwd4Shared sh;
+  LightTile LT;
+};
+
+template <int NB, bool SHADE>
+__device__ __forceinline__ void exp_bwd4_item(const float* __restrict__ gIn, const float* __restrict__ vis,
+                                              const float* __restrict__ saved, int64_t P, float eps, int k,
+                                              float* __restrict__ Wout, const ShadeArgs& sa, int64_t bx,
+                                              Exp4BwdShared<NB>& S) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t p = bx * 64 + lane;
+  const bool ok = p < P;
+  switch (wave) {
+    case 0: exp_bwd_group<NB, 0, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 1: exp_bwd_group<NB, 1, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 2: exp_bwd_group<NB, 2, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    default:
+      exp_bwd_group<NB, 3, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa);
+      break;
+  }
+}
+
+template <int NB, bool SHADE>
+__global__ __launch_bounds__(SHV_BLOCK, 2) void k_exp_bwd4(const float* __restrict__ gIn, const float* __restrict__ vis,
+                                                        const float* __restrict__ saved, int64_t P, float eps, int k,
+                                                        float* __restrict__ Wout, ShadeArgs sa) {
+  __shared__ Exp4BwdShared<NB> S;
+  exp_bwd4_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, S);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers for one band count (instantiated per band count in shv_nb.hip).
+
+template <int NB, bool SHADE>
+hipError_t exp_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis, float* saved,
+                      const float* nrm, const float* alb, const float* M, float* rad, uint32_t flags, hipStream_t st) {
+  const ShadeArgs sa{nrm, alb, M, rad, nullptr, nullptr, nullptr};
+  if (exp_four_waves(P, flags)) {
+    k_exp_fwd4<NB, SHADE><<<(unsigned)((P + 63) / 64), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, k, vis, saved, sa);
+  } else {
+    k_exp_fwd<NB, SHADE><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, k, vis, saved, sa);
+  }
+  return hipGetLastError();
+}
+
+template <int NB, bool SHADE>
+hipError_t exp_bwd_nb(const float* gIn, const float* vis, const float* saved, int64_t P, float eps, int k, float* W,
+                      const float* nrm, const float* alb, const float* M, float* gN, float* gA, float* Lpart,
+                      uint32_t flags, hipStream_t st) {
+  const ShadeArgs sa{nrm, alb, M, nullptr, gN, gA, Lpart};
+  if (exp_four_waves(P, flags)) {
+    k_exp_bwd4<NB, SHADE><<<(unsigned)((P + 63) / 64), SHV_BLOCK, 0, st>>>(gIn, vis, saved, P, eps, k, W, sa);
+  } else {
+    k_exp_bwd<NB, SHADE><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(gIn, vis, saved, P, eps, k, W, sa);
+  }
+  return hipGetLastError();
+}
+
+// Persistent batched phases of the fused render path: scenes with NB bands
+// whose exponential uses the four-wave layout (FOUR) or the one-wave layout.
+template <int NB, bool FOUR>
+__global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_fwd(const char* __restrict__ table) {
+  __shared__ Exp4FwdShared<NB> sh;
+  const BatchView v(table);
+  const int64_t total = v.h->total_exp[FOUR][NB];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const BatchScene& S = v.scene_of_exp(FOUR, NB, item);
+    const int64_t bx = item - S.off_exp;
+    const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
+    if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
+    else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx);
+    __syncthreads();
+  }
+}
+
+template <int NB, bool FOUR>
+__global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_bwd(const char* __restrict__ table) {
+  __shared__ Exp4BwdShared<NB> sh;
+  const BatchView v(table);
+  const int64_t total = v.h->total_exp[FOUR][NB];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const BatchScene& S = v.scene_of_exp(FOUR, NB, item);
+    const int64_t bx = item - S.off_exp;
+    const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
+    if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
+    else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT);
+    __syncthreads();
+  }
+}
+
+template <int NB>
+hipError_t batch_exp_fwd_nb(const void* table, bool four, hipStream_t st) {
+  if (four) k_batch_exp_fwd<NB, true><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+  else k_batch_exp_fwd<NB, false><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+  return hipGetLastError();
+}
+
+template <int NB>
+hipError_t batch_exp_bwd_nb(const void* table, bool four, hipStream_t st) {
+  if (four) k_batch_exp_bwd<NB, true><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+  else k_batch_exp_bwd<NB, false><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+  return hipGetLastError();
+}
+
+}  // namespace shv

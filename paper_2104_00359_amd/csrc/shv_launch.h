@@ -18,12 +18,13 @@ struct Split {
 Split choose_split(int64_t P, int64_t S);
 
 int64_t point_blocks(int64_t P);  // ceil(P / 256)
-int shade_blocks(int64_t P);      // grid of the shading adjoint
+int64_t pair_blocks(int64_t P);   // ceil(P / 64): pair-kernel blocks (rows of the sphere partials)
 
+// light / M: when M is non-NULL the first block also writes M(L) (fused render path).
 hipError_t launch_pair_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, Split sp,
-                           float* Fpart, hipStream_t st);
+                           float* Fpart, const float* light, float* M, hipStream_t st);
 hipError_t launch_exp_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k,
-                          float* vis, float* saved, hipStream_t st);
+                          float* vis, float* saved, uint32_t flags, hipStream_t st);
 hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st);
 hipError_t launch_shade_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
                             int64_t P, float* rad, hipStream_t st);
@@ -32,11 +33,63 @@ hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const flo
                             hipStream_t st);
 hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st);
 hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P,
-                          float eps, int k, float* W, hipStream_t st);
+                          float eps, int k, float* W, uint32_t flags, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,
                            Split sp, float* gp_part, float* gs_part, hipStream_t st);
 // Zero n floats with a plain kernel (safe inside captured graphs).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
 hipError_t launch_sum_chunks(const float* part, int nchunks, int64_t len, float* out, hipStream_t st);
+// Receiver-chunk sums, sphere-gradient and lighting-gradient column reductions in one launch
+// (each output may be NULL to skip it).
+hipError_t launch_finalize(const float* gp_part, int nchunks, int64_t P, float* grad_points, const float* gs_part,
+                           int rows_s, int64_t S, float* grad_spheres, const float* l_part, int rows_l, int N,
+                           float* grad_light, hipStream_t st);
+// Exponential with the shading step (forward) or the shading adjoint (backward) fused in.
+hipError_t launch_render_exp_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis,
+                                 float* saved, const float* nrm, const float* alb, const float* M, float* rad,
+                                 uint32_t flags, hipStream_t st);
+hipError_t launch_render_exp_bwd(int nb, const float* gB, const float* vis, const float* saved, int64_t P, float eps,
+                                 int k, float* W, const float* nrm, const float* alb, const float* M, float* gN,
+                                 float* gA, float* Lpart, uint32_t flags, hipStream_t st);
+
+// Persistent batched phases; `table` is the device copy of a batch table.
+// phase: 0 pair forward, 1 exponential + shading forward, 2 their adjoint,
+// 3 pair adjoint; one launch covers every scene with nb bands (and, for the
+// exponential phases, with the given layout).
+hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, hipStream_t st);
+hipError_t launch_batch_finalize(const void* table, hipStream_t st);
+
+// Per-band-count launchers (defined in the per-band-count translation units).
+template <int NB>
+hipError_t pair_fwd_nb(const float* pts, int64_t P, const float* sph, int S, Split sp, float* Fpart,
+                       const float* light, float* M, hipStream_t st);
+template <int NB>
+hipError_t pair_bwd_nb(const float* W, const float* pts, int64_t P, const float* sph, int S, Split sp, float* gp_part,
+                       float* gs_part, hipStream_t st);
+template <int NB, bool SHADE>
+hipError_t exp_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis, float* saved,
+                      const float* nrm, const float* alb, const float* M, float* rad, uint32_t flags, hipStream_t st);
+template <int NB, bool SHADE>
+hipError_t exp_bwd_nb(const float* gIn, const float* vis, const float* saved, int64_t P, float eps, int k, float* W,
+                      const float* nrm, const float* alb, const float* M, float* gN, float* gA, float* Lpart,
+                      uint32_t flags, hipStream_t st);
+template <int NB>
+hipError_t build_M_nb(const float* light, float* M, hipStream_t st);
+template <int NB>
+hipError_t shade_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int64_t P, float* rad,
+                        hipStream_t st);
+template <int NB>
+hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
+                        int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
+template <int NB>
+hipError_t batch_pair_fwd_nb(const void* table, hipStream_t st);
+template <int NB>
+hipError_t batch_pair_bwd_nb(const void* table, hipStream_t st);
+template <int NB>
+hipError_t batch_exp_fwd_nb(const void* table, bool four, hipStream_t st);
+template <int NB>
+hipError_t batch_exp_bwd_nb(const void* table, bool four, hipStream_t st);
+
+bool exp_four_waves(int64_t P, uint32_t flags);
 
 }  // namespace shv

@@ -53,6 +53,9 @@ def _f32(x: torch.Tensor) -> torch.Tensor:
 
 
 class ShadeSH(torch.autograd.Function):
+    """Radiance with soft shadows through the fused render entry points
+    (sh_render_forward / sh_render_backward)."""
+
     @staticmethod
     def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings):
         dev = points.device
@@ -66,38 +69,31 @@ class ShadeSH(torch.autograd.Function):
         if L.numel() != N:
             raise ValueError(f"light has {L.numel()} coefficients, expected {N} for {n_bands} bands")
         vis = torch.empty(N, P, dtype=torch.float32, device=dev)
-        saved = torch.empty(_lib.shv_saved_floats(P, prm), dtype=torch.float32, device=dev)
+        saved = torch.empty(_lib.shv_render_saved_floats(P, prm), dtype=torch.float32, device=dev)
         rad = torch.empty(P, dtype=torch.float32, device=dev)
-        nbytes = _lib.shv_workspace_bytes(P, S, prm)
-        ws = workspace(dev, nbytes)
-        st = _stream()
-        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), st)
-        _lib.sh_shade(vis, nrm, alb, L, P, prm, rad, ws, ws.numel(), st)
-        ctx.save_for_backward(pts, nrm, alb, sph, L, vis, saved)
+        ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
+        _lib.sh_render_forward(pts, nrm, alb, sph, L, P, S, prm, vis, rad, saved, ws, ws.numel(), _stream())
+        ctx.save_for_backward(pts, nrm, alb, sph, vis, saved)
         ctx.cfg = (n_bands, eps, n_squarings)
         return rad
 
     @staticmethod
     def backward(ctx, grad_rad):
-        pts, nrm, alb, sph, L, vis, saved = ctx.saved_tensors
+        pts, nrm, alb, sph, vis, saved = ctx.saved_tensors
         n_bands, eps, n_squarings = ctx.cfg
         prm = _lib.params(n_bands, eps, n_squarings)
         dev = pts.device
         P, S, N = pts.shape[1], sph.shape[0], n_bands * n_bands
         gB = _f32(grad_rad)
         need_p, need_n, need_a, need_s, need_l = ctx.needs_input_grad[:5]
-        gV = torch.empty(N, P, dtype=torch.float32, device=dev)
+        gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
         gN = torch.empty(3, P, dtype=torch.float32, device=dev) if need_n else None
         gA = torch.empty(P, dtype=torch.float32, device=dev) if need_a else None
-        gL = torch.empty(N, dtype=torch.float32, device=dev) if need_l else None
-        gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
         gS = torch.empty(S, 4, dtype=torch.float32, device=dev) if need_s else None
-        nbytes = _lib.shv_workspace_bytes(P, S, prm)
-        ws = workspace(dev, nbytes)
-        st = _stream()
-        _lib.sh_shade_backward(gB, vis, nrm, alb, L, P, prm, gV, gN, gA, gL, ws, ws.numel(), st)
-        if need_p or need_s:
-            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), st)
+        gL = torch.empty(N, dtype=torch.float32, device=dev) if need_l else None
+        ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
+        _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, gP, gN, gA, gS, gL, ws, ws.numel(),
+                                _stream())
         return (gP.t() if gP is not None else None, gN.t() if gN is not None else None, gA, gS, gL,
                 None, None, None)
 

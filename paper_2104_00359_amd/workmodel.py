@@ -93,7 +93,7 @@ def shade_bwd_flops(n: int) -> int:
     mv = c["supp"] * (2 * N + 3)
     vbar = N * (2 * c["supp"] + 1)
     nbar = 10 * N + 15
-    lbar = N + c["vh_pairs"] + 2 * c["vh"]
+    lbar = c["supp"] + 2 * N * c["supp"]        # w H, then the Q GEMM (contraction with C is per call)
     return h + mv + vbar + nbar + lbar
 
 
@@ -121,4 +121,8 @@ def kernel_work(name: str, n: int, k: int, P: int, S: int):
         return shade_fwd_flops(n) * P, P
     if name == "shade_bwd":
         return shade_bwd_flops(n) * P, P
+    if name == "exp_shade_fwd":
+        return (exp_fwd_flops(n, k) + shade_fwd_flops(n)) * P, P
+    if name == "exp_shade_bwd":
+        return (exp_bwd_flops(n, k) + shade_bwd_flops(n)) * P, P
     return None, None

@@ -19,7 +19,7 @@ def to_dev(a, dev="cuda"):
     return torch.as_tensor(np.ascontiguousarray(a)).to(dev)
 
 
-def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True):
+def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True, flags=0):
     """Forward (+ backward when grad_B is given) through the C ABI.
     Returns numpy arrays: V [P, N], B [P], and the gradients."""
     L = lib()
@@ -30,7 +30,7 @@ def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True):
     N = n * n
     P = scene["points"].shape[0]
     S = scene["spheres"].shape[0]
-    prm = L.params(n, eps, k)
+    prm = L.params(n, eps, k, flags)
     pts = to_dev(scene["points"].T)
     nrm = to_dev(scene["normals"].T)
     alb = to_dev(scene["albedo"])
@@ -59,6 +59,52 @@ def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True):
                    grad_albedo=gA.cpu().numpy(), grad_light=gL.cpu().numpy(),
                    grad_spheres=gS[:S].cpu().numpy())
     torch.cuda.synchronize()
+    return out
+
+
+def run_render(scene, grad_B, eps=3.0, k=4, flags=0, null=()):
+    """Fused path (sh_render_forward / sh_render_backward) through the C ABI;
+    outputs named in ``null`` are passed as NULL."""
+    L = lib()
+    from paper_2104_00359_amd import ops
+    dev = torch.device("cuda", 0)
+    ops.ensure_init(dev)
+    n = int(scene["n_bands"])
+    N = n * n
+    P = scene["points"].shape[0]
+    S = scene["spheres"].shape[0]
+    prm = L.params(n, eps, k, flags)
+    pts = to_dev(scene["points"].T)
+    nrm = to_dev(scene["normals"].T)
+    alb = to_dev(scene["albedo"])
+    sph = to_dev(scene["spheres"]).reshape(S, 4)
+    lig = to_dev(scene["light"])
+    vis = torch.empty(N, P, device=dev)
+    saved = torch.empty(max(L.shv_render_saved_floats(P, prm), 1), device=dev)
+    rad = torch.empty(P, device=dev)
+    nb = L.shv_workspace_bytes(P, S, prm)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    L.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, ws, nb, st)
+    out = {"V": vis.t().cpu().numpy(), "B": rad.cpu().numpy()}
+    gB = to_dev(np.asarray(grad_B, np.float32))
+    g = {"grad_points": torch.empty(3, P, device=dev), "grad_normals": torch.empty(3, P, device=dev),
+         "grad_albedo": torch.empty(P, device=dev), "grad_spheres": torch.empty(max(S, 1), 4, device=dev),
+         "grad_light": torch.empty(N, device=dev)}
+    a = {k2: (None if k2 in null else v) for k2, v in g.items()}
+    L.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, a["grad_points"], a["grad_normals"],
+                         a["grad_albedo"], a["grad_spheres"], a["grad_light"], ws, nb, st)
+    torch.cuda.synchronize()
+    if "grad_points" not in null:
+        out["grad_points"] = g["grad_points"].t().cpu().numpy()
+    if "grad_normals" not in null:
+        out["grad_normals"] = g["grad_normals"].t().cpu().numpy()
+    if "grad_albedo" not in null:
+        out["grad_albedo"] = g["grad_albedo"].cpu().numpy()
+    if "grad_spheres" not in null:
+        out["grad_spheres"] = g["grad_spheres"][:S].cpu().numpy()
+    if "grad_light" not in null:
+        out["grad_light"] = g["grad_light"].cpu().numpy()
     return out
 
 

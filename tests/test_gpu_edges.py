@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import scenegen
-from gpu_helpers import lib, rel_l2, rel_max, run_hip, run_oracle, to_dev
+from gpu_helpers import lib, rel_l2, rel_max, run_hip, run_oracle, run_render, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +63,41 @@ def test_bitwise_determinism():
     b = run_hip(sc, w)
     for key in a:
         assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("n,k", [(8, 4), (6, 0), (3, 2)])
+def test_exponential_variants_are_bitwise_identical(n, k):
+    """One receiver per lane vs each receiver spread over four waves."""
+    sc = scenegen.scene_random_shell(21, 3000, 40, n)
+    w = sc["grad_radiance"]
+    a = run_hip(sc, w, k=k, flags=1)
+    b = run_hip(sc, w, k=k, flags=2)
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("n,k,P,flags", [(8, 4, 3000, 0), (8, 4, 3000, 1), (6, 0, 777, 2), (4, 3, 70000, 0),
+                                          (5, 2, 130, 1)])
+def test_render_path_matches_separate_entry_points(n, k, P, flags):
+    """sh_render_forward / sh_render_backward are bit-identical to the four
+    separate entry points, in both exponential layouts."""
+    sc = scenegen.scene_random_shell(31 + n, P, 37, n)
+    w = sc["grad_radiance"]
+    a = run_hip(sc, w, k=k, flags=flags)
+    b = run_render(sc, w, k=k, flags=flags)
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_render_path_null_outputs():
+    sc = scenegen.scene_random_shell(41, 900, 12, 6)
+    w = sc["grad_radiance"]
+    full = run_render(sc, w)
+    part = run_render(sc, w, null=("grad_points", "grad_normals", "grad_light"))
+    for key in ("grad_albedo", "grad_spheres", "V", "B"):
+        assert np.array_equal(full[key], part[key]), key
+    only_light = run_render(sc, w, null=("grad_points", "grad_normals", "grad_albedo", "grad_spheres"))
+    assert np.array_equal(full["grad_light"], only_light["grad_light"])
 
 
 def test_zero_receivers_is_noop_and_zeroes_reductions():
