@@ -157,13 +157,15 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
                               hipStream_t stream);
 
 /* Batched render path: many independent scenes (each with its own P, S,
- * n_bands and k) forward and backward in a few persistent launches, every
- * scene bit-identical to single-scene sh_render_forward / sh_render_backward.
+ * n_bands and k) forward and backward in one launch per phase and group of
+ * scenes sharing a band count (and exponential layout), every scene
+ * bit-identical to single-scene sh_render_forward / sh_render_backward.
  *
  * Scene description (host structure; every pointer is a device pointer as in
  * the single-scene calls).  ws must hold shv_workspace_bytes(P, S, &params)
  * bytes and saved shv_render_saved_floats(P, &params) floats; grad_* may be
- * NULL; grad_radiance is read by the backward only. */
+ * NULL; grad_radiance is read by the backward only, which skips a scene whose
+ * grad_radiance is NULL (its gradient outputs are left unwritten). */
 typedef struct shv_scene {
   const float* points;        /* [3][P] */
   const float* normals;       /* [3][P] */
@@ -192,28 +194,38 @@ size_t shv_batch_table_bytes(int32_t n_scenes);
 /* Host-side: validates every scene (errors name the scene index) and packs
  * the work table into `table` (HOST memory, table_bytes bytes).  The caller
  * copies the table verbatim to device memory and passes the device copy to
- * the batched calls; the device copy may be rewritten between calls (a
- * captured graph of the batched calls can be replayed for new batches, since
- * the launch grids do not depend on the table's contents). */
+ * the batched calls, with the block counts from shv_batch_table_grid(). */
 shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void* table,
                                  size_t table_bytes);
 
-/* Launch mask of a built (host) table: bit n set when some scene with n bands
- * uses the four-wave exponential layout, bit 16 + n when one uses the
- * one-wave layout (the single-scene calls pick the layout from P and flags). */
-uint32_t shv_batch_table_launch_mask(const void* table_host);
+/* Block counts of the batched launches.  pair[n]: the pair launches of the
+ * scenes with n bands; exp[0][n] / exp[1][n]: the exponential launches of
+ * those scenes using the one-wave / four-wave layout (the layout each scene's
+ * single-scene call would pick from P and flags); finalize: the closing
+ * reductions of all scenes.  Index 0 is unused and must be 0.  A group with
+ * 0 blocks is not launched. */
+typedef struct shv_batch_grid {
+  int64_t pair[SHV_MAX_BANDS_API + 1];
+  int64_t exp[2][SHV_MAX_BANDS_API + 1];
+  int64_t finalize;
+} shv_batch_grid;
 
-/* Forward of every scene of the batch: persistent launches, one per band
- * count for the pair stage and one per (layout, band count) for the
- * exponential and shading stage, as selected by launch_mask (pass the table's
- * mask or a superset of it: launches for absent groups find no work).  The
- * table itself stays on the device. */
-shv_status sh_render_batched_forward(const void* table_device, uint32_t launch_mask, hipStream_t stream);
+/* The exact block counts of a built (host) table.  Any larger counts work
+ * too (blocks past a group's work exit at once): a captured graph of the
+ * batched calls can be replayed for a new table written into the same device
+ * buffer when each of its counts is at most the captured one. */
+shv_status shv_batch_table_grid(const void* table_host, shv_batch_grid* grid);
+
+/* Forward of every scene of the batch: one launch per band count for the
+ * pair stage and one per (layout, band count) for the exponential and
+ * shading stage, with the block counts of `grid` (host memory).  The table
+ * itself stays on the device. */
+shv_status sh_render_batched_forward(const void* table_device, const shv_batch_grid* grid, hipStream_t stream);
 
 /* Backward of every scene of the batch (the same launch groups in reverse,
  * then one launch for the closing reductions of all scenes); reads each
  * scene's grad_radiance, vis and saved. */
-shv_status sh_render_batched_backward(const void* table_device, uint32_t launch_mask, hipStream_t stream);
+shv_status sh_render_batched_backward(const void* table_device, const shv_batch_grid* grid, hipStream_t stream);
 
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream.  shv_profile_enable(1) starts a new collection (at most

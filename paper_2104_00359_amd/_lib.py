@@ -32,7 +32,7 @@ EXPORTED = [
     "shv_init", "shv_status_string", "shv_last_error", "shv_saved_floats", "shv_workspace_bytes",
     "sh_visibility_forward", "sh_shade", "sh_shade_backward", "sh_visibility_backward",
     "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
-    "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_launch_mask",
+    "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
     "sh_render_batched_forward", "sh_render_batched_backward",
     "shv_profile_enable", "shv_profile_report",
 ]
@@ -52,6 +52,11 @@ class shv_scene(ctypes.Structure):
         "points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved",
         "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light", "ws")] + [
         ("ws_bytes", ctypes.c_size_t), ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("params", shv_params)]
+
+
+class shv_batch_grid(ctypes.Structure):
+    """Block counts of the batched launches (see the C header)."""
+    _fields_ = [("pair", ctypes.c_int64 * 9), ("exp", (ctypes.c_int64 * 9) * 2), ("finalize", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -75,9 +80,9 @@ _sig = {
                                             _SZ, _P]),
     "shv_batch_table_bytes": (_SZ, [ctypes.c_int32]),
     "shv_batch_table_build": (ctypes.c_int32, [ctypes.POINTER(shv_scene), ctypes.c_int32, _P, _SZ]),
-    "shv_batch_table_launch_mask": (ctypes.c_uint32, [_P]),
-    "sh_render_batched_forward": (ctypes.c_int32, [_P, ctypes.c_uint32, _P]),
-    "sh_render_batched_backward": (ctypes.c_int32, [_P, ctypes.c_uint32, _P]),
+    "shv_batch_table_grid": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid)]),
+    "sh_render_batched_forward": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid), _P]),
+    "sh_render_batched_backward": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid), _P]),
     "shv_profile_enable": (ctypes.c_int32, [ctypes.c_int, ctypes.c_int32]),
     "shv_profile_report": (_I64, [ctypes.c_char_p, _I64]),
 }
@@ -192,17 +197,20 @@ def shv_batch_table_build(scenes, table_host) -> None:
     _check(_lib.shv_batch_table_build(arr, n, addr, size), "shv_batch_table_build")
 
 
-def shv_batch_table_launch_mask(table_host) -> int:
+def shv_batch_table_grid(table_host) -> shv_batch_grid:
     addr = table_host.data_ptr() if hasattr(table_host, "data_ptr") else ctypes.addressof(table_host)
-    return int(_lib.shv_batch_table_launch_mask(addr))
+    g = shv_batch_grid()
+    _check(_lib.shv_batch_table_grid(addr, ctypes.byref(g)), "shv_batch_table_grid")
+    return g
 
 
-def sh_render_batched_forward(table_device, launch_mask, stream):
-    _check(_lib.sh_render_batched_forward(ptr(table_device), int(launch_mask), stream), "sh_render_batched_forward")
+def sh_render_batched_forward(table_device, grid, stream):
+    _check(_lib.sh_render_batched_forward(ptr(table_device), ctypes.byref(grid), stream),
+           "sh_render_batched_forward")
 
 
-def sh_render_batched_backward(table_device, launch_mask, stream):
-    _check(_lib.sh_render_batched_backward(ptr(table_device), int(launch_mask), stream),
+def sh_render_batched_backward(table_device, grid, stream):
+    _check(_lib.sh_render_batched_backward(ptr(table_device), ctypes.byref(grid), stream),
            "sh_render_batched_backward")
 
 

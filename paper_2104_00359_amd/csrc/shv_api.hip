@@ -571,7 +571,6 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     tf += b.n_fin;
     h.grp_count[nb] += 1;
     h.egrp_count[lay][nb] += 1;
-    if (b.n_exp > 0) h.launch_mask |= 1u << (nb + (lay ? 0 : 16));
     out[i] = b;
   }
   h.total_fin = tf;
@@ -592,50 +591,73 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
   return SHV_OK;
 }
 
-uint32_t shv_batch_table_launch_mask(const void* table) {
-  return table ? ((const shv::BatchHeader*)table)->launch_mask : 0u;
+shv_status shv_batch_table_grid(const void* table, shv_batch_grid* grid) {
+  if (!table) return set_error(SHV_ERR_INVALID_ARG, "table is NULL");
+  if (!grid) return set_error(SHV_ERR_INVALID_ARG, "grid is NULL");
+  const shv::BatchHeader& h = *(const shv::BatchHeader*)table;
+  shv_batch_grid g{};
+  for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
+    g.pair[nb] = h.total_pair[nb];
+    g.exp[0][nb] = h.total_exp[0][nb];
+    g.exp[1][nb] = h.total_exp[1][nb];
+  }
+  g.finalize = h.total_fin;
+  *grid = g;
+  return SHV_OK;
 }
 
-// Launches of one phase for every (layout, band count) group in the mask:
-// bit nb = four-wave exponential layout, bit 16 + nb = one-wave layout.
-static shv_status batched_phase(int phase, uint32_t mask, const void* table, hipStream_t stream) {
+static shv_status check_grid(const shv_batch_grid* g) {
+  SHV_TRY(need(g, "grid"));
+  const int64_t lim = 0x7fffffff;
+  auto bad = [&](int64_t x) { return x < 0 || x > lim; };
+  if (g->pair[0] || g->exp[0][0] || g->exp[1][0])
+    return set_error(SHV_ERR_INVALID_ARG, "grid entries for 0 bands must be 0");
+  for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb)
+    if (bad(g->pair[nb]) || bad(g->exp[0][nb]) || bad(g->exp[1][nb]))
+      return set_error(SHV_ERR_INVALID_ARG, "grid entry for %d bands outside [0, 2^31)", nb);
+  if (bad(g->finalize)) return set_error(SHV_ERR_INVALID_ARG, "finalize grid outside [0, 2^31)");
+  return SHV_OK;
+}
+
+// Launches of one phase for every group with a non-empty grid.
+static shv_status batched_phase(int phase, const shv_batch_grid* g, const void* table, hipStream_t stream) {
   static const char* names[4] = {"batch_pair_fwd", "batch_exp_shade_fwd", "batch_exp_shade_bwd", "batch_pair_bwd"};
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
-    const bool four = mask & (1u << nb), one = mask & (1u << (nb + 16));
     if (phase == 0 || phase == 3) {
-      if (four || one)
-        SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, false, table, stream); }));
+      const int64_t blocks = g->pair[nb];
+      if (blocks > 0)
+        SHV_TRY(launch(names[phase], stream,
+                       [&] { return shv::launch_batch_nb(nb, phase, false, table, blocks, stream); }));
       continue;
     }
-    if (four)
-      SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, true, table, stream); }));
-    if (one)
-      SHV_TRY(launch(names[phase], stream, [&] { return shv::launch_batch_nb(nb, phase, false, table, stream); }));
+    for (int lay = 1; lay >= 0; --lay) {
+      const int64_t blocks = g->exp[lay][nb];
+      if (blocks > 0)
+        SHV_TRY(launch(names[phase], stream,
+                       [&] { return shv::launch_batch_nb(nb, phase, lay == 1, table, blocks, stream); }));
+    }
   }
   return SHV_OK;
 }
 
-static shv_status check_mask(uint32_t mask) {
-  if (mask & ~0x01FE01FEu) return set_error(SHV_ERR_INVALID_ARG, "launch mask 0x%x has unknown bits", mask);
+shv_status sh_render_batched_forward(const void* table, const shv_batch_grid* grid, hipStream_t stream) {
+  SHV_TRY(check_device());
+  SHV_TRY(need(table, "table"));
+  SHV_TRY(check_grid(grid));
+  SHV_TRY(batched_phase(0, grid, table, stream));
+  SHV_TRY(batched_phase(1, grid, table, stream));
   return SHV_OK;
 }
 
-shv_status sh_render_batched_forward(const void* table, uint32_t launch_mask, hipStream_t stream) {
+shv_status sh_render_batched_backward(const void* table, const shv_batch_grid* grid, hipStream_t stream) {
   SHV_TRY(check_device());
   SHV_TRY(need(table, "table"));
-  SHV_TRY(check_mask(launch_mask));
-  SHV_TRY(batched_phase(0, launch_mask, table, stream));
-  SHV_TRY(batched_phase(1, launch_mask, table, stream));
-  return SHV_OK;
-}
-
-shv_status sh_render_batched_backward(const void* table, uint32_t launch_mask, hipStream_t stream) {
-  SHV_TRY(check_device());
-  SHV_TRY(need(table, "table"));
-  SHV_TRY(check_mask(launch_mask));
-  SHV_TRY(batched_phase(2, launch_mask, table, stream));
-  SHV_TRY(batched_phase(3, launch_mask, table, stream));
-  SHV_TRY(launch("batch_finalize", stream, [&] { return shv::launch_batch_finalize(table, stream); }));
+  SHV_TRY(check_grid(grid));
+  SHV_TRY(batched_phase(2, grid, table, stream));
+  SHV_TRY(batched_phase(3, grid, table, stream));
+  if (grid->finalize > 0)
+    SHV_TRY(launch("batch_finalize", stream,
+                   [&] { return shv::launch_batch_finalize(table, grid->finalize, stream); }));
   return SHV_OK;
 }
 

@@ -3,11 +3,11 @@
 // The host packs a BatchHeader, one BatchScene record per scene and two index
 // arrays that list the scenes grouped by band count (pair phases) and by
 // exponential layout and band count (exponential phases).  Every phase of a
-// batched forward or backward runs as persistent launches, one per group
-// present, whose blocks walk that group's item space with a fixed stride
-// (item = one block's worth of work of one scene, exactly a block of the
-// single-scene kernel); the closing reductions run as one launch over all
-// scenes.  Scene
+// batched forward or backward runs as one launch per group present, whose
+// blocks cover that group's item space (item = one block's worth of work of
+// one scene, exactly a block of the single-scene kernel; the scene is found by
+// binary search over the group's offsets, and blocks past the end exit); the
+// closing reductions run as one launch over all scenes.  Scene
 // records carry the split decisions of the single-scene entry points, so every
 // scene's results are bit-identical to a single-scene call.
 #pragma once
@@ -60,7 +60,6 @@ struct BatchScene {
 
 struct BatchHeader {
   int32_t n_scenes;
-  uint32_t launch_mask;                          // see shv_batch_table_launch_mask()
   int64_t total_fin;
   int64_t total_pair[SHV_MAX_BANDS_API + 1];     // pair items per band count
   int32_t grp_begin[SHV_MAX_BANDS_API + 1];      // slice of `order` per band count
@@ -70,9 +69,6 @@ struct BatchHeader {
   int32_t egrp_count[2][SHV_MAX_BANDS_API + 1];
 };
 
-enum BatchPhase { kPhasePair = 0, kPhaseExp = 1 };
-
-constexpr int kBatchGrid = 1024;  // persistent blocks per launch
 
 // Layout: header, n scene records, `order` (scene ids grouped by band count),
 // `eorder` (scene ids grouped by exponential layout, then band count).
@@ -104,7 +100,7 @@ struct BatchView {
     return sc[g[lo]];
   }
 
-  __device__ const BatchScene& scene_of(int nb, int64_t item, int) const {
+  __device__ const BatchScene& scene_of(int nb, int64_t item) const {
     return find(order + h->grp_begin[nb], h->grp_count[nb], item, [](const BatchScene& s) { return s.off_pair; });
   }
 
@@ -123,5 +119,41 @@ struct BatchView {
     return sc[lo];
   }
 };
+
+// Pointers read from the table have no known address space, so the compiler
+// would address them with flat instructions and 64-bit per-lane addresses.
+// Every buffer of a scene is global device memory: read each pointer field
+// from the table as a pointer to global memory.
+template <class T>
+__device__ __forceinline__ T* load_global_ptr(T* const& field) {
+  const void* addr = &field;
+  return (T*)*static_cast<T __attribute__((address_space(1)))* const*>(addr);
+}
+
+// Copy of a scene record (a reference into the table) with global pointers.
+__device__ __forceinline__ BatchScene in_global(const BatchScene& s) {
+  BatchScene r = s;
+  r.points = load_global_ptr(s.points);
+  r.normals = load_global_ptr(s.normals);
+  r.albedo = load_global_ptr(s.albedo);
+  r.spheres = load_global_ptr(s.spheres);
+  r.light = load_global_ptr(s.light);
+  r.grad_radiance = load_global_ptr(s.grad_radiance);
+  r.vis = load_global_ptr(s.vis);
+  r.radiance = load_global_ptr(s.radiance);
+  r.saved = load_global_ptr(s.saved);
+  r.grad_points = load_global_ptr(s.grad_points);
+  r.grad_normals = load_global_ptr(s.grad_normals);
+  r.grad_albedo = load_global_ptr(s.grad_albedo);
+  r.grad_spheres = load_global_ptr(s.grad_spheres);
+  r.grad_light = load_global_ptr(s.grad_light);
+  r.Fpart = load_global_ptr(s.Fpart);
+  r.M = load_global_ptr(s.M);
+  r.W = load_global_ptr(s.W);
+  r.gp = load_global_ptr(s.gp);
+  r.gs = load_global_ptr(s.gs);
+  r.lp = load_global_ptr(s.lp);
+  return r;
+}
 
 }  // namespace shv

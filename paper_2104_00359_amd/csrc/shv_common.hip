@@ -148,18 +148,17 @@ hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out,
 __global__ __launch_bounds__(SHV_BLOCK) void k_batch_finalize(const char* __restrict__ table) {
   __shared__ float buf[SHV_BLOCK];
   const BatchView v(table);
-  const int64_t total = v.h->total_fin;
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const BatchScene& S = v.scene_of_fin(item);
-    const int b = (int)(item - S.off_fin);
-    finalize_item(S.gp, S.nchunks, S.P, S.fin_pts ? S.grad_points : nullptr, S.fin_pts, S.gs, (int)S.pair_tiles,
-                  S.fin_cols_s, S.grad_spheres, S.lp, (int)S.pair_tiles, S.fin_cols_l, S.grad_light, b, buf);
-    __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= v.h->total_fin) return;
+  const BatchScene S = in_global(v.scene_of_fin(item));
+  if (!S.grad_radiance) return;  // uniform: scene packed without a cotangent
+  const int b = (int)(item - S.off_fin);
+  finalize_item(S.gp, S.nchunks, S.P, S.fin_pts ? S.grad_points : nullptr, S.fin_pts, S.gs, (int)S.pair_tiles,
+                S.fin_cols_s, S.grad_spheres, S.lp, (int)S.pair_tiles, S.fin_cols_l, S.grad_light, b, buf);
 }
 
-hipError_t launch_batch_finalize(const void* table, hipStream_t st) {
-  k_batch_finalize<<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+hipError_t launch_batch_finalize(const void* table, int64_t blocks, hipStream_t st) {
+  k_batch_finalize<<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
   return hipGetLastError();
 }
 
@@ -251,18 +250,18 @@ hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const flo
 #undef C
 }
 
-hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, hipStream_t st) {
+hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, int64_t blocks, hipStream_t st) {
   switch (phase) {
-#define C(N) batch_pair_fwd_nb<N>(table, st)
+#define C(N) batch_pair_fwd_nb<N>(table, blocks, st)
     case 0: SHV_NB_SWITCH(nb, C)
 #undef C
-#define C(N) batch_exp_fwd_nb<N>(table, four, st)
+#define C(N) batch_exp_fwd_nb<N>(table, four, blocks, st)
     case 1: SHV_NB_SWITCH(nb, C)
 #undef C
-#define C(N) batch_exp_bwd_nb<N>(table, four, st)
+#define C(N) batch_exp_bwd_nb<N>(table, four, blocks, st)
     case 2: SHV_NB_SWITCH(nb, C)
 #undef C
-#define C(N) batch_pair_bwd_nb<N>(table, st)
+#define C(N) batch_pair_bwd_nb<N>(table, blocks, st)
     case 3: SHV_NB_SWITCH(nb, C)
 #undef C
     default: return hipErrorInvalidValue;

@@ -577,49 +577,47 @@ hipError_t exp_bwd_nb(const float* gIn, const float* vis, const float* saved, in
   return hipGetLastError();
 }
 
-// Persistent batched phases of the fused render path: scenes with NB bands
-// whose exponential uses the four-wave layout (FOUR) or the one-wave layout.
+// Batched phases of the fused render path: scenes with NB bands whose
+// exponential uses the four-wave layout (FOUR) or the one-wave layout; one
+// block per item of the group's item space (blocks beyond it exit).
 template <int NB, bool FOUR>
 __global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_fwd(const char* __restrict__ table) {
   __shared__ Exp4FwdShared<NB> sh;
   const BatchView v(table);
-  const int64_t total = v.h->total_exp[FOUR][NB];
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const BatchScene& S = v.scene_of_exp(FOUR, NB, item);
-    const int64_t bx = item - S.off_exp;
-    const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
-    if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
-    else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx);
-    __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= v.h->total_exp[FOUR][NB]) return;
+  const BatchScene S = in_global(v.scene_of_exp(FOUR, NB, item));
+  const int64_t bx = item - S.off_exp;
+  const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
+  if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
+  else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx);
 }
 
 template <int NB, bool FOUR>
-__global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_bwd(const char* __restrict__ table) {
+__global__ __launch_bounds__(SHV_BLOCK, FOUR ? 2 : 1) void k_batch_exp_bwd(const char* __restrict__ table) {
   __shared__ Exp4BwdShared<NB> sh;
   const BatchView v(table);
-  const int64_t total = v.h->total_exp[FOUR][NB];
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const BatchScene& S = v.scene_of_exp(FOUR, NB, item);
-    const int64_t bx = item - S.off_exp;
-    const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
-    if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
-    else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT);
-    __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= v.h->total_exp[FOUR][NB]) return;
+  const BatchScene S = in_global(v.scene_of_exp(FOUR, NB, item));
+  if (!S.grad_radiance) return;  // uniform: scene packed without a cotangent
+  const int64_t bx = item - S.off_exp;
+  const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
+  if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
+  else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT);
 }
 
 template <int NB>
-hipError_t batch_exp_fwd_nb(const void* table, bool four, hipStream_t st) {
-  if (four) k_batch_exp_fwd<NB, true><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
-  else k_batch_exp_fwd<NB, false><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+hipError_t batch_exp_fwd_nb(const void* table, bool four, int64_t blocks, hipStream_t st) {
+  if (four) k_batch_exp_fwd<NB, true><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
+  else k_batch_exp_fwd<NB, false><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
   return hipGetLastError();
 }
 
 template <int NB>
-hipError_t batch_exp_bwd_nb(const void* table, bool four, hipStream_t st) {
-  if (four) k_batch_exp_bwd<NB, true><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
-  else k_batch_exp_bwd<NB, false><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+hipError_t batch_exp_bwd_nb(const void* table, bool four, int64_t blocks, hipStream_t st) {
+  if (four) k_batch_exp_bwd<NB, true><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
+  else k_batch_exp_bwd<NB, false><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
   return hipGetLastError();
 }
 

@@ -52,12 +52,12 @@ hipError_t launch_render_exp_bwd(int nb, const float* gB, const float* vis, cons
                                  int k, float* W, const float* nrm, const float* alb, const float* M, float* gN,
                                  float* gA, float* Lpart, uint32_t flags, hipStream_t st);
 
-// Persistent batched phases; `table` is the device copy of a batch table.
-// phase: 0 pair forward, 1 exponential + shading forward, 2 their adjoint,
-// 3 pair adjoint; one launch covers every scene with nb bands (and, for the
-// exponential phases, with the given layout).
-hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, hipStream_t st);
-hipError_t launch_batch_finalize(const void* table, hipStream_t st);
+// Batched phases; `table` is the device copy of a batch table.  phase: 0 pair
+// forward, 1 exponential + shading forward, 2 their adjoint, 3 pair adjoint;
+// one launch of `blocks` blocks covers every scene with nb bands (and, for
+// the exponential phases, with the given layout).
+hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, int64_t blocks, hipStream_t st);
+hipError_t launch_batch_finalize(const void* table, int64_t blocks, hipStream_t st);
 
 // Per-band-count launchers (defined in the per-band-count translation units).
 template <int NB>
@@ -82,13 +82,13 @@ template <int NB>
 hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
                         int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
 template <int NB>
-hipError_t batch_pair_fwd_nb(const void* table, hipStream_t st);
+hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>
-hipError_t batch_pair_bwd_nb(const void* table, hipStream_t st);
+hipError_t batch_pair_bwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>
-hipError_t batch_exp_fwd_nb(const void* table, bool four, hipStream_t st);
+hipError_t batch_exp_fwd_nb(const void* table, bool four, int64_t blocks, hipStream_t st);
 template <int NB>
-hipError_t batch_exp_bwd_nb(const void* table, bool four, hipStream_t st);
+hipError_t batch_exp_bwd_nb(const void* table, bool four, int64_t blocks, hipStream_t st);
 
 bool exp_four_waves(int64_t P, uint32_t flags);
 

@@ -23,8 +23,8 @@ template hipError_t shade_fwd_nb<SHV_NB>(const float*, const float*, const float
                                          hipStream_t);
 template hipError_t shade_bwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, const float*, int64_t,
                                          float*, float*, float*, float*, hipStream_t);
-template hipError_t batch_pair_fwd_nb<SHV_NB>(const void*, hipStream_t);
-template hipError_t batch_pair_bwd_nb<SHV_NB>(const void*, hipStream_t);
+template hipError_t batch_pair_fwd_nb<SHV_NB>(const void*, int64_t, hipStream_t);
+template hipError_t batch_pair_bwd_nb<SHV_NB>(const void*, int64_t, hipStream_t);
 #elif SHV_PART == 1
 template hipError_t exp_fwd_nb<SHV_NB, false>(const float*, int, int64_t, float, int, float*, float*, const float*,
                                               const float*, const float*, float*, uint32_t, hipStream_t);
@@ -39,9 +39,9 @@ template hipError_t exp_bwd_nb<SHV_NB, true>(const float*, const float*, const f
                                              const float*, const float*, const float*, float*, float*, float*,
                                              uint32_t, hipStream_t);
 #elif SHV_PART == 4
-template hipError_t batch_exp_fwd_nb<SHV_NB>(const void*, bool, hipStream_t);
+template hipError_t batch_exp_fwd_nb<SHV_NB>(const void*, bool, int64_t, hipStream_t);
 #elif SHV_PART == 5
-template hipError_t batch_exp_bwd_nb<SHV_NB>(const void*, bool, hipStream_t);
+template hipError_t batch_exp_bwd_nb<SHV_NB>(const void*, bool, int64_t, hipStream_t);
 #endif
 
 }  // namespace shv

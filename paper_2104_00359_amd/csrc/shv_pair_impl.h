@@ -292,49 +292,45 @@ hipError_t pair_bwd_nb(const float* W, const float* pts, int64_t P, const float*
   return hipGetLastError();
 }
 
-// Persistent batched phases over the scenes with NB bands.
+// Batched pair phases over the scenes with NB bands, one block per item.
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_fwd(const char* __restrict__ table) {
   __shared__ PairFwdShared<NB> sh;
   const BatchView v(table);
-  const int64_t total = v.h->total_pair[NB];
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const BatchScene& S = v.scene_of(NB, item, kPhasePair);
-    const int64_t local = item - S.off_pair;
-    const int64_t bx = local % S.pair_tiles;
-    const int by = (int)(local / S.pair_tiles);
-    pair_fwd_item<NB>(S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.Fpart, S.light,
-                      S.M, bx, by, S.pair_tiles, sh);
-    __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= v.h->total_pair[NB]) return;
+  const BatchScene S = in_global(v.scene_of(NB, item));
+  const int64_t local = item - S.off_pair;
+  const int64_t bx = local % S.pair_tiles;
+  const int by = (int)(local / S.pair_tiles);
+  pair_fwd_item<NB>(S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.Fpart, S.light,
+                    S.M, bx, by, S.pair_tiles, sh);
 }
 
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_bwd(const char* __restrict__ table) {
   __shared__ PairBwdShared sh;
   const BatchView v(table);
-  const int64_t total = v.h->total_pair[NB];
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const BatchScene& S = v.scene_of(NB, item, kPhasePair);
-    if (!S.grad_points && !S.grad_spheres) continue;  // uniform: no geometry gradients wanted
-    const int64_t local = item - S.off_pair;
-    const int64_t bx = local % S.pair_tiles;
-    const int by = (int)(local / S.pair_tiles);
-    pair_bwd_item<NB>(S.W, S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.gp,
-                      reinterpret_cast<float4*>(S.gs), bx, by, sh);
-    __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= v.h->total_pair[NB]) return;
+  const BatchScene S = in_global(v.scene_of(NB, item));
+  if (!S.grad_radiance || (!S.grad_points && !S.grad_spheres)) return;  // uniform: nothing to do
+  const int64_t local = item - S.off_pair;
+  const int64_t bx = local % S.pair_tiles;
+  const int by = (int)(local / S.pair_tiles);
+  pair_bwd_item<NB>(S.W, S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.gp,
+                    reinterpret_cast<float4*>(S.gs), bx, by, sh);
 }
 
 template <int NB>
-hipError_t batch_pair_fwd_nb(const void* table, hipStream_t st) {
-  k_batch_pair_fwd<NB><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st) {
+  k_batch_pair_fwd<NB><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
   return hipGetLastError();
 }
 
 template <int NB>
-hipError_t batch_pair_bwd_nb(const void* table, hipStream_t st) {
-  k_batch_pair_bwd<NB><<<kBatchGrid, SHV_BLOCK, 0, st>>>((const char*)table);
+hipError_t batch_pair_bwd_nb(const void* table, int64_t blocks, hipStream_t st) {
+  k_batch_pair_bwd<NB><<<(unsigned)blocks, SHV_BLOCK, 0, st>>>((const char*)table);
   return hipGetLastError();
 }
 

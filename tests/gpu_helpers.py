@@ -131,3 +131,39 @@ def rel_l2(a, b):
     b = np.asarray(b, np.float64)
     den = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def run_batched(scenes, cfgs=None, eps=3.0, graph_replays=0):
+    """Every scene through one RenderBatch (batched forward then backward).
+    ``cfgs[i]`` may set k, flags and null (outputs passed as NULL) per scene;
+    a scene without "grad_radiance" is packed without a cotangent.  Returns
+    one dict per scene in the format of run_render."""
+    from paper_2104_00359_amd import batch, ops
+    dev = torch.device("cuda", 0)
+    ops.ensure_init(dev)
+    cfgs = cfgs or [{} for _ in scenes]
+    bufs = []
+    for sc, c in zip(scenes, cfgs):
+        grads = tuple(g for g in batch.GRAD_NAMES if g not in c.get("null", ()))
+        bufs.append(batch.scene_buffers(sc, dev, eps=eps, n_squarings=c.get("k", 4), flags=c.get("flags", 0),
+                                        grads=grads))
+    rb = batch.RenderBatch(bufs, dev)
+    rb.forward()
+    rb.backward()
+    torch.cuda.synchronize()
+    return [collect(b) for b in bufs]
+
+
+def collect(b):
+    """Host copies of a SceneBuffers' outputs (format of run_render)."""
+    o = b.out
+    out = {"V": o["vis"].t().cpu().numpy(), "B": o["radiance"].cpu().numpy()}
+    for g in b.grads:
+        t = o[g]
+        if g in ("grad_points", "grad_normals"):
+            out[g] = t.t().cpu().numpy()
+        elif g == "grad_spheres":
+            out[g] = t[:b.S].cpu().numpy()
+        else:
+            out[g] = t.cpu().numpy()
+    return out

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -74,3 +75,58 @@ def test_invalid_parameters_rejected_before_any_device_call(L):
         assert f(None, 10, None, 0, ctypes.byref(flags), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
     g = L.raw("sh_shade")
     assert g(None, None, None, None, 5, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+
+
+def _fake_scene(L, P, S, n, k=4, flags=0, base=1 << 40):
+    """A scene record with distinct, aligned fake device addresses (the table
+    is packed on the host; nothing is dereferenced)."""
+    r = L.shv_scene()
+    addr = [base]
+
+    def nxt():
+        addr[0] += 1 << 24
+        return addr[0]
+    for name in ("points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved",
+                 "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light", "ws"):
+        setattr(r, name, nxt())
+    prm = L.params(n, 3.0, k, flags)
+    r.ws_bytes = L.shv_workspace_bytes(P, S, prm)
+    r.P, r.S, r.params = P, S, prm
+    return r
+
+
+def test_batch_table_packing_and_grid(L):
+    """Host-side packing: block counts per group follow the single-scene
+    launch shapes (exponential: 64 receivers per block in the four-wave
+    layout, 256 in the one-wave layout, picked by P and flags)."""
+    scenes = [_fake_scene(L, 3000, 40, 8), _fake_scene(L, 70000, 20, 4), _fake_scene(L, 777, 37, 8),
+              _fake_scene(L, 0, 5, 5), _fake_scene(L, 5000, 100, 8, flags=L.SHV_FLAG_EXP_ONE_WAVE)]
+    n = len(scenes)
+    buf = (ctypes.c_uint8 * L.shv_batch_table_bytes(n))()
+    L.shv_batch_table_build(scenes, buf)
+    g = L.shv_batch_table_grid(buf)
+    exp_four = np.ctypeslib.as_array(g.exp)[1]
+    exp_one = np.ctypeslib.as_array(g.exp)[0]
+    assert exp_four[8] == (3000 + 63) // 64 + (777 + 63) // 64
+    assert exp_one[8] == (5000 + 255) // 256
+    assert exp_one[4] == (70000 + 255) // 256 and exp_four[4] == 0
+    assert exp_four[5] == 0 and exp_one[5] == 0 and np.ctypeslib.as_array(g.pair)[5] == 0
+    pair = np.ctypeslib.as_array(g.pair)
+    assert pair[0] == 0 and pair[8] >= (3000 + 63) // 64 + (777 + 63) // 64 + (5000 + 63) // 64
+    assert g.finalize > 0
+    assert L.shv_batch_table_bytes(-1) == 0
+
+
+def test_batch_table_validation_names_the_scene(L):
+    good = _fake_scene(L, 100, 10, 4)
+    bad = _fake_scene(L, 100, 10, 4)
+    bad.ws_bytes = 16
+    buf = (ctypes.c_uint8 * L.shv_batch_table_bytes(2))()
+    with pytest.raises(RuntimeError, match="scene 1"):
+        L.shv_batch_table_build([good, bad], buf)
+    bad = _fake_scene(L, 100, 10, 9)
+    with pytest.raises(RuntimeError, match="scene 0"):
+        L.shv_batch_table_build([bad, good], buf)
+    small = (ctypes.c_uint8 * 8)()
+    with pytest.raises(RuntimeError, match="table has"):
+        L.shv_batch_table_build([good], small)
