@@ -1,15 +1,22 @@
 """Benchmark: point-sphere pair evaluations per second, forward + backward.
 
-One step = the whole differentiable path on one scene resident in HBM: the
-fused sh_render_forward (visibility + shading) and sh_render_backward
-(gradients for receivers, normals, albedo, spheres and lighting), through the
-C ABI (``--path separate`` uses the four separate entry points instead; the
-results are bit-identical).  Default workload: the body-like scene (20,000
-receivers on 24 capsules, 128 spheres, 8 bands, k = 4), synthetic and seeded.
+Default workload (one step = the whole differentiable path on one scene
+resident in HBM): the body-like scene (20,000 receivers on 24 capsules, 128
+spheres, 8 bands, k = 4), synthetic and seeded, through the fused
+sh_render_forward (visibility + shading) and sh_render_backward (gradients
+for receivers, normals, albedo, spheres and lighting) of the C ABI
+(``--path separate`` uses the four separate entry points instead; the results
+are bit-identical).
+
+``--workload batched64``: 64 independent scenes (P ~ U{5k..50k}, S ~
+U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b); one step = the batched forward +
+backward over all 64, replayed from one captured graph; the same 64 scenes
+through 64 sequential single-scene forward + backward calls are timed beside
+it.
 
 Prints one JSON line with the throughput, a roofline entry for the dominant
 kernel (its average launch time from HIP events recorded around every launch
-on the launch stream during the timed steps) and the FP64 oracle timed on a
+on the launch stream, during eager steps) and the FP64 oracle timed on a
 bounded sample on the host's cores.
 """
 from __future__ import annotations
@@ -26,6 +33,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 flop/clk (packed FMA)
 PEAK_HBM_GBS = 8000.0
+METRIC = "point-sphere pair evals/s fwd+bwd"
 
 
 def parse():
@@ -33,12 +41,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="body", choices=["body", "gbuffer", "icosphere"])
+    ap.add_argument("--workload", default="body", choices=["body", "gbuffer", "icosphere", "batched64"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--path", default="render", choices=["render", "separate"])
     ap.add_argument("--flags", type=int, default=0, help="shv_params.flags (kernel-variant selection)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="batched64: time eager batched calls instead of graph replays")
     return ap.parse_args()
 
 
@@ -58,37 +68,97 @@ def make_scene(name):
     return sc, desc
 
 
-def cpu_baseline(sc, k, seconds):
-    """The FP64 oracle (autograd for the backward) on a seeded sample of
-    receivers of the same scene, all spheres, grown in chunks of 256 until
-    ``seconds`` have elapsed."""
+def cpu_baseline(scenes, k, seconds):
+    """The FP64 oracle (autograd for the backward) on seeded samples of
+    receivers (chunks of 256, all spheres), cycling over ``scenes`` until
+    ``seconds`` have elapsed or every receiver is done."""
     import numpy as np
     import torch
 
     from oracle import method
-    P = sc["points"].shape[0]
-    S = sc["spheres"].shape[0]
-    order = np.random.default_rng(123).permutation(P)
-    done = 0
+    perms = [np.random.default_rng(123 + i).permutation(sc["points"].shape[0]) for i, sc in enumerate(scenes)]
+    done = [0] * len(scenes)
+    pairs = 0
     t0 = time.perf_counter()
-    while done < P:
-        idx = np.sort(order[done:done + 256])
-        method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=k, idx=idx)
-        done += len(idx)
-        if time.perf_counter() - t0 >= seconds:
+    i = 0
+    while time.perf_counter() - t0 < seconds:
+        j = i % len(scenes)
+        sc = scenes[j]
+        if done[j] < sc["points"].shape[0]:
+            idx = np.sort(perms[j][done[j]:done[j] + 256])
+            method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=k, idx=idx)
+            done[j] += len(idx)
+            pairs += len(idx) * sc["spheres"].shape[0]
+        elif all(d >= s["points"].shape[0] for d, s in zip(done, scenes)):
             break
+        i += 1
     dt = time.perf_counter() - t0
-    return {"value": done * S / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{done} of {P} receivers (seeded permutation) x all {S} spheres, FP64 forward + "
-                      f"autograd backward, {dt:.1f} s"}
+    tot = sum(s["points"].shape[0] for s in scenes)
+    where = (f"{done[0]} of {tot} receivers (seeded permutation)" if len(scenes) == 1 else
+             f"{sum(done)} of {tot} receivers over {sum(1 for d in done if d)} of {len(scenes)} scenes "
+             "(seeded permutations, 256 per scene in turn)")
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{where} x all spheres, FP64 forward + autograd backward, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the single-GPU figure is whole-job throughput).", file=sys.stderr)
-        sys.exit(2)
+def kernel_table(prof):
+    kernels = {}
+    for name, (cnt, tot) in prof.items():
+        if cnt:
+            kernels[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt, "total_ms": tot}
+    return kernels
+
+
+def roofline(kernels, steps, work):
+    """Roofline entry of the kernel with the largest total time; ``work(name)``
+    gives its algorithmic flops per step.  achieved = flops per launch /
+    average launch time."""
+    dom = max(kernels, key=lambda kname: kernels[kname]["total_ms"])
+    flops_step, _ = work(dom)
+    for name, kv in kernels.items():
+        f, _ = work(name)
+        if f is not None:
+            kv["tflops"] = round(f * steps / (kv["total_ms"] * 1e-3) / 1e12, 3)
+        kv["avg_us"] = round(kv["avg_us"], 2)
+    if flops_step is None:
+        return None
+    per_launch = flops_step * steps / kernels[dom]["launches"]
+    ach = per_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e12
+    return {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "flops_per_launch": int(per_launch), "avg_launch_us": kernels[dom]["avg_us"]}
+
+
+def timed(step, stream, warmup, steps, profile):
+    """Average milliseconds per step over ``steps`` steps after ``warmup``;
+    with ``profile``, the library's per-launch HIP-event report as well."""
+    import torch
+
+    from paper_2104_00359_amd import _lib
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            _lib.shv_profile_enable(True, capacity=400 * steps + 64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if profile:
+            _lib.shv_profile_enable(False)
+    return (t1 - t0) * 1e3 / steps, (_lib.shv_profile_report() if profile else None)
+
+
+def finish_kernels(kernels):
+    for kv in kernels.values():
+        kv.pop("total_ms", None)
+    return kernels
+
+
+def bench_single(args):
     import numpy as np
     import torch
 
@@ -136,64 +206,92 @@ def main():
             _lib.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, gN, gA, gL, ws, nb, st)
             _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        _lib.shv_profile_enable(True, capacity=16 * args.steps + 64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _lib.shv_profile_enable(False)
-    prof = _lib.shv_profile_report()
-    ms = (t1 - t0) * 1e3 / args.steps
-    value = P * S / (ms * 1e-3)
-
-    kernels = {}
-    for name, (cnt, tot) in prof.items():
-        if cnt:
-            kernels[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt}
-    dom = max(kernels, key=lambda kname: kernels[kname]["avg_us"] * kernels[kname]["launches"])
-    flops, units = workmodel.kernel_work(dom, n, k, P, S)
-    avg_s = kernels[dom]["avg_us"] * 1e-6
-    roof = None
-    if flops is not None:
-        ach = flops / avg_s / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "flops_per_launch": flops, "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
-    for name, kv in kernels.items():
-        f, _ = workmodel.kernel_work(name, n, k, P, S)
-        if f is not None:
-            kv["tflops"] = round(f / (kv["avg_us"] * 1e-6) / 1e12, 3)
-        kv["avg_us"] = round(kv["avg_us"], 2)
-
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(sc, k, args.cpu_seconds)
-
-    out = {
-        "metric": "point-sphere pair evals/s fwd+bwd",
-        "value": value,
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    kernels = kernel_table(prof)
+    roof = roofline(kernels, args.steps, lambda name: workmodel.kernel_work(name, n, k, P, S))
+    cpu = cpu_baseline([sc], k, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    return {
+        "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0,
                    "entry_points": args.path},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
+        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
     }
+
+
+def bench_batched(args):
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import _lib, batch, ops, workmodel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    k = args.k
+    scenes = [scenegen.scene_batched(b) for b in range(64)]
+    bufs = [batch.scene_buffers(sc, dev, n_squarings=k) for sc in scenes]
+    rb = batch.RenderBatch(bufs, dev)
+    pairs = rb.pairs
+    stream = torch.cuda.Stream(device=dev)   # default priority
+    st = stream.cuda_stream
+
+    def batched():
+        rb.forward(stream)
+        rb.backward(stream)
+
+    def sequential():
+        for b in bufs:
+            o, prm = b.out, b.params()
+            ws_bytes = o["ws"].numel()
+            _lib.sh_render_forward(b.points, b.normals, b.albedo, b.spheres, b.light, b.P, b.S, prm, o["vis"],
+                                   o["radiance"], o["saved"], o["ws"], ws_bytes, st)
+            _lib.sh_render_backward(b.grad_radiance, b.points, b.normals, b.albedo, b.spheres, b.P, b.S, prm,
+                                    o["vis"], o["saved"], o["grad_points"], o["grad_normals"], o["grad_albedo"],
+                                    o["grad_spheres"], o["grad_light"], o["ws"], ws_bytes, st)
+
+    # per-kernel times from eager batched steps
+    steps_prof = max(args.steps // 4, 5)
+    ms_eager, prof = timed(batched, stream, args.warmup, steps_prof, True)
+    ms_seq, _ = timed(sequential, stream, max(args.warmup // 4, 2), max(args.steps // 4, 5), False)
+    if args.no_graph:
+        ms, mode = ms_eager, "eager batched calls"
+    else:
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            batched()
+        torch.cuda.synchronize()
+        ms, _ = timed(g.replay, stream, args.warmup, args.steps, False)
+        mode = "one captured graph (all batched phases) per step"
+    kernels = kernel_table(prof)
+    desc = [(b.n_bands, k, b.P, b.S) for b in bufs]
+    roof = roofline(kernels, steps_prof, lambda name: workmodel.batch_work(name, desc))
+    cpu = cpu_baseline(scenes, k, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    return {
+        "metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 independent scenes: P ~ U{5000..50000}, S ~ U{32..256}, n ~ U{4,6,8} "
+                               "(seeds 100+b), k=4, fwd+bwd, batched",
+                   "scenes": 64, "pairs_per_step": pairs, "receivers": sum(b.P for b in bufs),
+                   "n_squarings": k, "eps": 3.0, "launch": mode},
+        "batched_eager": {"ms_per_step": ms_eager, "value": pairs / (ms_eager * 1e-3)},
+        "sequential": {"ms_per_step": ms_seq, "value": pairs / (ms_seq * 1e-3),
+                       "what": "64 x (sh_render_forward + sh_render_backward), eager"},
+        "speedup_vs_sequential": ms_seq / ms,
+        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the single-GPU figure is whole-job throughput).", file=sys.stderr)
+        sys.exit(2)
+    out = bench_batched(args) if args.workload == "batched64" else bench_single(args)
     print(json.dumps(out))
 
 

@@ -84,6 +84,8 @@ class RenderBatch:
         self.grid = _lib.shv_batch_table_grid(self.table_host)
         self.table = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.table.copy_(self.table_host, non_blocking=True)
+        self._uploaded = torch.cuda.Event()
+        self._uploaded.record(torch.cuda.current_stream(dev))
         self._recs = recs
 
     def _allocate(self, sc: SceneBuffers):
@@ -113,7 +115,11 @@ class RenderBatch:
         return r
 
     def _stream(self, stream):
-        return (stream if stream is not None else torch.cuda.current_stream(self.device)).cuda_stream
+        """Raw handle of the launch stream, ordered after the table upload."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if not torch.cuda.is_current_stream_capturing():   # a captured graph orders itself at replay
+            s.wait_event(self._uploaded)
+        return s.cuda_stream
 
     def forward(self, stream=None):
         _lib.sh_render_batched_forward(self.table, self.grid, self._stream(stream))
@@ -124,3 +130,75 @@ class RenderBatch:
     @property
     def pairs(self) -> int:
         return sum(sc.P * sc.S for sc in self.scenes)
+
+
+class ShadeSHBatched(torch.autograd.Function):
+    """Radiance of many scenes through one batched forward / backward.
+    Inputs: a tuple of per-scene settings (n_bands, eps, n_squarings), then
+    five tensors per scene (points [P,3], normals [P,3], albedo [P], spheres
+    [S,4], light [n_bands^2])."""
+
+    @staticmethod
+    def forward(ctx, cfg, *flat):
+        if len(flat) != 5 * len(cfg):
+            raise ValueError("expected five tensors per scene")
+        dev = flat[0].device if flat else torch.device("cuda", torch.cuda.current_device())
+        if dev.type != "cuda":
+            raise RuntimeError("shade_sh_batched runs on the GPU only; move the inputs to a HIP device")
+        bufs = []
+        for i, (n, eps, k) in enumerate(cfg):
+            pts, nrm, alb, sph, L = flat[5 * i:5 * i + 5]
+            if L.numel() != n * n:
+                raise ValueError(f"scene {i}: light has {L.numel()} coefficients, expected {n * n}")
+            need = ctx.needs_input_grad[1 + 5 * i:6 + 5 * i]
+            grads = tuple(g for g, w in zip(("grad_points", "grad_normals", "grad_albedo", "grad_spheres",
+                                              "grad_light"), need) if w)
+            P = pts.shape[0]
+            f32 = lambda x: x.detach().to(torch.float32).contiguous()  # noqa: E731
+            bufs.append(SceneBuffers(points=f32(pts).t().contiguous(), normals=f32(nrm).t().contiguous(),
+                                     albedo=f32(alb), spheres=f32(sph).reshape(-1, 4), light=f32(L),
+                                     grad_radiance=torch.zeros(max(P, 1), device=dev),
+                                     n_bands=int(n), eps=float(eps), n_squarings=int(k), grads=grads))
+        rb = RenderBatch(bufs, dev)
+        rb.forward()
+        ctx.rb = rb
+        return tuple(b.out["radiance"] for b in bufs)
+
+    @staticmethod
+    def backward(ctx, *grad_outputs):
+        rb = ctx.rb
+        for b, g in zip(rb.scenes, grad_outputs):
+            if g is None:
+                b.grad_radiance.zero_()
+            elif b.P > 0:
+                b.grad_radiance[:b.P].copy_(g.detach().to(torch.float32))
+        rb.backward()
+        out = [None]
+        for b in rb.scenes:
+            o = b.out
+            for name in GRAD_NAMES:
+                t = o.get(name)
+                if t is None:
+                    out.append(None)
+                elif name in ("grad_points", "grad_normals"):
+                    out.append(t.t())
+                elif name == "grad_spheres":
+                    out.append(t[:b.S])
+                else:
+                    out.append(t)
+        ctx.rb = None
+        return tuple(out)
+
+
+def shade_sh_batched(points, normals, albedo, spheres, light, n_bands, eps: float = 3.0, n_squarings: int = 4):
+    """Per-scene radiance [P_b] for lists of scene tensors (layouts as in
+    ``ops.shade_sh``); ``n_bands`` is an int or a list of per-scene ints.
+    Differentiable with respect to every tensor input; each scene's results
+    are bit-identical to ``ops.shade_sh`` on that scene alone."""
+    m = len(points)
+    nb = list(n_bands) if isinstance(n_bands, (list, tuple)) else [int(n_bands)] * m
+    cfg = tuple((nb[i], eps, n_squarings) for i in range(m))
+    flat = []
+    for i in range(m):
+        flat += [points[i], normals[i], albedo[i], spheres[i], light[i]]
+    return list(ShadeSHBatched.apply(cfg, *flat))

@@ -126,3 +126,21 @@ def kernel_work(name: str, n: int, k: int, P: int, S: int):
     if name == "exp_shade_bwd":
         return (exp_bwd_flops(n, k) + shade_bwd_flops(n)) * P, P
     return None, None
+
+
+BATCH_KERNELS = {"batch_pair_fwd": "pair_fwd", "batch_pair_bwd": "pair_bwd", "batch_exp_shade_fwd": "exp_shade_fwd",
+                 "batch_exp_shade_bwd": "exp_shade_bwd"}
+
+
+def batch_work(name: str, scenes):
+    """(flops, unit count) of all launches of batched kernel ``name`` in one
+    batched call over ``scenes`` (tuples (n, k, P, S))."""
+    single = BATCH_KERNELS.get(name)
+    if single is None:
+        return None, None
+    flops = units = 0
+    for n, k, P, S in scenes:
+        f, u = kernel_work(single, n, k, P, S)
+        flops += f
+        units += u
+    return flops, units

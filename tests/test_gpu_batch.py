@@ -151,3 +151,26 @@ def test_graph_replay_and_new_batch_in_same_table():
     torch.cuda.synchronize()
     for b, ref in zip(bufs2, eager2):
         _assert_same(collect(b), ref, "new batch")
+
+
+def test_autograd_batched_matches_single_scene_autograd():
+    from paper_2104_00359_amd import batch, ops
+    dev = torch.device("cuda", 0)
+    cases = [(70, 1500, 30, 8), (71, 900, 50, 4), (72, 2100, 12, 6)]
+    scenes = [scenegen.scene_random_shell(s, P, S, n) for s, P, S, n in cases]
+
+    def leaves(sc):
+        return [torch.tensor(sc[key], device=dev, requires_grad=True)
+                for key in ("points", "normals", "albedo", "spheres", "light")]
+    batched_in = [leaves(sc) for sc in scenes]
+    outs = batch.shade_sh_batched(*[[x[i] for x in batched_in] for i in range(5)],
+                                  n_bands=[sc["n_bands"] for sc in scenes])
+    loss = sum((o * torch.tensor(sc["grad_radiance"], device=dev)).sum() for o, sc in zip(outs, scenes))
+    loss.backward()
+    for sc, xs, o in zip(scenes, batched_in, outs):
+        ys = leaves(sc)
+        r = ops.shade_sh(*ys, n_bands=sc["n_bands"])
+        (r * torch.tensor(sc["grad_radiance"], device=dev)).sum().backward()
+        assert torch.equal(o.detach(), r.detach())
+        for x, y in zip(xs, ys):
+            assert torch.equal(x.grad, y.grad)
