@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="body", choices=["body", "gbuffer", "icosphere", "batched64"])
+    ap.add_argument("--workload", default="body", choices=["body", "gbuffer", "icosphere", "batched64", "serve"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--k", type=int, default=4)
@@ -49,6 +49,11 @@ def parse():
     ap.add_argument("--flags", type=int, default=0, help="shv_params.flags (kernel-variant selection)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched64: time eager batched calls instead of graph replays")
+    ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
+                    help="serve: Poisson arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=4.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--chunk-pairs", type=int, default=8 << 20, help="serve: pair bound of a request range")
+    ap.add_argument("--step-pairs", type=int, default=64 << 20, help="serve: pair bound of a step")
     return ap.parse_args()
 
 
@@ -285,13 +290,80 @@ def bench_batched(args):
     }
 
 
+def bench_serve(args):
+    """Poisson load against the continuous-batching server and against one
+    request at a time (single-scene calls), per arrival rate."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import batch, serve
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    small = [batch.scene_buffers(scenegen.scene_batched(b), dev) for b in range(64)]
+    large = [batch.scene_buffers(scenegen.large_request_scene(500 + i), dev) for i in range(4)]
+    free, _ = torch.cuda.mem_get_info(dev)
+    budget = int(free - (16 << 30))
+    rates = [float(r) for r in args.rates.split(",")]
+    pick_rng = np.random.default_rng(7)
+    n_max = int(max(rates) * args.duration * 1.5 + 100)
+    is_large = pick_rng.random(n_max) < 0.1
+    which = np.where(is_large, pick_rng.integers(0, 4, n_max), pick_rng.integers(0, 64, n_max))
+
+    def make_request(i):
+        src = large[which[i]] if is_large[i] else small[which[i]]
+        return dataclasses.replace(src, out={}, rec=None), src.P, src.S
+
+    mean_pairs = float(np.mean([(large[w] if l else small[w]).P * (large[w] if l else small[w]).S
+                                for l, w in zip(is_large[:2000], which[:2000])]))
+    results = {"continuous": [], "one_at_a_time": []}
+    for mode in results:
+        for rate in rates:
+            if mode == "continuous":
+                ex = serve.GpuExecutor(dev)
+                sched = serve.Scheduler(ex, budget, chunk_pairs=args.chunk_pairs, step_pairs=args.step_pairs,
+                                        max_inflight=2, keep_results=False, admit_ahead=4 * args.step_pairs)
+            else:
+                ex = serve.GpuExecutor(dev, single_scene=True)
+                sched = serve.Scheduler(ex, budget, chunk_pairs=None, max_active=1, max_inflight=1,
+                                        keep_results=False)
+            sched.start()
+            r = serve.run_load(sched, make_request, rate, args.duration, warmup=0.5, seed=7, drain=15.0)
+            sched.stop(timeout=30)
+            torch.cuda.synchronize()
+            print(f"[serve] {mode} rate {rate:g}: {json.dumps(r)}", file=sys.stderr, flush=True)
+            results[mode].append(r)
+    best = max((r for r in results["continuous"] if r["p99_ms"] is not None and r["unfinished"] == 0),
+               key=lambda r: r["throughput_rps"] or 0, default=None)
+    return {
+        "metric": "served fwd+bwd requests/s (continuous batching, Poisson arrivals)",
+        "value": best["throughput_rps"] if best else None, "unit": "requests/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "90% requests from the 64-scene distribution (P 5k..50k, S 32..256, n 4/6/8), "
+                               "10% large (P 262144, S 512, n 8); Poisson arrivals, seed 7",
+                   "duration_s": args.duration, "warmup_s": 0.5, "chunk_pairs": args.chunk_pairs,
+                   "step_pairs": args.step_pairs, "memory_budget_gb": round(budget / 2**30, 1),
+                   "mean_pairs_per_request": mean_pairs},
+        "p50_ms": best["p50_ms"] if best else None, "p99_ms": best["p99_ms"] if best else None,
+        "sweep": results,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
               "(the single-GPU figure is whole-job throughput).", file=sys.stderr)
         sys.exit(2)
-    out = bench_batched(args) if args.workload == "batched64" else bench_single(args)
+    if args.workload == "batched64":
+        out = bench_batched(args)
+    elif args.workload == "serve":
+        out = bench_serve(args)
+    else:
+        out = bench_single(args)
     print(json.dumps(out))
 
 

@@ -58,6 +58,7 @@ typedef int32_t shv_status;
 
 #define SHV_MAX_BANDS_API 8
 #define SHV_MAX_SQUARINGS 12
+#define SHV_RANGE_ALIGN 256   /* receiver-range granularity of batched calls */
 
 /* Method parameters.  n_bands: number of SH bands n (l < n), the paper uses
  * n = 8 (Sec. 3.2).  n_squarings: k, the number of squarings of the SH
@@ -186,6 +187,19 @@ typedef struct shv_scene {
   int64_t P;
   int64_t S;
   shv_params params;
+  /* Receiver range [range_begin, range_end) processed by this call; 0, 0
+   * means the whole scene.  A scene may be processed by several calls over
+   * disjoint ranges covering [0, P), each with the scene's full buffers
+   * (P, ws and saved sized for the whole scene); both ends must be multiples
+   * of SHV_RANGE_ALIGN, except range_end = P.  Receiver outputs of a range
+   * are final after its forward / backward; the sphere, lighting and
+   * receiver-position gradients are reduced over all receivers by the
+   * backward of the call whose defer_reductions is 0, which must come after
+   * the backward of every other range in stream order.  The results are
+   * bit-identical to one whole-scene call. */
+  int64_t range_begin;
+  int64_t range_end;
+  int32_t defer_reductions;
 } shv_scene;
 
 /* Bytes of the work table for n_scenes scenes. */

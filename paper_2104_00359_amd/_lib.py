@@ -37,6 +37,7 @@ EXPORTED = [
     "shv_profile_enable", "shv_profile_report",
 ]
 
+SHV_RANGE_ALIGN = 256
 SHV_FLAG_EXP_ONE_WAVE = 1
 SHV_FLAG_EXP_FOUR_WAVES = 2
 
@@ -51,7 +52,8 @@ class shv_scene(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in (
         "points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved",
         "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light", "ws")] + [
-        ("ws_bytes", ctypes.c_size_t), ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("params", shv_params)]
+        ("ws_bytes", ctypes.c_size_t), ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("params", shv_params),
+        ("range_begin", ctypes.c_int64), ("range_end", ctypes.c_int64), ("defer_reductions", ctypes.c_int32)]
 
 
 class shv_batch_grid(ctypes.Structure):

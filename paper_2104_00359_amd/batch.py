@@ -9,6 +9,7 @@ single-scene ``sh_render_forward`` / ``sh_render_backward`` call.
 """
 from __future__ import annotations
 
+import ctypes
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -20,9 +21,18 @@ from .ops import ensure_init
 GRAD_NAMES = ("grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light")
 
 
-@dataclass
+_ALIGN = 256
+
+
+def _aligned(n: int) -> int:
+    return (int(n) + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+@dataclass(eq=False)
 class SceneBuffers:
-    """Device buffers of one scene in the C layout (SoA [3][P] geometry)."""
+    """Device buffers of one scene in the C layout (SoA [3][P] geometry).
+    ``allocate`` carves the outputs, saved state and workspace out of one
+    device allocation and prepares the scene's C record."""
     points: torch.Tensor
     normals: torch.Tensor
     albedo: torch.Tensor
@@ -35,6 +45,7 @@ class SceneBuffers:
     flags: int = 0
     grads: tuple = GRAD_NAMES
     out: dict = field(default_factory=dict)
+    rec: object = None
 
     @property
     def P(self) -> int:
@@ -46,6 +57,71 @@ class SceneBuffers:
 
     def params(self):
         return _lib.params(self.n_bands, self.eps, self.n_squarings, self.flags)
+
+    def _layout(self):
+        """(name, shape or byte count) of every buffer the scene needs."""
+        P, S, N = self.P, self.S, self.n_bands * self.n_bands
+        prm = self.params()
+        lay = [("vis", (N, P)), ("radiance", (P,)), ("saved", (max(_lib.shv_render_saved_floats(P, prm), 1),)),
+               ("ws", max(_lib.shv_workspace_bytes(P, S, prm), _ALIGN))]
+        shapes = {"grad_points": (3, P), "grad_normals": (3, P), "grad_albedo": (P,), "grad_spheres": (max(S, 1), 4),
+                  "grad_light": (N,)}
+        lay += [(g, shapes[g]) for g in GRAD_NAMES if g in self.grads]
+        return lay
+
+    @staticmethod
+    def _nbytes(spec) -> int:
+        if isinstance(spec, int):
+            return spec
+        n = 1
+        for d in spec:
+            n *= d
+        return 4 * n
+
+    def device_bytes(self, include_inputs: bool = True) -> int:
+        """Device memory this scene occupies once allocated (HBM footprint)."""
+        total = sum(_aligned(self._nbytes(spec)) for _, spec in self._layout())
+        if include_inputs:
+            ins = [self.points, self.normals, self.albedo, self.spheres, self.light, self.grad_radiance]
+            total += sum(_aligned(t.numel() * t.element_size()) for t in ins if t is not None)
+        return total
+
+    def allocate(self, device=None) -> None:
+        dev = device if device is not None else self.points.device
+        lay = self._layout()
+        offs, total = [], 0
+        for _, spec in lay:
+            offs.append(total)
+            total += _aligned(self._nbytes(spec))
+        arena = torch.empty(max(total, _ALIGN), dtype=torch.uint8, device=dev)
+        o = {"arena": arena}
+        for (name, spec), off in zip(lay, offs):
+            nb = self._nbytes(spec)
+            if name == "ws":
+                o[name] = arena[off:off + nb]
+            else:
+                o[name] = arena[off:off + nb].view(torch.float32).view(*spec)
+        for g in GRAD_NAMES:
+            o.setdefault(g, None)
+        self.out = o
+        r = _lib.shv_scene()
+        r.points, r.normals, r.albedo = _lib.ptr(self.points), _lib.ptr(self.normals), _lib.ptr(self.albedo)
+        r.spheres, r.light = _lib.ptr(self.spheres), _lib.ptr(self.light)
+        r.grad_radiance = _lib.ptr(self.grad_radiance)
+        r.vis, r.radiance, r.saved = _lib.ptr(o["vis"]), _lib.ptr(o["radiance"]), _lib.ptr(o["saved"])
+        r.grad_points, r.grad_normals = _lib.ptr(o["grad_points"]), _lib.ptr(o["grad_normals"])
+        r.grad_albedo, r.grad_spheres = _lib.ptr(o["grad_albedo"]), _lib.ptr(o["grad_spheres"])
+        r.grad_light = _lib.ptr(o["grad_light"])
+        r.ws, r.ws_bytes = _lib.ptr(o["ws"]), o["ws"].numel()
+        r.P, r.S, r.params = self.P, self.S, self.params()
+        self.rec = r
+
+    def record(self, begin: int = 0, end: int = 0, defer: bool = False):
+        """The scene's C record for receivers [begin, end) (0, 0: all)."""
+        r = _lib.shv_scene()
+        ctypes.pointer(r)[0] = self.rec
+        r.range_begin, r.range_end, r.defer_reductions = int(begin), int(end), 1 if defer else 0
+        return r
 
 
 def scene_buffers(scene: dict, device, eps=3.0, n_squarings=4, flags=0, grads=GRAD_NAMES) -> SceneBuffers:
@@ -64,10 +140,39 @@ def scene_buffers(scene: dict, device, eps=3.0, n_squarings=4, flags=0, grads=GR
                         grads=tuple(grads))
 
 
+class Table:
+    """A packed work table (host copy in pinned memory, device copy) and its
+    launch grid.  ``records``: C scene records (SceneBuffers.record())."""
+
+    def __init__(self, records, device, stream=None):
+        n = len(records)
+        nbytes = _lib.shv_batch_table_bytes(n)
+        self.host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        _lib.shv_batch_table_build(records, self.host)
+        self.grid = _lib.shv_batch_table_grid(self.host)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.device = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        with torch.cuda.stream(s):
+            self.device.copy_(self.host, non_blocking=True)
+        self.uploaded = torch.cuda.Event()
+        self.uploaded.record(s)
+
+    def _handle(self, stream):
+        if not torch.cuda.is_current_stream_capturing():   # a captured graph orders itself at replay
+            stream.wait_event(self.uploaded)
+        return stream.cuda_stream
+
+    def forward(self, stream):
+        _lib.sh_render_batched_forward(self.device, self.grid, self._handle(stream))
+
+    def backward(self, stream):
+        _lib.sh_render_batched_backward(self.device, self.grid, self._handle(stream))
+
+
 class RenderBatch:
-    """One batch of scenes: outputs are allocated here, the table is built
-    and uploaded once; ``forward`` and ``backward`` enqueue the batched calls
-    on ``stream`` (default: the current stream)."""
+    """Whole scenes in one batch: buffers are allocated and the table is
+    built and uploaded once; ``forward`` and ``backward`` enqueue the batched
+    calls on ``stream`` (default: the current stream)."""
 
     def __init__(self, scenes: list[SceneBuffers], device=None):
         self.scenes = list(scenes)
@@ -75,57 +180,26 @@ class RenderBatch:
             self.scenes[0].points.device if self.scenes else torch.device("cuda", torch.cuda.current_device()))
         self.device = dev
         ensure_init(dev)
-        recs = []
         for sc in self.scenes:
-            recs.append(self._allocate(sc))
-        nbytes = _lib.shv_batch_table_bytes(len(recs))
-        self.table_host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
-        _lib.shv_batch_table_build(recs, self.table_host)
-        self.grid = _lib.shv_batch_table_grid(self.table_host)
-        self.table = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        self.table.copy_(self.table_host, non_blocking=True)
-        self._uploaded = torch.cuda.Event()
-        self._uploaded.record(torch.cuda.current_stream(dev))
-        self._recs = recs
+            sc.allocate(dev)
+        self.tab = Table([sc.record() for sc in self.scenes], dev)
 
-    def _allocate(self, sc: SceneBuffers):
-        dev = self.device
-        P, S, N = sc.P, sc.S, sc.n_bands * sc.n_bands
-        prm = sc.params()
-        o = sc.out
-        o["vis"] = torch.empty(N, P, device=dev)
-        o["radiance"] = torch.empty(P, device=dev)
-        o["saved"] = torch.empty(max(_lib.shv_render_saved_floats(P, prm), 1), device=dev)
-        ws_bytes = _lib.shv_workspace_bytes(P, S, prm)
-        o["ws"] = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
-        shapes = {"grad_points": (3, P), "grad_normals": (3, P), "grad_albedo": (P,), "grad_spheres": (max(S, 1), 4),
-                  "grad_light": (N,)}
-        for g in GRAD_NAMES:
-            o[g] = torch.empty(*shapes[g], device=dev) if g in sc.grads else None
-        r = _lib.shv_scene()
-        r.points, r.normals, r.albedo = _lib.ptr(sc.points), _lib.ptr(sc.normals), _lib.ptr(sc.albedo)
-        r.spheres, r.light = _lib.ptr(sc.spheres), _lib.ptr(sc.light)
-        r.grad_radiance = _lib.ptr(sc.grad_radiance)
-        r.vis, r.radiance, r.saved = _lib.ptr(o["vis"]), _lib.ptr(o["radiance"]), _lib.ptr(o["saved"])
-        r.grad_points, r.grad_normals = _lib.ptr(o["grad_points"]), _lib.ptr(o["grad_normals"])
-        r.grad_albedo, r.grad_spheres = _lib.ptr(o["grad_albedo"]), _lib.ptr(o["grad_spheres"])
-        r.grad_light = _lib.ptr(o["grad_light"])
-        r.ws, r.ws_bytes = _lib.ptr(o["ws"]), ws_bytes
-        r.P, r.S, r.params = P, S, prm
-        return r
+    @property
+    def table(self) -> torch.Tensor:
+        return self.tab.device
 
-    def _stream(self, stream):
-        """Raw handle of the launch stream, ordered after the table upload."""
-        s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        if not torch.cuda.is_current_stream_capturing():   # a captured graph orders itself at replay
-            s.wait_event(self._uploaded)
-        return s.cuda_stream
+    @property
+    def grid(self):
+        return self.tab.grid
+
+    def _s(self, stream):
+        return stream if stream is not None else torch.cuda.current_stream(self.device)
 
     def forward(self, stream=None):
-        _lib.sh_render_batched_forward(self.table, self.grid, self._stream(stream))
+        self.tab.forward(self._s(stream))
 
     def backward(self, stream=None):
-        _lib.sh_render_batched_backward(self.table, self.grid, self._stream(stream))
+        self.tab.backward(self._s(stream))
 
     @property
     def pairs(self) -> int:

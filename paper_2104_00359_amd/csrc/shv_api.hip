@@ -174,20 +174,27 @@ size_t visbwd_bytes(int64_t P, int64_t S, int nb, VisBwdWs* o = nullptr) {
 struct RenderBwdWs {
   size_t W, gp, gs, lp;
 };
+// The render backward's W ([N][P]) may alias the forward's sphere-chunk
+// partials ([nchunks][N][P], from offset 0): both are indexed by receiver
+// column, and a call (or receiver range of a batched call) only touches its
+// own receivers' columns.  The receiver-gradient partials and the per-tile
+// sphere and lighting partials must outlive later ranges' forwards until the
+// closing reductions, so they start after the forward's region.
 size_t render_bwd_bytes(int64_t P, int64_t S, int nb, RenderBwdWs* o = nullptr) {
   const shv::Split sp = shv::choose_split(P, S);
   const size_t N = (size_t)nb * nb;
   const size_t w = align_up(N * (size_t)P * 4);
+  const size_t base = std::max(w, fwd_bytes(P, S, nb));
   const size_t gp = align_up((size_t)sp.nchunks * 3 * (size_t)P * 4);
   const size_t gs = align_up((size_t)shv::pair_blocks(P) * (size_t)S * 16);
   const size_t lp = align_up((size_t)shv::pair_blocks(P) * N * 4);
   if (o) {
     o->W = 0;
-    o->gp = w;
-    o->gs = w + gp;
-    o->lp = w + gp + gs;
+    o->gp = base;
+    o->gs = base + gp;
+    o->lp = base + gp + gs;
   }
-  return w + gp + gs + lp;
+  return base + gp + gs + lp;
 }
 // Forward: the F' partials, then M(L) when it is not kept in `saved`.
 size_t render_fwd_bytes(int64_t P, int64_t S, int nb) {
@@ -512,6 +519,13 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
       else if (in.S > 0 && (((uintptr_t)in.spheres) & 15u)) st = set_error(SHV_ERR_INVALID_ARG, "spheres misaligned");
     }
     if (st == SHV_OK) st = check_ws(in.ws, in.ws_bytes, in.P > 0 ? shv_workspace_bytes(in.P, in.S, prm) : 0);
+    if (st == SHV_OK && !(in.range_begin == 0 && in.range_end == 0)) {
+      const int64_t a = in.range_begin, e = in.range_end;
+      if (a < 0 || a > e || e > in.P || a % SHV_RANGE_ALIGN || (e != in.P && e % SHV_RANGE_ALIGN))
+        st = set_error(SHV_ERR_INVALID_ARG,
+                       "receiver range [%lld, %lld) invalid for P = %lld (ends must be multiples of %d or P)",
+                       (long long)a, (long long)e, (long long)in.P, SHV_RANGE_ALIGN);
+    }
     if (st != SHV_OK) {
       const std::string msg = g_last_error;
       return set_error(st, "scene %d: %s", (int)i, msg.c_str());
@@ -545,6 +559,12 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     b.four_waves = shv::exp_four_waves(in.P, prm->flags) ? 1 : 0;
     b.pair_tiles = shv::pair_blocks(in.P);
     b.exp_blocks = b.four_waves ? (in.P + 63) / 64 : shv::point_blocks(in.P);
+    // receiver range of this call (whole scene by default)
+    const int64_t r0 = in.range_begin, r1 = (in.range_begin == 0 && in.range_end == 0) ? in.P : in.range_end;
+    const int64_t eb = b.four_waves ? 64 : SHV_BLOCK;  // receivers per exponential block
+    b.tile0 = r0 / 64;
+    b.range_tiles = (r1 + 63) / 64 - r0 / 64;
+    b.exp_block0 = r0 / eb;
     // the same workspace carving as the single-scene render entry points
     RenderBwdWs L;
     render_bwd_bytes(in.P, in.S, nb, &L);
@@ -559,9 +579,9 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     b.fin_pts = (need_pair && in.grad_points) ? (int32_t)((3 * in.P + SHV_BLOCK - 1) / SHV_BLOCK) : 0;
     b.fin_cols_s = b.grad_spheres ? (int32_t)(4 * in.S) : 0;
     b.fin_cols_l = in.grad_light ? (int32_t)N : 0;
-    b.n_pair = in.P > 0 ? b.pair_tiles * sp.nchunks : 0;
-    b.n_exp = in.P > 0 ? b.exp_blocks : 0;
-    b.n_fin = (int64_t)b.fin_pts + b.fin_cols_s + b.fin_cols_l;
+    b.n_pair = in.P > 0 ? b.range_tiles * sp.nchunks : 0;
+    b.n_exp = in.P > 0 ? (r1 + eb - 1) / eb - b.exp_block0 : 0;
+    b.n_fin = in.defer_reductions ? 0 : (int64_t)b.fin_pts + b.fin_cols_s + b.fin_cols_l;
     const int lay = b.four_waves;
     b.off_pair = h.total_pair[nb];
     b.off_exp = h.total_exp[lay][nb];

@@ -50,8 +50,10 @@ struct BatchScene {
   int32_t nchunks, chunk;      // sphere split of the pair kernels
   int32_t four_waves;          // exponential layout
   int32_t fin_pts, fin_cols_s, fin_cols_l;
-  int64_t pair_tiles;          // ceil(P / 64)
-  int64_t exp_blocks;          // blocks of the exponential kernels
+  int64_t pair_tiles;          // ceil(P / 64): receiver tiles of the whole scene
+  int64_t exp_blocks;          // exponential blocks of the whole scene
+  int64_t tile0, range_tiles;  // receiver tiles of this call's range
+  int64_t exp_block0;          // first exponential block of the range
   int64_t n_pair, n_exp, n_fin;        // items per phase
   int64_t off_pair;            // first pair item within the band count's item space
   int64_t off_exp;             // first exponential item within the (layout, band count) item space

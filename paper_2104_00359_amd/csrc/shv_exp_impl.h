@@ -587,7 +587,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_fwd(const char* __restr
   const int64_t item = blockIdx.x;
   if (item >= v.h->total_exp[FOUR][NB]) return;
   const BatchScene S = in_global(v.scene_of_exp(FOUR, NB, item));
-  const int64_t bx = item - S.off_exp;
+  const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
   if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
   else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx);
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(SHV_BLOCK, FOUR ? 2 : 1) void k_batch_exp_bwd(const
   if (item >= v.h->total_exp[FOUR][NB]) return;
   const BatchScene S = in_global(v.scene_of_exp(FOUR, NB, item));
   if (!S.grad_radiance) return;  // uniform: scene packed without a cotangent
-  const int64_t bx = item - S.off_exp;
+  const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
   if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
   else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT);

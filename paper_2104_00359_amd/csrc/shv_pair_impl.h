@@ -60,12 +60,13 @@ struct PairFwdShared {
 };
 
 // One block of the pair forward: receivers [64 bx, 64 bx + 64), sphere chunk
-// by; nbx = number of receiver tiles of the scene.
+// by.  Blocks of chunk 0 also build M(L), block m_idx of m_count taking every
+// m_count-th entry.
 template <int NB>
 __device__ __forceinline__ void pair_fwd_item(const float* __restrict__ pts, int64_t P, const float4* __restrict__ sph,
                                               int S, int chunk, float* __restrict__ Fpart,
                                               const float* __restrict__ L, float* __restrict__ M, int64_t bx, int by,
-                                              int64_t nbx, PairFwdShared<NB>& sh) {
+                                              int64_t m_idx, int64_t m_count, PairFwdShared<NB>& sh) {
   constexpr int N = NB * NB;
   auto& X = sh.X;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -136,7 +137,7 @@ __device__ __forceinline__ void pair_fwd_item(const float* __restrict__ pts, int
   // Side job for the fused render path, spread over the first chunk's blocks:
   // the lit transfer matrix M(L), needed by the shading that follows in
   // stream order.
-  if (M && by == 0) build_M_range<NB>(L, M, (int)(bx * SHV_BLOCK) + threadIdx.x, (int)(nbx * SHV_BLOCK));
+  if (M && by == 0) build_M_range<NB>(L, M, (int)(m_idx * SHV_BLOCK) + threadIdx.x, (int)(m_count * SHV_BLOCK));
 }
 
 template <int NB>
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_pair_fwd(const float* __restrict_
                                                         float* __restrict__ Fpart, const float* __restrict__ L,
                                                         float* __restrict__ M) {
   __shared__ PairFwdShared<NB> sh;
-  pair_fwd_item<NB>(pts, P, sph, S, chunk, Fpart, L, M, blockIdx.x, blockIdx.y, gridDim.x, sh);
+  pair_fwd_item<NB>(pts, P, sph, S, chunk, Fpart, L, M, blockIdx.x, blockIdx.y, blockIdx.x, gridDim.x, sh);
 }
 
 struct PairBwdShared {
@@ -301,10 +302,10 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_fwd(const char* __rest
   if (item >= v.h->total_pair[NB]) return;
   const BatchScene S = in_global(v.scene_of(NB, item));
   const int64_t local = item - S.off_pair;
-  const int64_t bx = local % S.pair_tiles;
-  const int by = (int)(local / S.pair_tiles);
+  const int64_t tile = local % S.range_tiles;
+  const int by = (int)(local / S.range_tiles);
   pair_fwd_item<NB>(S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.Fpart, S.light,
-                    S.M, bx, by, S.pair_tiles, sh);
+                    S.M, S.tile0 + tile, by, tile, S.range_tiles, sh);
 }
 
 template <int NB>
@@ -316,8 +317,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_bwd(const char* __rest
   const BatchScene S = in_global(v.scene_of(NB, item));
   if (!S.grad_radiance || (!S.grad_points && !S.grad_spheres)) return;  // uniform: nothing to do
   const int64_t local = item - S.off_pair;
-  const int64_t bx = local % S.pair_tiles;
-  const int by = (int)(local / S.pair_tiles);
+  const int64_t bx = S.tile0 + local % S.range_tiles;
+  const int by = (int)(local / S.range_tiles);
   pair_bwd_item<NB>(S.W, S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.gp,
                     reinterpret_cast<float4*>(S.gs), bx, by, sh);
 }

@@ -130,3 +130,22 @@ def test_batch_table_validation_names_the_scene(L):
     small = (ctypes.c_uint8 * 8)()
     with pytest.raises(RuntimeError, match="table has"):
         L.shv_batch_table_build([good], small)
+
+
+def test_batch_receiver_range_validation(L):
+    buf = (ctypes.c_uint8 * L.shv_batch_table_bytes(1))()
+    for begin, end in ((100, 512), (0, 300), (512, 256), (0, 1100), (-256, 0)):
+        r = _fake_scene(L, 1000, 10, 4)
+        r.range_begin, r.range_end = begin, end
+        with pytest.raises(RuntimeError, match="receiver range"):
+            L.shv_batch_table_build([r], buf)
+    for begin, end in ((0, 256), (256, 1000), (512, 512)):
+        r = _fake_scene(L, 1000, 10, 4)
+        r.range_begin, r.range_end = begin, end
+        L.shv_batch_table_build([r], buf)
+    r = _fake_scene(L, 1000, 10, 4)
+    r.range_begin, r.range_end, r.defer_reductions = 256, 1000, 1
+    L.shv_batch_table_build([r], buf)
+    g = L.shv_batch_table_grid(buf)
+    assert g.finalize == 0
+    assert np.ctypeslib.as_array(g.exp)[1][4] == (1000 + 63) // 64 - 256 // 64
