@@ -8,6 +8,11 @@ for receivers, normals, albedo, spheres and lighting) of the C ABI
 (``--path separate`` uses the four separate entry points instead; the results
 are bit-identical).
 
+``--workload serve``: Poisson arrivals of forward + backward requests (90%
+from the 64-scene distribution, 10% at 262,144 receivers x 512 spheres)
+against the continuous-batching server and against one request at a time,
+per arrival rate; prints throughput and p50 / p99 latency.
+
 ``--workload batched64``: 64 independent scenes (P ~ U{5k..50k}, S ~
 U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b); one step = the batched forward +
 backward over all 64, replayed from one captured graph; the same 64 scenes
@@ -54,6 +59,7 @@ def parse():
     ap.add_argument("--duration", type=float, default=4.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--chunk-pairs", type=int, default=8 << 20, help="serve: pair bound of a request range")
     ap.add_argument("--step-pairs", type=int, default=64 << 20, help="serve: pair bound of a step")
+    ap.add_argument("--modes", default="continuous,one_at_a_time", help="serve: scheduler modes to sweep")
     return ap.parse_args()
 
 
@@ -319,7 +325,7 @@ def bench_serve(args):
 
     mean_pairs = float(np.mean([(large[w] if l else small[w]).P * (large[w] if l else small[w]).S
                                 for l, w in zip(is_large[:2000], which[:2000])]))
-    results = {"continuous": [], "one_at_a_time": []}
+    results = {m: [] for m in args.modes.split(",")}
     for mode in results:
         for rate in rates:
             if mode == "continuous":
@@ -336,7 +342,7 @@ def bench_serve(args):
             torch.cuda.synchronize()
             print(f"[serve] {mode} rate {rate:g}: {json.dumps(r)}", file=sys.stderr, flush=True)
             results[mode].append(r)
-    best = max((r for r in results["continuous"] if r["p99_ms"] is not None and r["unfinished"] == 0),
+    best = max((r for r in results.get("continuous", []) if r["p99_ms"] is not None and r["unfinished"] == 0),
                key=lambda r: r["throughput_rps"] or 0, default=None)
     return {
         "metric": "served fwd+bwd requests/s (continuous batching, Poisson arrivals)",
