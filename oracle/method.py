@@ -26,7 +26,9 @@ Readings where the paper is silent (each is listed in the design notes):
     a = b = exp(|G|^2 / (8 pi)) (the least-squares line through exp(g) when
     g's values over the sphere are Gaussian with variance |G|^2 / (4 pi)),
     then squared k times with the truncated triple product; k is fixed per
-    call (default 4);
+    call (default 4).  The paper's own fitted OL tables are not available, so
+    agreement with its exponential is parity unpinned; this closed form is
+    pinned by the exact cases and the least-squares and second-order tests;
   * a receiver inside a sphere (r >= d) sees a hemisphere cap (t = 0); a
     sphere centred on the receiver (d = 0) contributes nothing;
   * normals are normalised before use; no clamping of V or B anywhere.
