@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--chunk-pairs", type=int, default=8 << 20, help="serve: pair bound of a request range")
     ap.add_argument("--step-pairs", type=int, default=64 << 20, help="serve: pair bound of a step")
     ap.add_argument("--modes", default="continuous,one_at_a_time", help="serve: scheduler modes to sweep")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device-to-device once (a plain copy kernel "
+                         "of known size, to calibrate HBM byte counters)")
     return ap.parse_args()
 
 
@@ -140,6 +143,39 @@ def roofline(kernels, steps, work):
             "flops_per_launch": int(per_launch), "avg_launch_us": kernels[dom]["avg_us"]}
 
 
+def kernel_source_hash():
+    """SHA-256 over the kernel sources and the C header: measured counter data
+    is only quoted for the build it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2104_00359_amd", "csrc")
+    for f in sorted(x for x in os.listdir(d) if x.endswith((".h", ".hip")) or x == "gen_tables.py"):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "shvis.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of ``kernel`` from rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (scaled by a plain copy of known size), recorded in
+    profiles/traffic.json; None when not measured or when the kernel sources
+    changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            entries = json.load(fh)["entries"]
+    except (OSError, ValueError, KeyError):
+        return None
+    digest = kernel_source_hash()
+    for e in entries:
+        if e.get("workload") == workload and e.get("kernel") == kernel and e.get("source_sha256") == digest:
+            return int(e["bytes_per_launch"])
+    return None
+
+
 def timed(step, stream, warmup, steps, profile):
     """Average milliseconds per step over ``steps`` steps after ``warmup``;
     with ``profile``, the library's per-launch HIP-event report as well."""
@@ -161,6 +197,19 @@ def timed(step, stream, warmup, steps, profile):
         if profile:
             _lib.shv_profile_enable(False)
     return (t1 - t0) * 1e3 / steps, (_lib.shv_profile_report() if profile else None)
+
+
+def copy_calibration(args, dev, stream):
+    if args.copy_mib <= 0:
+        return
+    import torch
+    n = args.copy_mib << 18   # floats
+    src = torch.ones(n, device=dev)
+    dst = torch.empty(n, device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def finish_kernels(kernels):
@@ -218,8 +267,11 @@ def bench_single(args):
             _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
 
     ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
     roof = roofline(kernels, args.steps, lambda name: workmodel.kernel_work(name, n, k, P, S))
+    if roof is not None:
+        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
     cpu = cpu_baseline([sc], k, args.cpu_seconds) if args.cpu_seconds > 0 else None
     return {
         "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
