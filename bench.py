@@ -57,8 +57,8 @@ def parse():
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
                     help="serve: Poisson arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=4.0, help="serve: seconds of arrivals per rate")
-    ap.add_argument("--chunk-pairs", type=int, default=8 << 20, help="serve: pair bound of a request range")
-    ap.add_argument("--step-pairs", type=int, default=64 << 20, help="serve: pair bound of a step")
+    ap.add_argument("--chunk-pairs", type=int, default=32 << 20, help="serve: pair bound of a request range")
+    ap.add_argument("--step-pairs", type=int, default=128 << 20, help="serve: pair bound of a step")
     ap.add_argument("--modes", default="continuous,one_at_a_time", help="serve: scheduler modes to sweep")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device once (a plain copy kernel "

@@ -260,18 +260,35 @@ class Scheduler:
         return sum(len(fin) for _, fin, _ in self._inflight)
 
     def _plan(self):
-        items, finishing, pairs = [], [], 0
-        for req in list(self._active):
+        """One range from each admitted request with work left (arrival order,
+        within the step bound); then, while the bound leaves room, requests
+        extend their range over their next consecutive ranges (a merged range
+        gives the same bits as its parts)."""
+        picked, pairs = [], 0
+        for req in self._active:
             rq = self._ranges[req.rid]
             a, e = rq[0]
             p = (e - a) * req.S
-            if items and self.step_pairs is not None and pairs + p > self.step_pairs:
+            if picked and self.step_pairs is not None and pairs + p > self.step_pairs:
                 break
             rq.popleft()
-            last = not rq
-            items.append((req, a, e, not last))
+            picked.append([req, a, e])
             pairs += p
             self._pending_pairs -= p
+        if self.step_pairs is not None:
+            for it in picked:
+                req = it[0]
+                rq = self._ranges[req.rid]
+                while rq and rq[0][0] == it[2] and pairs + (rq[0][1] - rq[0][0]) * req.S <= self.step_pairs:
+                    a, e = rq.popleft()
+                    p = (e - a) * req.S
+                    it[2] = e
+                    pairs += p
+                    self._pending_pairs -= p
+        items, finishing = [], []
+        for req, a, e in picked:
+            last = not self._ranges[req.rid]
+            items.append((req, a, e, not last))
             if last:
                 finishing.append(req)
                 self._active.remove(req)

@@ -24,7 +24,7 @@ def test_served_in_mix_equals_alone_bitwise():
     pool = [scenegen.scene_random_shell(s, P, S, n) for s, P, S, n in specs]
     inputs = [batch.scene_buffers(sc, dev) for sc in pool]
     ex = serve.GpuExecutor(dev)
-    sched = serve.Scheduler(ex, memory_budget=16 << 30, chunk_pairs=300_000, max_inflight=2,
+    sched = serve.Scheduler(ex, memory_budget=16 << 30, chunk_pairs=300_000, step_pairs=1_500_000, max_inflight=2,
                             record_steps=True).start()
     rng = np.random.default_rng(5)
     picks = rng.integers(0, len(pool), 40)

@@ -148,3 +148,15 @@ def test_admission_window_limits_admitted_work():
     assert s.used == 0
     assert all(len(step) == 1 for step in s.step_log)          # the step bound holds
     assert s.peak_used <= 3 * 100                               # at most ~3 admitted at once
+
+
+def test_ranges_merge_when_the_step_has_room():
+    ex = FakeExecutor(delay=0.002)
+    s = serve.Scheduler(ex, memory_budget=10**9, chunk_pairs=256 * 10, step_pairs=256 * 10 * 4, max_inflight=1,
+                        record_steps=True).start()
+    big = s.submit(_scene(), P=256 * 10, S=10)         # 10 ranges of 256 receivers
+    r = big.result(timeout=10)
+    s.stop(timeout=10)
+    items = [(a, e, d) for step in s.step_log for rid, a, e, d in step if rid == r.rid]
+    assert [(a, e) for a, e, _ in items] == [(0, 1024), (1024, 2048), (2048, 2560)]   # 4 ranges per step
+    assert [d for *_, d in items] == [True, True, False]
