@@ -125,8 +125,9 @@ def kernel_table(prof):
 
 def roofline(kernels, steps, work):
     """Roofline entry of the kernel with the largest total time; ``work(name)``
-    gives its algorithmic flops per step.  achieved = flops per launch /
-    average launch time."""
+    gives its algorithmic flops per step and ``steps`` is the number of steps
+    whose launches were timed.  achieved = flops per launch / average launch
+    time."""
     dom = max(kernels, key=lambda kname: kernels[kname]["total_ms"])
     flops_step, _ = work(dom)
     for name, kv in kernels.items():
@@ -176,9 +177,13 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def timed(step, stream, warmup, steps, profile):
-    """Average milliseconds per step over ``steps`` steps after ``warmup``;
-    with ``profile``, the library's per-launch HIP-event report as well."""
+def timed(step, stream, warmup, steps, profile, every=10):
+    """Average milliseconds per step over ``steps`` steps after ``warmup``.
+    With ``profile``, one step in ``every`` of the timed steps also records a
+    HIP event pair around each of its launches (on the launch stream), and
+    the library's per-kernel report over those sampled steps is returned.
+    Events around every launch would add about 4 us per launch to the timed
+    steps; sampling keeps that to a tenth."""
     import torch
 
     from paper_2104_00359_amd import _lib
@@ -187,16 +192,24 @@ def timed(step, stream, warmup, steps, profile):
             step()
         torch.cuda.synchronize()
         if profile:
-            _lib.shv_profile_enable(True, capacity=400 * steps + 64)
+            _lib.shv_profile_enable(True, capacity=40 * (steps // every + 1) + 64)
+            _lib.shv_profile_enable(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
+            sample = profile and i % every == 0
+            if sample:
+                _lib.shv_profile_enable(True, resume=True)
             step()
+            if sample:
+                _lib.shv_profile_enable(False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if profile:
-            _lib.shv_profile_enable(False)
     return (t1 - t0) * 1e3 / steps, (_lib.shv_profile_report() if profile else None)
+
+
+def sampled_steps(steps, every=10):
+    return (steps + every - 1) // every
 
 
 def copy_calibration(args, dev, stream):
@@ -269,7 +282,7 @@ def bench_single(args):
     ms, prof = timed(step, stream, args.warmup, args.steps, True)
     copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
-    roof = roofline(kernels, args.steps, lambda name: workmodel.kernel_work(name, n, k, P, S))
+    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
     if roof is not None:
         roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
     cpu = cpu_baseline([sc], k, args.cpu_seconds) if args.cpu_seconds > 0 else None
@@ -316,7 +329,7 @@ def bench_batched(args):
 
     # per-kernel times from eager batched steps
     steps_prof = max(args.steps // 4, 5)
-    ms_eager, prof = timed(batched, stream, args.warmup, steps_prof, True)
+    ms_eager, prof = timed(batched, stream, args.warmup, steps_prof, True, every=1)
     ms_seq, _ = timed(sequential, stream, max(args.warmup // 4, 2), max(args.steps // 4, 5), False)
     if args.no_graph:
         ms, mode = ms_eager, "eager batched calls"

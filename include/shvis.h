@@ -244,7 +244,8 @@ shv_status sh_render_batched_backward(const void* table_device, const shv_batch_
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream.  shv_profile_enable(1) starts a new collection (at most
  * `capacity` launches are recorded; later ones are counted but not timed);
- * shv_profile_enable(0) stops recording.  shv_profile_report() must be called
+ * shv_profile_enable(0) pauses recording and shv_profile_enable(2) resumes
+ * it, adding to the current collection (to time a sample of the launches).  shv_profile_report() must be called
  * after the stream has drained: it writes "name count total_ms\n" lines into
  * buf (NUL-terminated, truncated to len) and returns the number of bytes
  * needed. */

@@ -216,8 +216,10 @@ def sh_render_batched_backward(table_device, grid, stream):
            "sh_render_batched_backward")
 
 
-def shv_profile_enable(enable: bool, capacity: int = 4096) -> None:
-    _check(_lib.shv_profile_enable(1 if enable else 0, int(capacity)), "shv_profile_enable")
+def shv_profile_enable(enable: bool, capacity: int = 4096, resume: bool = False) -> None:
+    """Start (or with ``resume`` continue) recording per-launch events; False pauses."""
+    mode = (2 if resume else 1) if enable else 0
+    _check(_lib.shv_profile_enable(mode, int(capacity)), "shv_profile_enable")
 
 
 def shv_profile_report() -> dict:

@@ -695,8 +695,10 @@ shv_status shv_profile_enable(int enable, int32_t capacity) {
     if (e1 != hipSuccess || e2 != hipSuccess) return set_error(SHV_ERR_HIP, "hipEventCreate failed");
     g_prof.push_back(r);
   }
-  g_prof_used = 0;
-  g_prof_untimed.clear();
+  if (enable != 2) {  // 2 resumes the current collection
+    g_prof_used = 0;
+    g_prof_untimed.clear();
+  }
   g_prof_on = true;
   return SHV_OK;
 }
