@@ -165,10 +165,11 @@ def clamped_cosine(l):
 N_GROUPS = 4
 
 
-def output_groups(n, ng=N_GROUPS):
-    """Partition of the N output coefficients of a squaring into ``ng`` groups
-    with balanced cost (FMAs plus the distinct products each group needs),
-    greedy over outputs in decreasing term count.  Deterministic."""
+def adjoint_groups(n, ng=N_GROUPS):
+    """Output groups of the adjoint squaring (one per wave of the four-wave
+    backward kernels; also the canonical grouping of the backward's sums):
+    balanced cost (FMAs plus the distinct products each group needs), greedy
+    over outputs in decreasing term count.  Deterministic."""
     N = n * n
     C = real_gaunt(n)
     terms = {i: set() for i in range(N)}
@@ -190,6 +191,73 @@ def output_groups(n, ng=N_GROUPS):
         pairs[g] |= terms[i]
         fm[g] += len(terms[i])
     return [sorted(x) for x in groups]
+
+
+def forward_groups(n, ng=N_GROUPS):
+    """Output groups of the forward squaring (one per wave of the four-wave
+    forward kernels).  Cost of a group: its FMAs plus the distinct products
+    e_j e_k it needs.  Start from the classes (l odd, m < 0): the selection
+    rules of the real Gaunt coefficients make the products a class needs
+    largely shared within it.  Then take best-improvement single moves while
+    they lower the largest group cost.  Deterministic."""
+    import collections
+    N = n * n
+    C = real_gaunt(n)
+    ft = {i: [] for i in range(N)}
+    at = {m: set() for m in range(N)}
+    for (i, j, k) in C:
+        if j <= k:
+            ft[i].append((j, k))
+        at[j].add((i, k) if i <= k else (k, i))
+    at = {m: sorted(v) for m, v in at.items()}
+    grp = []
+    for i in range(N):
+        l, m = lm(i)
+        grp.append((2 * (l % 2) + (1 if m < 0 else 0)) % ng)
+    fc = [collections.Counter() for _ in range(ng)]
+    ac = [collections.Counter() for _ in range(ng)]
+    fterm, aterm = [0] * ng, [0] * ng
+
+    def add(i, g, sgn):
+        if sgn > 0:
+            fc[g].update(ft[i])
+            ac[g].update(at[i])
+        else:
+            fc[g].subtract(ft[i])
+            ac[g].subtract(at[i])
+            fc[g] += collections.Counter()
+            ac[g] += collections.Counter()
+        fterm[g] += sgn * len(ft[i])
+        aterm[g] += sgn * len(at[i])
+
+    for i in range(N):
+        add(i, grp[i], 1)
+
+    def score():
+        return max(fterm[g] + len(fc[g]) for g in range(ng))
+
+    cur = score()
+    while True:
+        best = None
+        for i in range(N):
+            a = grp[i]
+            for b in range(ng):
+                if b == a:
+                    continue
+                add(i, a, -1)
+                add(i, b, 1)
+                s = score()
+                add(i, b, -1)
+                add(i, a, 1)
+                if s < cur and (best is None or s < best[0]):
+                    best = (s, i, b)
+        if best is None:
+            break
+        cur, i, b = best
+        add(i, grp[i], -1)
+        add(i, b, 1)
+        grp[i] = b
+    return [sorted(i for i in range(N) if grp[i] == g) for g in range(ng)]
 
 
 # ----------------------------------------------------------------- emission
@@ -304,12 +372,14 @@ def emit_gaunt(path):
         # Per-group variants for kernels that split one receiver's squaring
         # over several waves: group g computes only its outputs, with exactly
         # the per-output term order of the full functions above.
-        groups = output_groups(n)
-        gid = [0] * N
-        for g, members in enumerate(groups):
-            for i in members:
-                gid[i] = g
-        L.append(f"static constexpr unsigned char SHV_GRP_{n}[{N}] = {{" + ",".join(map(str, gid)) + "};")
+        groups = forward_groups(n)
+        agroups = adjoint_groups(n)
+        for name, grs in (("SHV_FGRP", groups), ("SHV_GRP", agroups)):
+            gid = [0] * N
+            for g, members in enumerate(grs):
+                for i in members:
+                    gid[i] = g
+            L.append(f"static constexpr unsigned char {name}_{n}[{N}] = {{" + ",".join(map(str, gid)) + "};")
         for g, members in enumerate(groups):
             mem = set(members)
             L.append(f"__device__ __forceinline__ void shv_square_{n}_g{g}(const float* __restrict__ e, float* __restrict__ o) {{")
@@ -331,6 +401,8 @@ def emit_gaunt(path):
                 if i not in touched:
                     L.append(f"  o[{i}] = 0.0f;")
             L.append("}")
+        for g, members in enumerate(agroups):
+            mem = set(members)
             L.append(f"__device__ __forceinline__ void shv_square_adj_{n}_g{g}(const float* __restrict__ ob, const float* __restrict__ e, float* __restrict__ eb) {{")
             touched = set()
             for (i, k) in sorted(upairs):

@@ -79,11 +79,17 @@ SHV_SQG4(8)
 #undef SHV_SQG4
 #undef SHV_SQG
 
+// Output group of coefficient i: in the adjoint squaring (and the canonical
+// grouping of the backward's sums), and in the forward squaring.
 template <int NB>
 __device__ __forceinline__ constexpr int group_of(int i);
-#define SHV_GOF(n) \
-  template <>      \
-  __device__ __forceinline__ constexpr int group_of<n>(int i) { return SHV_GRP_##n[i]; }
+template <int NB>
+__device__ __forceinline__ constexpr int fgroup_of(int i);
+#define SHV_GOF(n)                                                                          \
+  template <>                                                                               \
+  __device__ __forceinline__ constexpr int group_of<n>(int i) { return SHV_GRP_##n[i]; }    \
+  template <>                                                                               \
+  __device__ __forceinline__ constexpr int fgroup_of<n>(int i) { return SHV_FGRP_##n[i]; }
 SHV_GOF(1)
 SHV_GOF(2)
 SHV_GOF(3)
@@ -327,7 +333,7 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
   constexpr int N = NB * NB;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    if (group_of<NB>(i) != G) continue;
+    if (fgroup_of<NB>(i) != G) continue;
     float v = ok ? Fpart[(int64_t)i * P + p] : 0.0f;
     for (int c = 1; c < nchunks; ++c) v += ok ? Fpart[((int64_t)c * N + i) * P + p] : 0.0f;
     X[0][i][lane] = v;
@@ -343,13 +349,13 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
       float* dst = saved + (int64_t)(1 + j * N) * P + p;
 #pragma unroll
       for (int i = 0; i < N; ++i)
-        if (group_of<NB>(i) == G) dst[(int64_t)i * P] = E[i];
+        if (fgroup_of<NB>(i) == G) dst[(int64_t)i * P] = E[i];
     }
     SqGroup<NB, G>::square(E, O);
     const int b = (j + 1) & 1;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) X[b][i][lane] = O[i];
+      if (fgroup_of<NB>(i) == G) X[b][i][lane] = O[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < N; ++i) E[i] = X[b][i][lane];
@@ -360,7 +366,7 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
   if (ok) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) vis[(int64_t)i * P + p] = E[i];
+      if (fgroup_of<NB>(i) == G) vis[(int64_t)i * P + p] = E[i];
   }
   if constexpr (SHADE) {
     float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
