@@ -192,11 +192,16 @@ __device__ __forceinline__ void load_normal(const float* nrm, int64_t P, int64_t
 // ===========================================================================
 // One receiver per lane.
 
+// With SHADE, Ms is block-local LDS of MSupp<NB>::SIZE floats for the staged M.
 template <int NB, bool SHADE>
 __device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, int nchunks, int64_t P, float eps,
                                               int k, float* __restrict__ vis, float* __restrict__ saved,
-                                              const ShadeArgs& sa, int64_t bx) {
+                                              const ShadeArgs& sa, int64_t bx, float* Ms) {
   constexpr int N = NB * NB;
+  if constexpr (SHADE) {
+    stage_M<NB>(sa.M, Ms, threadIdx.x, SHV_BLOCK);
+    __syncthreads();
+  }
   const int64_t p = bx * SHV_BLOCK + threadIdx.x;
   if (p >= P) return;
   float E[N], O[N];
@@ -229,7 +234,7 @@ __device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, i
     float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
     load_normal(sa.nrm, P, p, true, nx, ny, nz);
     transfer<NB>(nx, ny, nz, H, ux, uy, uz);
-    sa.rad[p] = sa.alb[p] * shade_value<NB, false>(E, H, sa.M, 0.0f, Hb);
+    sa.rad[p] = sa.alb[p] * shade_value<NB, false>(E, H, Ms, 0.0f, Hb);
   }
 }
 
@@ -237,18 +242,27 @@ template <int NB, bool SHADE>
 __global__ __launch_bounds__(SHV_BLOCK) void k_exp_fwd(const float* __restrict__ Fpart, int nchunks, int64_t P,
                                                        float eps, int k, float* __restrict__ vis,
                                                        float* __restrict__ saved, ShadeArgs sa) {
-  exp_fwd1_item<NB, SHADE>(Fpart, nchunks, P, eps, k, vis, saved, sa, blockIdx.x);
+  if constexpr (SHADE) {
+    __shared__ float Ms[MSupp<NB>::SIZE];
+    exp_fwd1_item<NB, SHADE>(Fpart, nchunks, P, eps, k, vis, saved, sa, blockIdx.x, Ms);
+  } else {
+    exp_fwd1_item<NB, SHADE>(Fpart, nchunks, P, eps, k, vis, saved, sa, blockIdx.x, nullptr);
+  }
 }
 
 template <int NB, bool SHADE>
 __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, const float* __restrict__ vis,
                                               const float* __restrict__ saved, int64_t P, float eps, int k,
                                               float* __restrict__ Wout, const ShadeArgs& sa, int64_t bx,
-                                              LightTile* LTp) {
+                                              LightTile* LTp, float* Ms) {
   constexpr int N = NB * NB;
   const int64_t p = bx * SHV_BLOCK + threadIdx.x;
   const bool ok = p < P;
   if (!SHADE && !ok) return;  // no barriers in the unfused kernel
+  if constexpr (SHADE) {
+    stage_M<NB>(sa.M, Ms, threadIdx.x, SHV_BLOCK);
+    __syncthreads();
+  }
   float Eb[N], E[N], T[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) E[i] = ok ? vis[(int64_t)i * P + p] : 0.0f;  // V
@@ -263,7 +277,7 @@ __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, con
     const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
     const float bb = ok ? gIn[p] : 0.0f;
     const float w = bb * (ok ? sa.alb[p] : 0.0f);
-    const float s = shade_value<NB, true>(E, H, sa.M, w, Hb);
+    const float s = shade_value<NB, true>(E, H, Ms, w, Hb);
     if (ok && sa.gA) sa.gA[p] = bb * s;
     if (ok && sa.gN) {
       float gx, gy, gz;
@@ -286,7 +300,7 @@ __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, con
     }
     if (!ok) return;  // no barriers below
 #pragma unroll
-    for (int j = 0; j < N; ++j) Eb[j] = vbar_entry<NB>(j, H, sa.M, w);
+    for (int j = 0; j < N; ++j) Eb[j] = vbar_entry<NB>(j, H, Ms, w);
   } else {
 #pragma unroll
     for (int i = 0; i < N; ++i) Eb[i] = gIn[(int64_t)i * P + p];
@@ -316,9 +330,10 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_bwd(const float* __restrict__
                                                        float* __restrict__ Wout, ShadeArgs sa) {
   if constexpr (SHADE) {
     __shared__ LightTile LT;
-    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, &LT);
+    __shared__ float Ms[MSupp<NB>::SIZE];
+    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, &LT, Ms);
   } else {
-    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, nullptr);
+    exp_bwd1_item<NB, SHADE>(gIn, vis, saved, P, eps, k, Wout, sa, blockIdx.x, nullptr, nullptr);
   }
 }
 
@@ -369,10 +384,15 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
       if (fgroup_of<NB>(i) == G) vis[(int64_t)i * P + p] = E[i];
   }
   if constexpr (SHADE) {
+    // After the last barrier above every wave has read its final squares:
+    // the other exchange buffer is free for the staged M.
+    float* Ms = &X[(k + 1) & 1][0][0];
+    stage_M<NB>(sa.M, Ms, G * 64 + lane, SHV_BLOCK);
     float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
     load_normal(sa.nrm, P, p, ok, nx, ny, nz);
     transfer<NB>(nx, ny, nz, H, ux, uy, uz);
-    Bx[G][lane] = shade_partial<NB, G, false>(E, H, sa.M, 0.0f, Hb);
+    __syncthreads();
+    Bx[G][lane] = shade_partial<NB, G, false>(E, H, Ms, 0.0f, Hb);
     __syncthreads();
     if (G == 0 && ok) sa.rad[p] = sa.alb[p] * (((Bx[0][lane] + Bx[1][lane]) + Bx[2][lane]) + Bx[3][lane]);
   }
@@ -414,7 +434,8 @@ struct Bwd4Shared {
 };
 
 template <int NB, int G, bool SHADE>
-__device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Shared& sh, LightTile& LT, int64_t bx,
+__device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Shared& sh, LightTile& LT, float* Ms,
+                                              int64_t bx,
                                               int lane, int64_t p, bool ok, const float* __restrict__ gIn,
                                               const float* __restrict__ vis, const float* __restrict__ saved,
                                               int64_t P, float eps, int k, float* __restrict__ Wout,
@@ -438,10 +459,12 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     sh.Cb[G][lane] = part;
     __syncthreads();
   } else {
-    // V from the group loads; then the shading adjoint split over the waves
+    // V from the group loads, M staged; then the shading adjoint split over
+    // the waves
 #pragma unroll
     for (int i = 0; i < N; ++i)
       if (group_of<NB>(i) == G) X[0][i][lane] = ok ? vis[(int64_t)i * P + p] : 0.0f;
+    stage_M<NB>(sa.M, Ms, G * 64 + lane, SHV_BLOCK);
     __syncthreads();
     float V[N], H[N], Hb[N], nx, ny, nz, ux, uy, uz;
 #pragma unroll
@@ -450,7 +473,7 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
     const float bb = ok ? gIn[p] : 0.0f;
     const float w = bb * (ok ? sa.alb[p] : 0.0f);
-    sh.Sx[G][lane] = shade_partial<NB, G, true>(V, H, sa.M, w, Hb);
+    sh.Sx[G][lane] = shade_partial<NB, G, true>(V, H, Ms, w, Hb);
     {
       int kk = 0;
 #pragma unroll
@@ -467,7 +490,7 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       if (group_of<NB>(j) != G) continue;
-      const float vb = vbar_entry<NB>(j, H, sa.M, w);
+      const float vb = vbar_entry<NB>(j, H, Ms, w);
       part = fmaf(vb, V[j], part);
       X[1][j][lane] = vb;
     }
@@ -501,12 +524,26 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     E[i] = X[0][i][lane] / ec;  // E_0 when k = 0; overwritten otherwise
   }
   const float cbar = ((sh.Cb[0][lane] + sh.Cb[1][lane]) + sh.Cb[2][lane]) + sh.Cb[3][lane];
-  for (int j = k - 1; j >= 0; --j) {
-    __syncthreads();  // everyone has read X[0] / X[1] of the previous step
-    const float* src = saved + (int64_t)(1 + j * N) * P + p;
+  // This wave's group of E_j is loaded one step ahead, so the loads are in
+  // flight during the previous step's product (barriers wait on LDS only).
+  float pre[N];
+  if (k > 0) {
+    const float* src = saved + (int64_t)(1 + (k - 1) * N) * P + p;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) X[0][i][lane] = ok ? src[(int64_t)i * P] : 0.0f;
+      if (group_of<NB>(i) == G) pre[i] = ok ? src[(int64_t)i * P] : 0.0f;
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    __syncthreads();  // everyone has read X[0] / X[1] of the previous step
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (group_of<NB>(i) == G) X[0][i][lane] = pre[i];
+    if (j > 0) {
+      const float* src = saved + (int64_t)(1 + (j - 1) * N) * P + p;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (group_of<NB>(i) == G) pre[i] = ok ? src[(int64_t)i * P] : 0.0f;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < N; ++i) E[i] = X[0][i][lane];
@@ -527,6 +564,7 @@ struct Exp4BwdShared {
   float X[2][NB * NB][64];
   Bwd4Shared sh;
   LightTile LT;
+  float Ms[MSupp<NB>::SIZE];  // staged M (fused shading adjoint)
 };
 
 template <int NB, bool SHADE>
@@ -538,11 +576,11 @@ __device__ __forceinline__ void exp_bwd4_item(const float* __restrict__ gIn, con
   const int64_t p = bx * 64 + lane;
   const bool ok = p < P;
   switch (wave) {
-    case 0: exp_bwd_group<NB, 0, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
-    case 1: exp_bwd_group<NB, 1, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
-    case 2: exp_bwd_group<NB, 2, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 0: exp_bwd_group<NB, 0, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 1: exp_bwd_group<NB, 1, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 2: exp_bwd_group<NB, 2, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
     default:
-      exp_bwd_group<NB, 3, SHADE>(S.X, S.sh, S.LT, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa);
+      exp_bwd_group<NB, 3, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa);
       break;
   }
 }
@@ -596,7 +634,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_fwd(const char* __restr
   const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
   if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
-  else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx);
+  else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, &sh.X[0][0][0]);
 }
 
 template <int NB, bool FOUR>
@@ -610,7 +648,7 @@ __global__ __launch_bounds__(SHV_BLOCK, FOUR ? 2 : 1) void k_batch_exp_bwd(const
   const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
   if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
-  else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT);
+  else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT, sh.Ms);
 }
 
 template <int NB>

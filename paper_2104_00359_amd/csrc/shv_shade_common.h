@@ -1,6 +1,10 @@
 // Shading pieces shared by the separate shading kernels and the fused render
 // kernels (Eq. 8 with the clamped-cosine transfer of Eqs. 10-11).
 //
+// M(L) is read from a block-local LDS copy of its transfer-support columns
+// (stage_M), so the many uniform reads of the shading products are LDS
+// broadcasts rather than scalar-cache loads.
+//
 // Canonical summation orders (every kernel uses these, so the separate and
 // fused paths and all kernel variants give bit-identical results):
 //   * B = a * sum_{g=0..3} ( sum over support columns kk = g, g+4, ... of
@@ -26,6 +30,7 @@ struct MTab;
     static __device__ __forceinline__ const int* lptr() { return shv_ltab_ptr_##n; }           \
     static __device__ __forceinline__ const unsigned short* lent() { return shv_ltab_ent_##n; } \
     static __device__ __forceinline__ const float* lval() { return shv_ltab_val_##n; }         \
+    static __device__ __forceinline__ int supp(int kk) { return SHV_HSUPP_##n[kk]; }           \
     static constexpr int HS = SHV_HSUPP_COUNT_##n;                                             \
   };
 SHV_MTAB(1)
@@ -53,6 +58,28 @@ __device__ __forceinline__ void build_M_range(const float* __restrict__ L, float
   }
 }
 
+// LDS copy of the support columns of M: support column kk = 4c + g of row j
+// at Ms[(g * N + j) * CPG + c], so wave group g's columns are contiguous.
+template <int NB>
+struct MSupp {
+  static constexpr int N = NB * NB;
+  static constexpr int CPG = (MTab<NB>::HS + 3) / 4;
+  static constexpr int SIZE = 4 * N * CPG;
+  static __device__ __forceinline__ constexpr int at(int j, int kk) { return ((kk & 3) * N + j) * CPG + (kk >> 2); }
+};
+
+// Fill Ms from M (global) with the threads tid = 0 .. nthreads-1 of a block;
+// the caller synchronises before reading it.
+template <int NB>
+__device__ __forceinline__ void stage_M(const float* __restrict__ M, float* Ms, int tid, int nthreads) {
+  constexpr int N = NB * NB, CPG = MSupp<NB>::CPG, HS = MTab<NB>::HS;
+  for (int e = tid; e < MSupp<NB>::SIZE; e += nthreads) {
+    const int c = e % CPG, j = (e / CPG) % N, g = e / (CPG * N);
+    const int kk = 4 * c + g;
+    Ms[e] = kk < HS ? M[j * N + MTab<NB>::supp(kk)] : 0.0f;
+  }
+}
+
 // The clamped cosine's odd bands above 1 vanish.
 __device__ __forceinline__ constexpr bool h_support(int l) { return l <= 2 || (l % 2) == 0; }
 
@@ -75,10 +102,11 @@ __device__ __forceinline__ float transfer(float nx, float ny, float nz, float (&
 }
 
 // Partial g of sum_k H_k t_k over support columns kk = g, g + 4, ...; also
-// Hb_k = w t_k A_l for those columns (the cotangent of y_k(n_hat)).
+// Hb_k = w t_k A_l for those columns (the cotangent of y_k(n_hat)).  Ms is
+// the staged copy of M (stage_M).
 template <int NB, int G, bool ADJ>
 __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const float (&H)[NB * NB],
-                                               const float* __restrict__ M, float w, float (&Hb)[NB * NB]) {
+                                               const float* Ms, float w, float (&Hb)[NB * NB]) {
   constexpr int N = NB * NB;
   float s = 0.0f;
   int kk = 0;
@@ -88,10 +116,11 @@ __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const 
 #pragma unroll
     for (int m = -l; m <= l; ++m) {
       const int k = idx(l, m);
-      if ((kk++ & 3) != G) continue;
+      const int col = kk++;
+      if ((col & 3) != G) continue;
       float t = 0.0f;
 #pragma unroll
-      for (int j = 0; j < N; ++j) t = fmaf(M[j * N + k], V[j], t);
+      for (int j = 0; j < N; ++j) t = fmaf(Ms[MSupp<NB>::at(j, col)], V[j], t);
       s = fmaf(H[k], t, s);
       if (ADJ) Hb[k] = w * t * SHV_AHAT[l];
     }
@@ -102,7 +131,7 @@ __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const 
 // V^T M H in the canonical order (and the y_k cotangents when ADJ).
 template <int NB, bool ADJ>
 __device__ __forceinline__ float shade_value(const float (&V)[NB * NB], const float (&H)[NB * NB],
-                                             const float* __restrict__ M, float w, float (&Hb)[NB * NB]) {
+                                             const float* M, float w, float (&Hb)[NB * NB]) {
   if (ADJ) {
 #pragma unroll
     for (int i = 0; i < NB * NB; ++i) Hb[i] = 0.0f;
@@ -114,16 +143,16 @@ __device__ __forceinline__ float shade_value(const float (&V)[NB * NB], const fl
   return ((s0 + s1) + s2) + s3;
 }
 
-// Vbar_j = w sum_k M_jk H_k over the support (k in index order).
+// Vbar_j = w sum_k M_jk H_k over the support (k in index order; Ms staged).
 template <int NB>
-__device__ __forceinline__ float vbar_entry(int j, const float (&H)[NB * NB], const float* __restrict__ M, float w) {
-  constexpr int N = NB * NB;
+__device__ __forceinline__ float vbar_entry(int j, const float (&H)[NB * NB], const float* Ms, float w) {
   float t = 0.0f;
+  int kk = 0;
 #pragma unroll
   for (int l = 0; l < NB; ++l) {
     if (!h_support(l)) continue;
 #pragma unroll
-    for (int m = -l; m <= l; ++m) t = fmaf(M[j * N + idx(l, m)], H[idx(l, m)], t);
+    for (int m = -l; m <= l; ++m) t = fmaf(Ms[MSupp<NB>::at(j, kk++)], H[idx(l, m)], t);
   }
   return w * t;
 }

@@ -33,6 +33,9 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_fwd(const float* __restrict
                                                          const float* __restrict__ alb, const float* __restrict__ M,
                                                          int64_t P, float* __restrict__ rad) {
   constexpr int N = NB * NB;
+  __shared__ float Ms[MSupp<NB>::SIZE];
+  stage_M<NB>(M, Ms, threadIdx.x, SHV_BLOCK);
+  __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   if (p >= P) return;
   float V[N], H[N], Hb[N];
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_fwd(const float* __restrict
   for (int i = 0; i < N; ++i) V[i] = vis[(int64_t)i * P + p];
   float ux, uy, uz;
   transfer<NB>(nrm[p], nrm[P + p], nrm[2 * P + p], H, ux, uy, uz);
-  rad[p] = alb[p] * shade_value<NB, false>(V, H, M, 0.0f, Hb);
+  rad[p] = alb[p] * shade_value<NB, false>(V, H, Ms, 0.0f, Hb);
 }
 
 // One receiver per lane, 256 receivers per block (4 tiles of 64).
@@ -52,6 +55,9 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict
                                                          float* __restrict__ gA, float* __restrict__ Lpart) {
   constexpr int N = NB * NB;
   __shared__ LightTile T;
+  __shared__ float Ms[MSupp<NB>::SIZE];
+  stage_M<NB>(M, Ms, threadIdx.x, SHV_BLOCK);
+  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   const bool ok = p < P;
@@ -62,12 +68,12 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict
   const float inv = transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
   const float bb = ok ? gB[p] : 0.0f;
   const float w = bb * (ok ? alb[p] : 0.0f);
-  const float s = shade_value<NB, true>(V, H, M, w, Hb);
+  const float s = shade_value<NB, true>(V, H, Ms, w, Hb);
   if (ok) {
     if (gA) gA[p] = bb * s;
     if (gV) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) gV[(int64_t)j * P + p] = vbar_entry<NB>(j, H, M, w);
+      for (int j = 0; j < N; ++j) gV[(int64_t)j * P + p] = vbar_entry<NB>(j, H, Ms, w);
     }
     if (gN) {
       float gx, gy, gz;
