@@ -165,38 +165,11 @@ def clamped_cosine(l):
 N_GROUPS = 4
 
 
-def adjoint_groups(n, ng=N_GROUPS):
-    """Output groups of the adjoint squaring (one per wave of the four-wave
-    backward kernels; also the canonical grouping of the backward's sums):
-    balanced cost (FMAs plus the distinct products each group needs), greedy
-    over outputs in decreasing term count.  Deterministic."""
-    N = n * n
-    C = real_gaunt(n)
-    terms = {i: set() for i in range(N)}
-    for (i, j, k) in C:
-        if j <= k:
-            terms[i].add((j, k))
-    order = sorted(range(N), key=lambda i: (-len(terms[i]), i))
-    groups = [[] for _ in range(ng)]
-    pairs = [set() for _ in range(ng)]
-    fm = [0] * ng
-    for i in order:
-        best = None
-        for g in range(ng):
-            c = fm[g] + len(terms[i]) + len(pairs[g] | terms[i])
-            if best is None or c < best[0]:
-                best = (c, g)
-        g = best[1]
-        groups[g].append(i)
-        pairs[g] |= terms[i]
-        fm[g] += len(terms[i])
-    return [sorted(x) for x in groups]
-
-
-def forward_groups(n, ng=N_GROUPS):
-    """Output groups of the forward squaring (one per wave of the four-wave
-    forward kernels).  Cost of a group: its FMAs plus the distinct products
-    e_j e_k it needs.  Start from the classes (l odd, m < 0): the selection
+def parity_groups(n, adjoint, ng=N_GROUPS):
+    """Output groups of a squaring (one per wave of the four-wave kernels).
+    Cost of a group: forward = its FMAs plus the distinct products e_j e_k it
+    needs; adjoint = its terms plus twice the distinct symmetric products
+    ob_i e_k it needs.  Start from the classes (l odd, m < 0): the selection
     rules of the real Gaunt coefficients make the products a class needs
     largely shared within it.  Then take best-improvement single moves while
     they lower the largest group cost.  Deterministic."""
@@ -234,6 +207,8 @@ def forward_groups(n, ng=N_GROUPS):
         add(i, grp[i], 1)
 
     def score():
+        if adjoint:
+            return max(aterm[g] + 2 * len(ac[g]) for g in range(ng))
         return max(fterm[g] + len(fc[g]) for g in range(ng))
 
     cur = score()
@@ -258,6 +233,15 @@ def forward_groups(n, ng=N_GROUPS):
         add(i, b, 1)
         grp[i] = b
     return [sorted(i for i in range(N) if grp[i] == g) for g in range(ng)]
+
+
+def forward_groups(n, ng=N_GROUPS):
+    return parity_groups(n, False, ng)
+
+
+def adjoint_groups(n, ng=N_GROUPS):
+    """Also the canonical grouping of the backward's sums."""
+    return parity_groups(n, True, ng)
 
 
 # ----------------------------------------------------------------- emission
