@@ -73,7 +73,9 @@ def make_scene(name):
         desc = "body-like scene: 20000 receivers on 24 capsules x 128 spheres, 8 bands, k=4, fwd+bwd"
     elif name == "gbuffer":
         sc = scenegen.scene_gbuffer()
-        desc = "G-buffer scene: 512x512 receivers x 256 spheres, 8 bands, k=4, fwd+bwd"
+        sc["grad_radiance"] = scenegen.np.random.default_rng(1).standard_normal(
+            sc["points"].shape[0]).astype("float32")
+        desc = "G-buffer scene: 512x512 receivers x 256 spheres, 8 bands, k=4, fwd+bwd (cotangent w ~ N(0,1))"
     else:
         sc = scenegen.scene_icosphere_shell()
         sc["grad_radiance"] = scenegen.np.random.default_rng(1).standard_normal(

@@ -67,7 +67,8 @@ typedef int32_t shv_status;
  * 0 or one of the SHV_FLAG_* values below (they select a kernel variant,
  * never the result: both variants are bitwise identical). */
 #define SHV_FLAG_EXP_ONE_WAVE 1u   /* exponential: one receiver per lane, one wave per 64 receivers */
-#define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves */
+#define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves
+                                      (the default; both layouts give identical bits) */
 typedef struct shv_params {
   int32_t n_bands;
   int32_t n_squarings;

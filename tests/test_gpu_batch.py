@@ -13,11 +13,11 @@ pytestmark = pytest.mark.gpu
 KEYS = ["V", "B", "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light"]
 
 # (seed, P, S, n, k, flags, outputs passed as NULL): mixed band counts, both
-# exponential layouts (P >= 65,536 selects the one-wave layout by default),
+# exponential layouts (flags 1 forces the one-wave layout, 2 the four-wave one),
 # empty scenes, ragged sizes and partial gradient requests.
 MIX = [
     (11, 3000, 40, 8, 4, 0, ()),
-    (12, 70000, 20, 4, 4, 0, ()),
+    (12, 70000, 20, 4, 4, 1, ()),
     (13, 777, 37, 6, 2, 0, ()),
     (14, 0, 5, 5, 4, 0, ()),
     (15, 130, 0, 3, 4, 0, ()),

@@ -98,8 +98,9 @@ def _fake_scene(L, P, S, n, k=4, flags=0, base=1 << 40):
 def test_batch_table_packing_and_grid(L):
     """Host-side packing: block counts per group follow the single-scene
     launch shapes (exponential: 64 receivers per block in the four-wave
-    layout, 256 in the one-wave layout, picked by P and flags)."""
-    scenes = [_fake_scene(L, 3000, 40, 8), _fake_scene(L, 70000, 20, 4), _fake_scene(L, 777, 37, 8),
+    layout, the default, and 256 in the one-wave layout selected by flags)."""
+    scenes = [_fake_scene(L, 3000, 40, 8), _fake_scene(L, 70000, 20, 4, flags=L.SHV_FLAG_EXP_ONE_WAVE),
+              _fake_scene(L, 777, 37, 8),
               _fake_scene(L, 0, 5, 5), _fake_scene(L, 5000, 100, 8, flags=L.SHV_FLAG_EXP_ONE_WAVE)]
     n = len(scenes)
     buf = (ctypes.c_uint8 * L.shv_batch_table_bytes(n))()
