@@ -346,13 +346,21 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
                                               int k, float* __restrict__ vis, float* __restrict__ saved,
                                               const ShadeArgs& sa) {
   constexpr int N = NB * NB;
+  // Sphere-chunk partials of this wave's group, summed in chunk order; the
+  // loads of one chunk are issued together.
+  float F[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (fgroup_of<NB>(i) != G) continue;
-    float v = ok ? Fpart[(int64_t)i * P + p] : 0.0f;
-    for (int c = 1; c < nchunks; ++c) v += ok ? Fpart[((int64_t)c * N + i) * P + p] : 0.0f;
-    X[0][i][lane] = v;
+  for (int i = 0; i < N; ++i)
+    if (fgroup_of<NB>(i) == G) F[i] = ok ? Fpart[(int64_t)i * P + p] : 0.0f;
+  for (int c = 1; c < nchunks; ++c) {
+    const float* src = Fpart + (int64_t)c * N * P + p;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (fgroup_of<NB>(i) == G) F[i] += ok ? src[(int64_t)i * P] : 0.0f;
   }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (fgroup_of<NB>(i) == G) X[0][i][lane] = F[i];
   __syncthreads();
   float E[N], O[N];
 #pragma unroll
