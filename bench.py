@@ -395,8 +395,8 @@ def bench_serve(args):
     results = {m: [] for m in args.modes.split(",")}
     for mode in results:
         for rate in rates:
-            if mode == "continuous":
-                ex = serve.GpuExecutor(dev)
+            if mode in ("continuous", "continuous_graph"):
+                ex = serve.GpuExecutor(dev, graphs=mode == "continuous_graph")
                 sched = serve.Scheduler(ex, budget, chunk_pairs=args.chunk_pairs, step_pairs=args.step_pairs,
                                         max_inflight=2, keep_results=False, admit_ahead=4 * args.step_pairs)
             else:

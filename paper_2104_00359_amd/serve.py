@@ -88,12 +88,78 @@ class Executor:
         pass
 
 
+def _round_up_pow2(x: int) -> int:
+    return 0 if x <= 0 else 1 << (int(x) - 1).bit_length()
+
+
+class StepGraphs:
+    """Captured graphs of the batched forward + backward, one per launch shape.
+
+    The graph is launched with per-group block counts that only grow (the
+    power of two at or above the largest count seen so far), so a new graph
+    is captured only when some group outgrows its capacity; each graph has a
+    device table buffer of its own, into which a step uploads its table (on
+    the same stream, so after the previous replay) before replaying.  Blocks
+    beyond a group's work exit at once, so one graph serves every table that
+    fits its grid."""
+
+    def __init__(self, device, stream, max_records: int = 1024):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+        self.max_records = max_records
+        self.capacity = _lib.shv_batch_table_bytes(max_records)
+        self.cache = {}
+        self.captures = 0
+        self.cap = [0] * 28   # pair[9], exp[0][9], exp[1][9], finalize
+
+    def _key(self, grid):
+        cur = list(grid.pair) + list(grid.exp[0]) + list(grid.exp[1]) + [grid.finalize]
+        self.cap = [max(c, _round_up_pow2(x)) for c, x in zip(self.cap, cur)]
+        return tuple(self.cap)
+
+    def run(self, table_host, grid, n_records: int) -> bool:
+        """Enqueue one step; False when the table is larger than the graphs'
+        table buffers (the caller then launches eagerly)."""
+        torch = self.torch
+        if n_records > self.max_records:
+            return False
+        key = self._key(grid)
+        ent = self.cache.get(key)
+        if ent is None:
+            buf = torch.zeros(self.capacity, dtype=torch.uint8, device=self.device)
+            cap = _lib.shv_batch_grid()
+            for i in range(9):
+                cap.pair[i] = key[i]
+                cap.exp[0][i] = key[9 + i]
+                cap.exp[1][i] = key[18 + i]
+            cap.finalize = key[27]
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize(self.device)
+            with torch.cuda.graph(g, stream=self.stream, capture_error_mode="thread_local"):
+                h = self.stream.cuda_stream
+                _lib.sh_render_batched_forward(buf, cap, h)
+                _lib.sh_render_batched_backward(buf, cap, h)
+            ent = (g, buf)
+            self.cache[key] = ent
+            self.captures += 1
+        g, buf = ent
+        n = table_host.numel()
+        with torch.cuda.stream(self.stream):
+            buf[:n].copy_(table_host, non_blocking=True)
+            g.replay()
+        return True
+
+
 class GpuExecutor(Executor):
     """Steps as batched library calls on one stream (default priority).
-    With ``single_scene`` a step holding one whole request goes through the
-    single-scene entry points instead (the one-request-at-a-time baseline)."""
+    With ``graphs`` each step replays a captured graph of the batched calls
+    (StepGraphs).  With ``single_scene`` a step holding one whole request goes
+    through the single-scene entry points instead (the one-request-at-a-time
+    baseline)."""
 
-    def __init__(self, device, stream=None, single_scene: bool = False):
+    def __init__(self, device, stream=None, single_scene: bool = False, graphs: bool = False):
         import torch
 
         from .ops import ensure_init
@@ -102,6 +168,7 @@ class GpuExecutor(Executor):
         ensure_init(self.device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.single_scene = single_scene
+        self.graphs = StepGraphs(self.device, self.stream) if graphs else None
 
     def footprint(self, req):
         return req.scene.device_bytes()
@@ -125,9 +192,19 @@ class GpuExecutor(Executor):
             tab = None
         else:
             recs = [req.scene.record(a, e, defer) for req, a, e, defer in items]
-            tab = Table(recs, self.device, st)
-            tab.forward(st)
-            tab.backward(st)
+            if self.graphs is not None:
+                host = torch.empty(_lib.shv_batch_table_bytes(len(recs)), dtype=torch.uint8, pin_memory=True)
+                _lib.shv_batch_table_build(recs, host)
+                grid = _lib.shv_batch_table_grid(host)
+                tab = host   # keeps the pinned source alive until the step completes
+                if not self.graphs.run(host, grid, len(recs)):
+                    tab = Table(recs, self.device, st)
+                    tab.forward(st)
+                    tab.backward(st)
+            else:
+                tab = Table(recs, self.device, st)
+                tab.forward(st)
+                tab.backward(st)
         ev = torch.cuda.Event()
         ev.record(st)
         return ev, tab

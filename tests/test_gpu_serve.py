@@ -16,14 +16,15 @@ pytestmark = pytest.mark.gpu
 KEYS = ["V", "B", "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light"]
 
 
-def test_served_in_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graphs"])
+def test_served_in_mix_equals_alone_bitwise(graphs):
     from paper_2104_00359_amd import batch, serve
     dev = torch.device("cuda", 0)
     specs = [(90, 20000, 64, 8), (91, 70000, 16, 4), (92, 3000, 40, 6), (93, 800, 100, 8), (94, 5000, 32, 5),
              (95, 256, 7, 3)]
     pool = [scenegen.scene_random_shell(s, P, S, n) for s, P, S, n in specs]
     inputs = [batch.scene_buffers(sc, dev) for sc in pool]
-    ex = serve.GpuExecutor(dev)
+    ex = serve.GpuExecutor(dev, graphs=graphs)
     sched = serve.Scheduler(ex, memory_budget=16 << 30, chunk_pairs=300_000, step_pairs=1_500_000, max_inflight=2,
                             record_steps=True).start()
     rng = np.random.default_rng(5)
@@ -34,7 +35,8 @@ def test_served_in_mix_equals_alone_bitwise():
         time.sleep(rng.exponential(0.0005))
     reqs = [f.result(timeout=120) for f in futs]
     sched.stop(timeout=30)
-    print(f"{sched.steps} steps; widest step {max(len(s) for s in sched.step_log)} ranges", flush=True)
+    print(f"{sched.steps} steps; widest step {max(len(s) for s in sched.step_log)} ranges"
+          + (f"; {ex.graphs.captures} graphs captured" if graphs else ""), flush=True)
     assert any(len(step) > 1 for step in sched.step_log)                   # requests shared steps
     assert any(d for step in sched.step_log for *_, d in step)              # some were split into ranges
     alone = {}
