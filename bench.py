@@ -428,7 +428,7 @@ def bench_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this benchmark runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the single-GPU figure is whole-job throughput).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched64":
