@@ -581,7 +581,7 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     b.fin_cols_l = in.grad_light ? (int32_t)N : 0;
     b.n_pair = in.P > 0 ? b.range_tiles * sp.nchunks : 0;
     b.n_exp = in.P > 0 ? (r1 + eb - 1) / eb - b.exp_block0 : 0;
-    b.n_fin = in.defer_reductions ? 0 : (int64_t)b.fin_pts + b.fin_cols_s + b.fin_cols_l;
+    b.n_fin = in.defer_reductions ? 0 : (int64_t)b.fin_pts + (b.fin_cols_s + 15) / 16 + (b.fin_cols_l + 15) / 16;
     const int lay = b.four_waves;
     b.off_pair = h.total_pair[nb];
     b.off_exp = h.total_exp[lay][nb];

@@ -49,7 +49,7 @@ struct BatchScene {
   uint32_t flags;
   int32_t nchunks, chunk;      // sphere split of the pair kernels
   int32_t four_waves;          // exponential layout
-  int32_t fin_pts, fin_cols_s, fin_cols_l;
+  int32_t fin_pts, fin_cols_s, fin_cols_l;  // closing reductions: point blocks, sphere / lighting columns
   int64_t pair_tiles;          // ceil(P / 64): receiver tiles of the whole scene
   int64_t exp_blocks;          // exponential blocks of the whole scene
   int64_t tile0, range_tiles;  // receiver tiles of this call's range

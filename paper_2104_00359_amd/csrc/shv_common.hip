@@ -63,52 +63,68 @@ hipError_t launch_sum_chunks(const float* part, int nchunks, int64_t len, float*
   return hipGetLastError();
 }
 
-// out[c] = sum_r part[r * cols + c]: the block's threads sum a fixed stride of
-// rows (batches of independent loads), then a fixed-shape tree in LDS.
-__device__ __forceinline__ void reduce_column(const float* __restrict__ part, int rows, int cols, int c,
-                                              float* __restrict__ out, float* buf) {
+// out[c] = sum_r part[r * cols + c] for the 16 columns c = 16 cb .. 16 cb + 15.
+// Thread t owns column 16 cb + (t % 16) and row group g = t / 16 (16 groups);
+// it sums rows g, g + 16, g + 32, ... in increasing order (loads issued 8 rows
+// at a time; each wave reads four contiguous 64-byte row segments), then the
+// 16 group partials of a column are added in group order.  The canonical
+// order of every column reduction (receiver tiles -> sphere and lighting
+// gradients).
+constexpr int kColsPerBlock = 16;
+constexpr int kRowGroups = SHV_BLOCK / kColsPerBlock;
+
+__device__ __forceinline__ void reduce_columns(const float* __restrict__ part, int rows, int cols, int cb,
+                                               float* __restrict__ out, float* buf) {
+  const int l = threadIdx.x % kColsPerBlock, g = threadIdx.x / kColsPerBlock;
+  const int c = cb * kColsPerBlock + l;
   float a = 0.0f;
-  for (int r0 = threadIdx.x; r0 < rows; r0 += 4 * SHV_BLOCK) {
-    float v[4];
+  if (c < cols) {
+    int r = g;
+    for (; r + 7 * kRowGroups < rows; r += 8 * kRowGroups) {
+      float v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + u * SHV_BLOCK;
-      v[u] = r < rows ? part[(int64_t)r * cols + c] : 0.0f;
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(r + u * kRowGroups) * cols + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a += v[u];
+    for (; r < rows; r += kRowGroups) a += part[(int64_t)r * cols + c];
   }
   buf[threadIdx.x] = a;
   __syncthreads();
+  if (g == 0 && c < cols) {
+    float t = buf[l];
 #pragma unroll
-  for (int w = SHV_BLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-    __syncthreads();
+    for (int q = 1; q < kRowGroups; ++q) t += buf[q * kColsPerBlock + l];
+    out[c] = t;
   }
-  if (threadIdx.x == 0) out[c] = buf[0];
 }
+
+// Blocks of kColsPerBlock columns.
+__host__ __device__ __forceinline__ int column_blocks(int cols) { return (cols + kColsPerBlock - 1) / kColsPerBlock; }
 
 __global__ __launch_bounds__(SHV_BLOCK) void k_reduce_rows(const float* __restrict__ part, int rows, int cols,
                                                            float* __restrict__ out) {
   __shared__ float buf[SHV_BLOCK];
-  reduce_column(part, rows, cols, blockIdx.x, out, buf);
+  reduce_columns(part, rows, cols, blockIdx.x, out, buf);
 }
 
 // All reductions that close a backward pass, in one launch: blocks
-// [0, nb_pts) sum the receiver-gradient chunks, the next 4S blocks reduce the
-// sphere-gradient columns, the last N blocks the lighting-gradient columns.
+// [0, nb_pts) sum the receiver-gradient chunks, the next blocks reduce the
+// 4S sphere-gradient columns (16 per block), the last ones the N
+// lighting-gradient columns.
 __device__ __forceinline__ void finalize_item(const float* __restrict__ gp_part, int nchunks, int64_t P,
                                               float* __restrict__ grad_points, int nb_pts,
                                               const float* __restrict__ gs_part, int rows_s, int cols_s,
                                               float* __restrict__ grad_spheres, const float* __restrict__ l_part,
                                               int rows_l, int cols_l, float* __restrict__ grad_light, int b,
                                               float* buf) {
+  const int nb_s = column_blocks(cols_s);
   if (b < nb_pts) {
     sum_chunks_at(gp_part, nchunks, 3 * P, (int64_t)b * SHV_BLOCK + threadIdx.x, grad_points);
-  } else if (b < nb_pts + cols_s) {
-    reduce_column(gs_part, rows_s, cols_s, b - nb_pts, grad_spheres, buf);
+  } else if (b < nb_pts + nb_s) {
+    reduce_columns(gs_part, rows_s, cols_s, b - nb_pts, grad_spheres, buf);
   } else {
-    reduce_column(l_part, rows_l, cols_l, b - nb_pts - cols_s, grad_light, buf);
+    reduce_columns(l_part, rows_l, cols_l, b - nb_pts - nb_s, grad_light, buf);
   }
 }
 
@@ -129,7 +145,7 @@ hipError_t launch_finalize(const float* gp_part, int nchunks, int64_t P, float* 
   const int nb_pts = grad_points ? (int)((3 * P + SHV_BLOCK - 1) / SHV_BLOCK) : 0;
   const int cols_s = grad_spheres ? (int)(4 * S) : 0;
   const int cols_l = grad_light ? N : 0;
-  const int grid = nb_pts + cols_s + cols_l;
+  const int grid = nb_pts + column_blocks(cols_s) + column_blocks(cols_l);
   if (grid == 0) return hipSuccess;
   k_finalize<<<(unsigned)grid, SHV_BLOCK, 0, st>>>(gp_part, nchunks, P, grad_points, nb_pts, gs_part, rows_s, cols_s,
                                                     grad_spheres, l_part, rows_l, cols_l, grad_light);
@@ -138,7 +154,7 @@ hipError_t launch_finalize(const float* gp_part, int nchunks, int64_t P, float* 
 
 hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st) {
   if (cols <= 0) return hipSuccess;
-  k_reduce_rows<<<(unsigned)cols, SHV_BLOCK, 0, st>>>(part, rows, cols, out);
+  k_reduce_rows<<<(unsigned)column_blocks(cols), SHV_BLOCK, 0, st>>>(part, rows, cols, out);
   return hipGetLastError();
 }
 

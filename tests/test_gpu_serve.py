@@ -26,13 +26,18 @@ def test_served_in_mix_equals_alone_bitwise(graphs):
     inputs = [batch.scene_buffers(sc, dev) for sc in pool]
     ex = serve.GpuExecutor(dev, graphs=graphs)
     sched = serve.Scheduler(ex, memory_budget=16 << 30, chunk_pairs=300_000, step_pairs=1_500_000, max_inflight=2,
-                            record_steps=True).start()
+                            record_steps=True)
     rng = np.random.default_rng(5)
     picks = rng.integers(0, len(pool), 40)
     futs = []
-    for j in picks:
+    # half the requests are queued before the loop starts (so steps are shared),
+    # the rest arrive while it runs (newcomers join at step boundaries)
+    for n, j in enumerate(picks):
+        if n == 20:
+            sched.start()
         futs.append(sched.submit(dataclasses.replace(inputs[j], out={}, rec=None), inputs[j].P, inputs[j].S))
-        time.sleep(rng.exponential(0.0005))
+        if n >= 20:
+            time.sleep(rng.exponential(0.0005))
     reqs = [f.result(timeout=120) for f in futs]
     sched.stop(timeout=30)
     print(f"{sched.steps} steps; widest step {max(len(s) for s in sched.step_log)} ranges"
