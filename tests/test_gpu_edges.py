@@ -187,3 +187,24 @@ def test_autograd_function_matches_c_abi():
     assert np.array_equal(t["light"].grad.cpu().numpy(), ref["grad_light"])
     assert np.array_equal(t["normals"].grad.cpu().numpy(), ref["grad_normals"])
     assert np.array_equal(t["albedo"].grad.cpu().numpy(), ref["grad_albedo"])
+
+
+def test_zero_radius_spheres_are_invisible():
+    """A sphere of radius 0 subtends no cap (its coefficients are exact
+    zeros): results equal the scene without it up to the summation order of
+    the other spheres, and its gradients are finite."""
+    sc = scenegen.scene_random_shell(12, 500, 12, 8)
+    sph = sc["spheres"].copy()
+    sph[3, 3] = 0.0
+    sph[7, 3] = 0.0
+    sc["spheres"] = sph
+    keep = np.array([i for i in range(12) if i not in (3, 7)])
+    sc2 = dict(sc)
+    sc2["spheres"] = np.ascontiguousarray(sph[keep])
+    w = sc["grad_radiance"]
+    h = run_render(sc, w)
+    h2 = run_render(sc2, w)
+    assert np.allclose(h["V"], h2["V"], rtol=0, atol=1e-6 * np.abs(h2["V"]).max())
+    assert rel_max(h["B"], h2["B"]) < 1e-6
+    assert np.all(np.isfinite(h["grad_spheres"]))
+    assert np.allclose(h["grad_spheres"][keep], h2["grad_spheres"], rtol=1e-5, atol=1e-6 * np.abs(h2["grad_spheres"]).max())

@@ -117,3 +117,29 @@ def test_gbuffer_scene_full_size_sampled():
     print("fp32 twin: V %.2e B %.2e" % (rel_l2(t["V"], o["V"]), rel_max(t["B"], o["B"])))
     check_forward({"V": h["V"][idx], "B": h["B"][idx]}, o)
     check_grads(h, o, tol_geom=1e-3, idx=idx)
+
+
+def test_largest_squaring_count():
+    """k = 12, the largest supported: FP32 error roughly doubles per squaring."""
+    sc = scenegen.scene_random_shell(9, 300, 24, 6)
+    w = sc["grad_radiance"]
+    h = run_hip(sc, w, k=12)
+    o = run_oracle(sc, w, k=12)
+    tol = TOL_V * 2 ** 8
+    check_forward(h, o, tol_v=tol, tol_b=tol)
+    check_grads(h, o, tol=TOL_G * 2 ** 8)
+
+
+def test_large_request_scene_sampled():
+    """The serving workload's large request (262,144 receivers on the unit
+    sphere, 512 shell spheres, 8 bands) at full size, compared on 128 sampled
+    receivers with the cotangent restricted to them."""
+    sc = scenegen.large_request_scene(500)
+    P = sc["points"].shape[0]
+    idx = np.sort(np.random.default_rng(3).choice(P, 128, replace=False))
+    w = np.zeros(P, np.float32)
+    w[idx] = sc["grad_radiance"][idx]
+    h = run_hip(sc, w)
+    o = run_oracle(sc, w[idx], idx=idx)
+    check_forward({"V": h["V"][idx], "B": h["B"][idx]}, o)
+    check_grads(h, o, idx=idx)
