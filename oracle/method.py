@@ -131,6 +131,14 @@ def shade(V, H, albedo, light, C):
     return albedo * (light * sh.triple_product(V, H, C)).sum(-1)
 
 
+def shade_channels(V, H, albedo, light, C):
+    """Several colour channels sharing one visibility: B_c = a_c (L_c . (V * H))
+    per channel (Eq. 8 for each channel; albedo [P, Ch], light [Ch, N] ->
+    [P, Ch])."""
+    T = sh.triple_product(V, H, C)                              # [P, N]
+    return albedo * (T @ light.T)
+
+
 # ---------------------------------------------------------------- pipeline
 
 def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0,

@@ -193,3 +193,32 @@ def project(fun, n_bands: int, degree: int) -> torch.Tensor:
 def triple_product(a: torch.Tensor, b: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
     """(a * b)_i = sum_jk C_ijk a_j b_k over the last axis (Eq. 7)."""
     return torch.einsum("ijk,...j,...k->...i", C, a, b)
+
+
+# ---------------------------------------------------------------- Eq. 9
+
+def envmap_directions(H: int, W: int):
+    """Pixel-centre directions and exact pixel solid angles of an
+    equirectangular map: row r spans polar angles [r pi / H, (r + 1) pi / H]
+    from +z, column c spans azimuths [c 2 pi / W, (c + 1) 2 pi / W]; the
+    weight of a pixel is the area of that patch, (cos th_r - cos th_{r+1})
+    2 pi / W, and the weights sum to 4 pi.  Returns dirs [H, W, 3] and
+    weights [H, W] (float64)."""
+    th_edges = np.arange(H + 1) * (np.pi / H)
+    th = (np.arange(H) + 0.5) * (np.pi / H)
+    ph = (np.arange(W) + 0.5) * (2.0 * np.pi / W)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], axis=-1)
+    wrow = (np.cos(th_edges[:-1]) - np.cos(th_edges[1:])) * (2.0 * np.pi / W)
+    return torch.tensor(d, dtype=DT), torch.tensor(np.repeat(wrow[:, None], W, axis=1), dtype=DT)
+
+
+def envmap_to_sh(image, n_bands: int) -> torch.Tensor:
+    """Eq. 9 by numerical integration over an equirectangular map:
+    L_i = sum over pixels of L(w) y_i(w) dw.  ``image`` [H, W] or [C, H, W]
+    -> [n^2] or [C, n^2]."""
+    img = torch.as_tensor(np.asarray(image), dtype=DT)
+    H, W = img.shape[-2:]
+    d, w = envmap_directions(H, W)
+    Y = real_sh(d, n_bands)                                   # [H, W, N]
+    return torch.einsum("...hw,hw,hwi->...i", img, w, Y)

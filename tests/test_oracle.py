@@ -452,3 +452,52 @@ def test_gradients_vs_central_differences():
         fd = central(key, u=u)
         an = (G.reshape(-1) * u).sum().item()
         assert abs(fd - an) <= 1e-6 * max(abs(an), scale), (key, fd, an)
+
+
+# --------------------------------------------------------------- Eq. 9, channels
+
+def test_envmap_weights_cover_the_sphere_and_constant_map_is_dc():
+    d, w = sh.envmap_directions(32, 64)
+    assert abs(float(w.sum()) - 4 * np.pi) < 1e-12
+    assert torch.allclose(torch.linalg.norm(d, dim=-1), torch.ones(32, 64, dtype=torch.float64))
+    L = sh.envmap_to_sh(np.full((32, 64), 2.5), 4)
+    assert abs(float(L[0]) - 2.5 * np.sqrt(4 * np.pi)) < 1e-12        # exact: weights sum to 4 pi
+    assert float(L[1:].abs().max()) < 1.5e-2   # midpoint-in-theta error of the m = 0 bands at 32 rows
+
+
+@pytest.mark.parametrize("j", [0, 2, 5, 7, 12, 20, 40, 63])
+def test_envmap_of_a_basis_function_recovers_its_coefficient(j):
+    """Orthonormality: projecting y_j sampled on the map gives e_j up to the
+    quadrature error, which falls as the map is refined."""
+    errs = []
+    for H in (64, 256):
+        d, _ = sh.envmap_directions(H, 2 * H)
+        img = sh.real_sh(d, 8)[..., j].numpy()
+        L = sh.envmap_to_sh(img, 8)
+        e = torch.zeros(64, dtype=torch.float64)
+        e[j] = 1.0
+        errs.append(float((L - e).abs().max()))
+    assert errs[1] < 2e-4 and errs[1] < errs[0] / 8
+
+
+def test_envmap_channels_are_independent():
+    rng = np.random.default_rng(0)
+    img = rng.random((3, 16, 32))
+    L = sh.envmap_to_sh(img, 5)
+    for c in range(3):
+        assert torch.allclose(L[c], sh.envmap_to_sh(img[c], 5), rtol=0, atol=1e-14)
+
+
+def test_shade_channels_is_monochrome_per_channel():
+    sc = scenegen.scene_random_shell(21, 40, 8, 6)
+    rng = np.random.default_rng(1)
+    alb = torch.tensor(rng.uniform(0.2, 0.9, (40, 3)))
+    light = torch.tensor(rng.standard_normal((3, 36)))
+    T = method.scene_tensors(sc)
+    C = sh.gaunt_tensor(6)
+    F = method.log_visibility(T["points"], T["spheres"], 6, 3.0)
+    V, _, _ = method.sh_exponential(F, C, 4)
+    H = method.transfer(T["normals"], 6)
+    B = method.shade_channels(V, H, alb, light, C)
+    for c in range(3):
+        assert torch.allclose(B[:, c], method.shade(V, H, alb[:, c], light[c], C), rtol=1e-14, atol=1e-14)
