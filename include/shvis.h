@@ -59,6 +59,9 @@ typedef int32_t shv_status;
 #define SHV_MAX_BANDS_API 8
 #define SHV_MAX_SQUARINGS 12
 #define SHV_RANGE_ALIGN 256   /* receiver-range granularity of batched calls */
+#define SHV_MAX_CHANNELS 4    /* colour channels of one multi-channel shading call */
+#define SHV_MAX_ENVMAP_ROWS 65536     /* environment-map rows (polar samples) */
+#define SHV_MAX_ENVMAP_COLS 1048576   /* environment-map columns (azimuth samples) */
 
 /* Method parameters.  n_bands: number of SH bands n (l < n), the paper uses
  * n = 8 (Sec. 3.2).  n_squarings: k, the number of squarings of the SH
@@ -125,6 +128,47 @@ shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const
                              const shv_params* prm, float* grad_vis, float* grad_normals,
                              float* grad_albedo, float* grad_light, void* ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/* Several colour channels lit through one visibility (Eq. 8 once per channel:
+ * B_c = a_c (L_c . (V * H)), the usual RGB setting of the paper's renders).
+ *   channels  C in [1, SHV_MAX_CHANNELS]
+ *   vis [N][P], normals [3][P] as for sh_shade
+ *   albedo [C][P], light [C][N], radiance [C][P] out
+ * Channel c's radiance is bitwise what sh_shade gives for albedo[c] and
+ * light[c].  ws must hold shv_channels_workspace_bytes(P, C, prm) bytes (0 is
+ * returned for invalid arguments). */
+size_t shv_channels_workspace_bytes(int64_t P, int channels, const shv_params* prm);
+shv_status sh_shade_channels(const float* vis, const float* normals, const float* albedo, const float* light,
+                             int channels, int64_t P, const shv_params* prm, float* radiance, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of sh_shade_channels for the cotangent grad_radiance [C][P]:
+ *   grad_albedo [C][P], grad_light [C][N] (summed over receivers): channel c
+ *   bitwise as sh_shade_backward for that channel alone;
+ *   grad_vis [N][P], grad_normals [3][P]: summed over the channels, since V
+ *   and n are shared (channel-order sum of the per-channel cotangents).
+ * Any output may be NULL.  Same workspace as sh_shade_channels. */
+shv_status sh_shade_channels_backward(const float* grad_radiance, const float* vis, const float* normals,
+                                      const float* albedo, const float* light, int channels, int64_t P,
+                                      const shv_params* prm, float* grad_vis, float* grad_normals,
+                                      float* grad_albedo, float* grad_light, void* ws, size_t ws_bytes,
+                                      hipStream_t stream);
+
+/* Distant lighting from an environment map (Eq. 9: L_i is the integral of the
+ * map times y_i over the sphere), by summation over the pixels of an
+ * equirectangular map.
+ *   image [C][H][W]: row r covers polar angles [r, r + 1] pi / H measured
+ *     from +z, column x azimuths [x, x + 1] 2 pi / W from +x towards +y;
+ *     each pixel is sampled at its centre and weighted by its exact solid
+ *     angle (cos th_r - cos th_{r+1}) 2 pi / W (the weights sum to 4 pi)
+ *   light [C][N] out (N = n_bands^2; eps, n_squarings and flags are unused)
+ *   1 <= C <= SHV_MAX_CHANNELS, 0 <= H <= SHV_MAX_ENVMAP_ROWS,
+ *   0 <= W <= SHV_MAX_ENVMAP_COLS; an empty map gives L = 0.
+ * Rows are summed in row order (deterministic).  ws must hold
+ * shv_envmap_workspace_bytes(C, H, W, prm) bytes (0 for invalid arguments). */
+size_t shv_envmap_workspace_bytes(int channels, int64_t H, int64_t W, const shv_params* prm);
+shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_t W, const shv_params* prm,
+                             float* light, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of sh_visibility_forward for the cotangent grad_vis [N][P]:
  *   vis, saved  the forward's outputs for the same inputs and parameters

@@ -220,3 +220,46 @@ def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=N
     out["grad_spheres"] = gs
     out["grad_light"] = gl
     return out
+
+
+def run_forward_backward_channels(scene, albedo, light, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=None,
+                                  dtype=DT):
+    """Colour channels sharing one visibility (Eq. 8 per channel):
+    albedo [P, Ch], light [Ch, N], grad_B [P', Ch] the cotangent of the
+    radiance [P', Ch] on receivers ``idx`` (all when None).  Returns B,
+    grad_points, grad_normals, grad_albedo [P', Ch] (or [P', 3]),
+    grad_spheres [S, 4] and grad_light [Ch, N], the last two summed over the
+    selected receivers."""
+    T = scene_tensors(scene, dtype)
+    n = int(scene["n_bands"])
+    C = sh.gaunt_tensor(n).to(dtype)
+    P = T["points"].shape[0]
+    sel = torch.arange(P) if idx is None else torch.as_tensor(idx)
+    alb_all = torch.as_tensor(albedo).to(dtype)
+    gB = torch.as_tensor(grad_B).to(dtype)
+    spheres = T["spheres"].clone().requires_grad_(True)
+    lights = torch.as_tensor(light).to(dtype).clone().requires_grad_(True)
+    gs = torch.zeros_like(spheres)
+    gl = torch.zeros_like(lights)
+    res = {k: [] for k in ("B", "grad_points", "grad_normals", "grad_albedo")}
+    for s in range(0, len(sel), chunk):
+        j = sel[s:s + chunk]
+        p = T["points"][j].clone().requires_grad_(True)
+        nrm = T["normals"][j].clone().requires_grad_(True)
+        a = alb_all[j].clone().requires_grad_(True)
+        F = log_visibility(p, spheres, n, eps)
+        V, _, _ = sh_exponential(F, C, n_squarings)
+        B = shade_channels(V, transfer(nrm, n), a, lights, C)
+        ins = [p, nrm, a, spheres, lights]
+        g = torch.autograd.grad((B * gB[s:s + chunk]).sum(), ins, allow_unused=True)
+        g = [torch.zeros_like(x) if gx is None else gx for gx, x in zip(g, ins)]
+        res["B"].append(B.detach())
+        res["grad_points"].append(g[0])
+        res["grad_normals"].append(g[1])
+        res["grad_albedo"].append(g[2])
+        gs += g[3]
+        gl += g[4]
+    out = {k: torch.cat(v) for k, v in res.items()}
+    out["grad_spheres"] = gs
+    out["grad_light"] = gl
+    return out

@@ -31,6 +31,8 @@ SHV_ERR_HIP = -5
 EXPORTED = [
     "shv_init", "shv_status_string", "shv_last_error", "shv_saved_floats", "shv_workspace_bytes",
     "sh_visibility_forward", "sh_shade", "sh_shade_backward", "sh_visibility_backward",
+    "shv_channels_workspace_bytes", "sh_shade_channels", "sh_shade_channels_backward",
+    "shv_envmap_workspace_bytes", "sh_envmap_project",
     "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
     "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
     "sh_render_batched_forward", "sh_render_batched_backward",
@@ -38,6 +40,9 @@ EXPORTED = [
 ]
 
 SHV_RANGE_ALIGN = 256
+SHV_MAX_CHANNELS = 4
+SHV_MAX_ENVMAP_ROWS = 65536
+SHV_MAX_ENVMAP_COLS = 1048576
 SHV_FLAG_EXP_ONE_WAVE = 1
 SHV_FLAG_EXP_FOUR_WAVES = 2
 
@@ -76,6 +81,12 @@ _sig = {
     "sh_shade": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _PRM, _P, _P, _SZ, _P]),
     "sh_shade_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _PRM, _P, _P, _P, _P, _P, _SZ, _P]),
     "sh_visibility_backward": (ctypes.c_int32, [_P, _P, _P, _I64, _P, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
+    "shv_channels_workspace_bytes": (_SZ, [_I64, ctypes.c_int, _PRM]),
+    "sh_shade_channels": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int, _I64, _PRM, _P, _P, _SZ, _P]),
+    "sh_shade_channels_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int, _I64, _PRM, _P, _P, _P, _P,
+                                                    _P, _SZ, _P]),
+    "shv_envmap_workspace_bytes": (_SZ, [ctypes.c_int, _I64, _I64, _PRM]),
+    "sh_envmap_project": (ctypes.c_int32, [_P, ctypes.c_int, _I64, _I64, _PRM, _P, _P, _SZ, _P]),
     "shv_render_saved_floats": (_I64, [_I64, _PRM]),
     "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
     "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -154,6 +165,33 @@ def sh_shade_backward(grad_radiance, vis, normals, albedo, light, P, prm, grad_v
     _check(_lib.sh_shade_backward(ptr(grad_radiance), ptr(vis), ptr(normals), ptr(albedo), ptr(light), int(P),
                                   ctypes.byref(prm), ptr(grad_vis), ptr(grad_normals), ptr(grad_albedo),
                                   ptr(grad_light), ptr(ws), int(ws_bytes), stream), "sh_shade_backward")
+
+
+def shv_channels_workspace_bytes(P: int, channels: int, prm: shv_params) -> int:
+    return int(_lib.shv_channels_workspace_bytes(int(P), int(channels), ctypes.byref(prm)))
+
+
+def sh_shade_channels(vis, normals, albedo, light, channels, P, prm, radiance, ws, ws_bytes, stream):
+    _check(_lib.sh_shade_channels(ptr(vis), ptr(normals), ptr(albedo), ptr(light), int(channels), int(P),
+                                  ctypes.byref(prm), ptr(radiance), ptr(ws), int(ws_bytes), stream),
+           "sh_shade_channels")
+
+
+def sh_shade_channels_backward(grad_radiance, vis, normals, albedo, light, channels, P, prm, grad_vis,
+                               grad_normals, grad_albedo, grad_light, ws, ws_bytes, stream):
+    _check(_lib.sh_shade_channels_backward(ptr(grad_radiance), ptr(vis), ptr(normals), ptr(albedo), ptr(light),
+                                           int(channels), int(P), ctypes.byref(prm), ptr(grad_vis),
+                                           ptr(grad_normals), ptr(grad_albedo), ptr(grad_light), ptr(ws),
+                                           int(ws_bytes), stream), "sh_shade_channels_backward")
+
+
+def shv_envmap_workspace_bytes(channels: int, H: int, W: int, prm: shv_params) -> int:
+    return int(_lib.shv_envmap_workspace_bytes(int(channels), int(H), int(W), ctypes.byref(prm)))
+
+
+def sh_envmap_project(image, channels, H, W, prm, light, ws, ws_bytes, stream):
+    _check(_lib.sh_envmap_project(ptr(image), int(channels), int(H), int(W), ctypes.byref(prm), ptr(light),
+                                  ptr(ws), int(ws_bytes), stream), "sh_envmap_project")
 
 
 def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, grad_points, grad_spheres, ws,

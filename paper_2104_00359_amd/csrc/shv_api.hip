@@ -201,6 +201,32 @@ size_t render_fwd_bytes(int64_t P, int64_t S, int nb) {
   return fwd_bytes(P, S, nb) + align_up((size_t)nb * nb * nb * nb * 4);
 }
 
+// Several channels: every channel's M(L_c), then the per-channel tile
+// partials of the lighting gradient.
+struct ChannelWs {
+  size_t M, lpart;
+};
+size_t channels_bytes(int64_t P, int channels, int nb, ChannelWs* o = nullptr) {
+  const size_t N = (size_t)nb * nb;
+  const size_t m = align_up((size_t)channels * N * N * 4);
+  const size_t lp = align_up((size_t)channels * (size_t)shv::pair_blocks(P) * N * 4);
+  if (o) {
+    o->M = 0;
+    o->lpart = m;
+  }
+  return m + lp;
+}
+// Environment map: the per-row partial sums [channels][H][N].
+size_t envmap_bytes(int channels, int64_t H, int nb) {
+  return align_up((size_t)channels * (size_t)H * nb * nb * 4);
+}
+
+shv_status check_channels(int channels) {
+  if (channels < 1 || channels > SHV_MAX_CHANNELS)
+    return set_error(SHV_ERR_INVALID_ARG, "channels must be in [1, %d] (got %d)", SHV_MAX_CHANNELS, channels);
+  return SHV_OK;
+}
+
 shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
   if (needed == 0) return SHV_OK;
   if (!ws) return set_error(SHV_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", needed);
@@ -434,6 +460,117 @@ shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const
       return shv::launch_reduce_rows(Lpart, (int)shv::pair_blocks(P), N, grad_light, stream);
     }));
   }
+  return SHV_OK;
+}
+
+size_t shv_channels_workspace_bytes(int64_t P, int channels, const shv_params* prm) {
+  if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || P < 0 || channels < 1 ||
+      channels > SHV_MAX_CHANNELS)
+    return 0;
+  return channels_bytes(P, channels, prm->n_bands);
+}
+
+shv_status sh_shade_channels(const float* vis, const float* normals, const float* albedo, const float* light,
+                             int channels, int64_t P, const shv_params* prm, float* radiance, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, 0));
+  SHV_TRY(check_channels(channels));
+  SHV_TRY(check_device());
+  if (P == 0) return SHV_OK;
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(light, "light"));
+  SHV_TRY(need(radiance, "radiance"));
+  const int nb = prm->n_bands;
+  const int N = nb * nb;
+  ChannelWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, channels_bytes(P, channels, nb, &L)));
+  float* M = (float*)((char*)ws + L.M);
+  for (int c = 0; c < channels; ++c)
+    SHV_TRY(launch("build_M", stream,
+                   [&] { return shv::launch_build_M(nb, light + (size_t)c * N, M + (size_t)c * N * N, stream); }));
+  SHV_TRY(launch("shade_ch_fwd", stream, [&] {
+    return shv::launch_shade_ch_fwd(nb, vis, normals, albedo, M, channels, P, radiance, stream);
+  }));
+  return SHV_OK;
+}
+
+shv_status sh_shade_channels_backward(const float* grad_radiance, const float* vis, const float* normals,
+                                      const float* albedo, const float* light, int channels, int64_t P,
+                                      const shv_params* prm, float* grad_vis, float* grad_normals,
+                                      float* grad_albedo, float* grad_light, void* ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_sizes(P, 0));
+  SHV_TRY(check_channels(channels));
+  SHV_TRY(check_device());
+  const int nb = prm->n_bands;
+  const int N = nb * nb;
+  if (P == 0) {
+    if (grad_light)
+      SHV_TRY(launch("fill_zero", stream,
+                     [&] { return shv::launch_fill_zero(grad_light, (int64_t)channels * N, stream); }));
+    return SHV_OK;
+  }
+  SHV_TRY(need(grad_radiance, "grad_radiance"));
+  SHV_TRY(need(vis, "vis"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(albedo, "albedo"));
+  SHV_TRY(need(light, "light"));
+  ChannelWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, channels_bytes(P, channels, nb, &L)));
+  float* M = (float*)((char*)ws + L.M);
+  float* Lpart = grad_light ? (float*)((char*)ws + L.lpart) : nullptr;
+  for (int c = 0; c < channels; ++c)
+    SHV_TRY(launch("build_M", stream,
+                   [&] { return shv::launch_build_M(nb, light + (size_t)c * N, M + (size_t)c * N * N, stream); }));
+  SHV_TRY(launch("shade_ch_bwd", stream, [&] {
+    return shv::launch_shade_ch_bwd(nb, grad_radiance, vis, normals, albedo, M, channels, P, grad_vis,
+                                    grad_normals, grad_albedo, Lpart, stream);
+  }));
+  if (grad_light) {
+    const int rows = (int)shv::pair_blocks(P);
+    for (int c = 0; c < channels; ++c)
+      SHV_TRY(launch("reduce_light", stream, [&] {
+        return shv::launch_reduce_rows(Lpart + (size_t)c * rows * N, rows, N, grad_light + (size_t)c * N, stream);
+      }));
+  }
+  return SHV_OK;
+}
+
+size_t shv_envmap_workspace_bytes(int channels, int64_t H, int64_t W, const shv_params* prm) {
+  if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || channels < 1 ||
+      channels > SHV_MAX_CHANNELS || H < 0 || W < 0 || H > SHV_MAX_ENVMAP_ROWS || W > SHV_MAX_ENVMAP_COLS)
+    return 0;
+  return envmap_bytes(channels, H, prm->n_bands);
+}
+
+shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_t W, const shv_params* prm,
+                             float* light, void* ws, size_t ws_bytes, hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(check_channels(channels));
+  if (H < 0 || W < 0) return set_error(SHV_ERR_INVALID_ARG, "negative map size (H=%lld, W=%lld)", (long long)H,
+                                       (long long)W);
+  if (H > SHV_MAX_ENVMAP_ROWS || W > SHV_MAX_ENVMAP_COLS)
+    return set_error(SHV_ERR_INVALID_ARG, "map too large (H=%lld, W=%lld)", (long long)H, (long long)W);
+  SHV_TRY(check_device());
+  SHV_TRY(need(light, "light"));
+  const int nb = prm->n_bands;
+  const int N = nb * nb;
+  if (H == 0 || W == 0)
+    return launch("fill_zero", stream,
+                  [&] { return shv::launch_fill_zero(light, (int64_t)channels * N, stream); });
+  SHV_TRY(need(image, "image"));
+  SHV_TRY(check_ws(ws, ws_bytes, envmap_bytes(channels, H, nb)));
+  float* part = (float*)ws;
+  SHV_TRY(launch("envmap_rows", stream,
+                 [&] { return shv::launch_envmap_rows(nb, image, channels, H, W, part, stream); }));
+  for (int c = 0; c < channels; ++c)
+    SHV_TRY(launch("reduce_envmap", stream, [&] {
+      return shv::launch_reduce_rows(part + (size_t)c * H * N, (int)H, N, light + (size_t)c * N, stream);
+    }));
   return SHV_OK;
 }
 

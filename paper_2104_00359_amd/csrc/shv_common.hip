@@ -266,6 +266,28 @@ hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const flo
 #undef C
 }
 
+hipError_t launch_shade_ch_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
+                               int channels, int64_t P, float* rad, hipStream_t st) {
+#define C(N) shade_ch_fwd_nb<N>(vis, nrm, alb, M, channels, P, rad, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_shade_ch_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
+                               const float* M, int channels, int64_t P, float* gV, float* gN, float* gA,
+                               float* Lpart, hipStream_t st) {
+#define C(N) shade_ch_bwd_nb<N>(gB, vis, nrm, alb, M, channels, P, gV, gN, gA, Lpart, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_envmap_rows(int nb, const float* img, int channels, int64_t H, int64_t W, float* part,
+                              hipStream_t st) {
+#define C(N) envmap_rows_nb<N>(img, channels, H, W, part, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
 hipError_t launch_batch_nb(int nb, int phase, bool four, const void* table, int64_t blocks, hipStream_t st) {
   switch (phase) {
 #define C(N) batch_pair_fwd_nb<N>(table, blocks, st)

@@ -4,3 +4,4 @@
 #define SHV_BLOCK 256                              // threads per block (4 waves of 64)
 #define SHV_WAVES_PER_BLOCK (SHV_BLOCK / 64)
 #define SHV_MAX_CHUNK 512                          // spheres per block in the pair kernels (LDS bound)
+#define SHV_MAX_CHANNELS 4                         // colour channels per multi-channel shading call

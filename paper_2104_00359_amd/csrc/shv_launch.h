@@ -32,6 +32,16 @@ hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const flo
                             const float* M, int64_t P, float* gV, float* gN, float* gA, float* Lpart,
                             hipStream_t st);
 hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st);
+// Several colour channels sharing V (channel c's data at M + c N^2, alb / rad / gB / gA + c P,
+// Lpart + c ceil(P / 64) N); 1 <= channels <= SHV_MAX_CHANNELS.
+hipError_t launch_shade_ch_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
+                               int channels, int64_t P, float* rad, hipStream_t st);
+hipError_t launch_shade_ch_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
+                               const float* M, int channels, int64_t P, float* gV, float* gN, float* gA,
+                               float* Lpart, hipStream_t st);
+// Per-row partial sums of Eq. 9 over an equirectangular map [channels][H][W] -> part [channels][H][N].
+hipError_t launch_envmap_rows(int nb, const float* img, int channels, int64_t H, int64_t W, float* part,
+                              hipStream_t st);
 hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P,
                           float eps, int k, float* W, uint32_t flags, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,
@@ -81,6 +91,14 @@ hipError_t shade_fwd_nb(const float* vis, const float* nrm, const float* alb, co
 template <int NB>
 hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
                         int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
+template <int NB>
+hipError_t shade_ch_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int channels,
+                           int64_t P, float* rad, hipStream_t st);
+template <int NB>
+hipError_t shade_ch_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
+                           int channels, int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
+template <int NB>
+hipError_t envmap_rows_nb(const float* img, int channels, int64_t H, int64_t W, float* part, hipStream_t st);
 template <int NB>
 hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>

@@ -23,6 +23,11 @@ template hipError_t shade_fwd_nb<SHV_NB>(const float*, const float*, const float
                                          hipStream_t);
 template hipError_t shade_bwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, const float*, int64_t,
                                          float*, float*, float*, float*, hipStream_t);
+template hipError_t shade_ch_fwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, int, int64_t,
+                                            float*, hipStream_t);
+template hipError_t shade_ch_bwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, const float*, int,
+                                            int64_t, float*, float*, float*, float*, hipStream_t);
+template hipError_t envmap_rows_nb<SHV_NB>(const float*, int, int64_t, int64_t, float*, hipStream_t);
 template hipError_t batch_pair_fwd_nb<SHV_NB>(const void*, int64_t, hipStream_t);
 template hipError_t batch_pair_bwd_nb<SHV_NB>(const void*, int64_t, hipStream_t);
 #elif SHV_PART == 1

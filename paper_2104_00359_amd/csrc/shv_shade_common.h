@@ -104,7 +104,7 @@ __device__ __forceinline__ float transfer(float nx, float ny, float nz, float (&
 // Partial g of sum_k H_k t_k over support columns kk = g, g + 4, ...; also
 // Hb_k = w t_k A_l for those columns (the cotangent of y_k(n_hat)).  Ms is
 // the staged copy of M (stage_M).
-template <int NB, int G, bool ADJ>
+template <int NB, int G, bool ADJ, bool ACC = false>
 __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const float (&H)[NB * NB],
                                                const float* Ms, float w, float (&Hb)[NB * NB]) {
   constexpr int N = NB * NB;
@@ -122,7 +122,8 @@ __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const 
 #pragma unroll
       for (int j = 0; j < N; ++j) t = fmaf(Ms[MSupp<NB>::at(j, col)], V[j], t);
       s = fmaf(H[k], t, s);
-      if (ADJ) Hb[k] = w * t * SHV_AHAT[l];
+      if (ADJ && ACC) Hb[k] += w * t * SHV_AHAT[l];
+      if (ADJ && !ACC) Hb[k] = w * t * SHV_AHAT[l];
     }
   }
   return s;
@@ -140,6 +141,18 @@ __device__ __forceinline__ float shade_value(const float (&V)[NB * NB], const fl
   const float s1 = shade_partial<NB, 1, ADJ>(V, H, M, w, Hb);
   const float s2 = shade_partial<NB, 2, ADJ>(V, H, M, w, Hb);
   const float s3 = shade_partial<NB, 3, ADJ>(V, H, M, w, Hb);
+  return ((s0 + s1) + s2) + s3;
+}
+
+// As shade_value<NB, true>, but adding this channel's y_k cotangents to Hb
+// (several colour channels that share V and H, Eq. 8 per channel).
+template <int NB>
+__device__ __forceinline__ float shade_value_acc(const float (&V)[NB * NB], const float (&H)[NB * NB],
+                                                 const float* M, float w, float (&Hb)[NB * NB]) {
+  const float s0 = shade_partial<NB, 0, true, true>(V, H, M, w, Hb);
+  const float s1 = shade_partial<NB, 1, true, true>(V, H, M, w, Hb);
+  const float s2 = shade_partial<NB, 2, true, true>(V, H, M, w, Hb);
+  const float s3 = shade_partial<NB, 3, true, true>(V, H, M, w, Hb);
   return ((s0 + s1) + s2) + s3;
 }
 

@@ -116,3 +116,88 @@ def visibility_sh(points, spheres, n_bands: int, eps: float = 3.0, n_squarings: 
     ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
     _lib.sh_visibility_forward(_soa(points), P, _f32(spheres), S, prm, vis, None, ws, ws.numel(), _stream())
     return vis.t()
+
+
+class ShadeSHChannels(torch.autograd.Function):
+    """Radiance of several colour channels that share one visibility
+    (sh_visibility_forward, then sh_shade_channels; backward through
+    sh_shade_channels_backward and sh_visibility_backward)."""
+
+    @staticmethod
+    def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings):
+        dev = points.device
+        if dev.type != "cuda":
+            raise RuntimeError("shade_sh_channels runs on the GPU only; move the inputs to a HIP device")
+        ensure_init(dev)
+        prm = _lib.params(n_bands, eps, n_squarings)
+        P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
+        if light.dim() != 2 or light.shape[1] != N:
+            raise ValueError(f"light must be [channels, {N}] for {n_bands} bands, got {tuple(light.shape)}")
+        C = light.shape[0]
+        if albedo.shape != (P, C):
+            raise ValueError(f"albedo must be [{P}, {C}], got {tuple(albedo.shape)}")
+        pts, nrm = _soa(points), _soa(normals)
+        alb, sph, L = _soa(albedo), _f32(spheres), _f32(light)
+        vis = torch.empty(N, P, dtype=torch.float32, device=dev)
+        saved = torch.empty(_lib.shv_saved_floats(P, prm), dtype=torch.float32, device=dev)
+        rad = torch.empty(C, P, dtype=torch.float32, device=dev)
+        ws = workspace(dev, max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm)))
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), _stream())
+        _lib.sh_shade_channels(vis, nrm, alb, L, C, P, prm, rad, ws, ws.numel(), _stream())
+        ctx.save_for_backward(pts, nrm, alb, sph, L, vis, saved)
+        ctx.cfg = (n_bands, eps, n_squarings)
+        return rad.t()
+
+    @staticmethod
+    def backward(ctx, grad_rad):
+        pts, nrm, alb, sph, L, vis, saved = ctx.saved_tensors
+        n_bands, eps, n_squarings = ctx.cfg
+        prm = _lib.params(n_bands, eps, n_squarings)
+        dev = pts.device
+        P, S, N, C = pts.shape[1], sph.shape[0], n_bands * n_bands, L.shape[0]
+        gB = _soa(grad_rad)
+        need_p, need_n, need_a, need_s, need_l = ctx.needs_input_grad[:5]
+        need_v = need_p or need_s
+        gV = torch.empty(N, P, dtype=torch.float32, device=dev) if need_v else None
+        gN = torch.empty(3, P, dtype=torch.float32, device=dev) if need_n else None
+        gA = torch.empty(C, P, dtype=torch.float32, device=dev) if need_a else None
+        gL = torch.empty(C, N, dtype=torch.float32, device=dev) if need_l else None
+        gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
+        gS = torch.empty(S, 4, dtype=torch.float32, device=dev) if need_s else None
+        ws = workspace(dev, max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm)))
+        _lib.sh_shade_channels_backward(gB, vis, nrm, alb, L, C, P, prm, gV, gN, gA, gL, ws, ws.numel(), _stream())
+        if need_v:
+            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), _stream())
+        return (gP.t() if gP is not None else None, gN.t() if gN is not None else None,
+                gA.t() if gA is not None else None, gS, gL, None, None, None)
+
+
+def shade_sh_channels(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0,
+                      n_squarings: int = 4):
+    """Radiance [P, C] of C colour channels (e.g. RGB) at receivers ``points``
+    [P, 3] with ``normals`` [P, 3] and ``albedo`` [P, C], under one shared
+    visibility from ``spheres`` [S, 4], lit by ``light`` [C, n_bands^2] (one
+    SH vector per channel; Eq. 8 per channel).  Differentiable with respect to
+    every tensor input."""
+    return ShadeSHChannels.apply(points, normals, albedo, spheres, light, n_bands, eps, n_squarings)
+
+
+def envmap_to_sh(image, n_bands: int):
+    """SH lighting coefficients of an equirectangular environment map (Eq. 9):
+    ``image`` [H, W] or [C, H, W] (row r covers polar angles [r, r+1] pi/H from
+    +z, column x azimuths [x, x+1] 2 pi/W from +x towards +y) -> [N] or
+    [C, N] with N = n_bands^2.  Forward only."""
+    dev = image.device
+    if dev.type != "cuda":
+        raise RuntimeError("envmap_to_sh runs on the GPU only; move the image to a HIP device")
+    ensure_init(dev)
+    mono = image.dim() == 2
+    img = _f32(image[None] if mono else image)
+    if img.dim() != 3:
+        raise ValueError(f"image must be [H, W] or [C, H, W], got {tuple(image.shape)}")
+    C, H, W = img.shape
+    prm = _lib.params(n_bands)
+    out = torch.empty(C, n_bands * n_bands, dtype=torch.float32, device=dev)
+    ws = workspace(dev, _lib.shv_envmap_workspace_bytes(C, H, W, prm))
+    _lib.sh_envmap_project(img, C, H, W, prm, out, ws, ws.numel(), _stream())
+    return out[0] if mono else out

@@ -355,3 +355,56 @@ def subset(scene, idx):
         if key in scene:
             out[key] = np.ascontiguousarray(scene[key][idx])
     return out
+
+
+# --------------------------------------------------------------------------
+# colour channels and environment maps
+# --------------------------------------------------------------------------
+
+
+def colour_channels(scene, C=3, seed=0):
+    """Per-channel albedo [P, C], lighting [C, n*n] and output cotangent
+    [P, C] for ``scene`` (RGB-like when C = 3).  Draw order: per channel the
+    light (DC 3 plus N(0, 1), as draw_light), then albedo uniform in
+    [0.2, 0.9], then the cotangent N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    P = scene["points"].shape[0]
+    n = int(scene["n_bands"])
+    light = np.stack([draw_light(rng, n) for _ in range(C)])
+    albedo = rng.uniform(0.2, 0.9, size=(P, C))
+    w = rng.standard_normal((P, C))
+    return dict(albedo=_f32(albedo), light=_f32(light), grad_radiance=_f32(w))
+
+
+def envmap_image(seed=0, C=3, H=256, W=512, suns=3):
+    """A synthetic equirectangular HDR environment map [C, H, W] (row r covers
+    polar angles [r, r + 1] pi / H from +z, column x azimuths
+    [x, x + 1] 2 pi / W): a sky-to-ground gradient, a slowly varying
+    azimuthal pattern and ``suns`` small bright Gaussian spots (the dynamic
+    range of captured sky maps).  Draw order: per-channel sky and ground
+    levels, pattern amplitudes and phases, then per sun its direction, width
+    (radians) and per-channel intensity."""
+    rng = np.random.default_rng(seed)
+    th = (np.arange(H) + 0.5) * (np.pi / H)
+    ph = (np.arange(W) + 0.5) * (2.0 * np.pi / W)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], axis=-1)
+    sky = rng.uniform(0.5, 1.5, size=C)
+    ground = rng.uniform(0.05, 0.3, size=C)
+    amp = rng.uniform(0.0, 0.3, size=(C, 3))
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=(C, 3))
+    img = np.empty((C, H, W))
+    up = np.clip(d[..., 2], 0.0, 1.0)
+    for c in range(C):
+        img[c] = ground[c] + (sky[c] - ground[c]) * up
+        for j in range(3):
+            img[c] *= 1.0 + amp[c, j] * np.cos((j + 1) * PH + phase[c, j]) * np.sin(TH)
+    for _ in range(suns):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        width = rng.uniform(0.03, 0.1)
+        power = rng.uniform(20.0, 200.0, size=C)
+        ang2 = np.arccos(np.clip(d @ v, -1.0, 1.0)) ** 2
+        for c in range(C):
+            img[c] += power[c] * np.exp(-ang2 / (2.0 * width * width))
+    return _f32(img)

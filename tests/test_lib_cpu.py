@@ -77,6 +77,43 @@ def test_invalid_parameters_rejected_before_any_device_call(L):
     assert g(None, None, None, None, 5, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
 
 
+def test_channel_and_envmap_workspace_sizes(L):
+    prm = L.params(8)
+    one = L.shv_channels_workspace_bytes(20000, 1, prm)
+    three = L.shv_channels_workspace_bytes(20000, 3, prm)
+    # per channel: M(L) (N^2 floats) and the tile partials of the lighting gradient
+    assert one >= 64 * 64 * 4 + ((20000 + 63) // 64) * 64 * 4
+    assert three >= 3 * 64 * 64 * 4 + 3 * ((20000 + 63) // 64) * 64 * 4 and three % 256 == 0
+    for bad in (0, L.SHV_MAX_CHANNELS + 1, -1):
+        assert L.shv_channels_workspace_bytes(100, bad, prm) == 0
+    assert L.shv_channels_workspace_bytes(100, 1, L.params(9)) == 0
+    e = L.shv_envmap_workspace_bytes(3, 256, 512, prm)
+    assert e >= 3 * 256 * 64 * 4 and e % 256 == 0
+    assert L.shv_envmap_workspace_bytes(3, L.SHV_MAX_ENVMAP_ROWS + 1, 8, prm) == 0
+    assert L.shv_envmap_workspace_bytes(3, 8, L.SHV_MAX_ENVMAP_COLS + 1, prm) == 0
+    assert L.shv_envmap_workspace_bytes(L.SHV_MAX_CHANNELS + 1, 8, 8, prm) == 0
+
+
+def test_channel_and_envmap_arguments_rejected_before_any_device_call(L):
+    st = None
+    prm = L.params(4)
+    f = L.raw("sh_shade_channels")
+    for bad in (0, L.SHV_MAX_CHANNELS + 1):
+        assert f(None, None, None, None, bad, 10, ctypes.byref(prm), None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+        assert "channels" in L.shv_last_error()
+    b = L.raw("sh_shade_channels_backward")
+    assert b(None, None, None, None, None, 0, 10, ctypes.byref(prm), None, None, None, None, None, 0,
+             st) == L.SHV_ERR_INVALID_ARG
+    assert b(None, None, None, None, None, 2, -1, ctypes.byref(prm), None, None, None, None, None, 0,
+             st) == L.SHV_ERR_INVALID_ARG
+    e = L.raw("sh_envmap_project")
+    assert e(None, 1, -1, 8, ctypes.byref(prm), None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert e(None, 1, 8, L.SHV_MAX_ENVMAP_COLS + 1, ctypes.byref(prm), None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert "too large" in L.shv_last_error()
+    assert e(None, 0, 8, 8, ctypes.byref(prm), None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert e(None, 1, 8, 8, ctypes.byref(L.params(9)), None, None, 0, st) == L.SHV_ERR_UNSUPPORTED
+
+
 def _fake_scene(L, P, S, n, k=4, flags=0, base=1 << 40):
     """A scene record with distinct, aligned fake device addresses (the table
     is packed on the host; nothing is dereferenced)."""

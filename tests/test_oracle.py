@@ -501,3 +501,24 @@ def test_shade_channels_is_monochrome_per_channel():
     B = method.shade_channels(V, H, alb, light, C)
     for c in range(3):
         assert torch.allclose(B[:, c], method.shade(V, H, alb[:, c], light[c], C), rtol=1e-14, atol=1e-14)
+
+
+def test_channel_gradients_are_per_channel_and_summed_where_shared():
+    """Per channel, the multi-channel oracle's radiance, albedo and lighting
+    gradients are the one-channel oracle's (each pinned above); the receiver,
+    normal and sphere gradients, through the shared V and H, are the sums of
+    the one-channel ones (linearity of the cotangent)."""
+    sc = scenegen.scene_random_shell(4, 60, 10, 5)
+    ch = scenegen.colour_channels(sc, 3, seed=2)
+    o = method.run_forward_backward_channels(sc, ch["albedo"], ch["light"], ch["grad_radiance"], chunk=25)
+    acc = {k: 0.0 for k in ("grad_points", "grad_normals", "grad_spheres")}
+    for c in range(3):
+        s1 = dict(sc, albedo=ch["albedo"][:, c].copy(), light=ch["light"][c].copy())
+        m = method.run_forward_backward(s1, ch["grad_radiance"][:, c])
+        assert torch.allclose(o["B"][:, c], m["B"], rtol=1e-13, atol=1e-13)
+        assert torch.allclose(o["grad_albedo"][:, c], m["grad_albedo"], rtol=1e-12, atol=1e-13)
+        assert torch.allclose(o["grad_light"][c], m["grad_light"], rtol=1e-12, atol=1e-12)
+        for k in acc:
+            acc[k] = acc[k] + m[k]
+    for k in acc:
+        assert torch.allclose(o[k], acc[k], rtol=1e-11, atol=1e-11), k
