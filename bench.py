@@ -13,6 +13,13 @@ from the 64-scene distribution, 10% at 262,144 receivers x 512 spheres)
 against the continuous-batching server and against one request at a time,
 per arrival rate; prints throughput and p50 / p99 latency.
 
+``--workload rgb``: the body-like scene with three colour channels (albedo
+and lighting per channel, one shared visibility, Eq. 8 per channel); one step
+= sh_visibility_forward, sh_shade_channels, sh_shade_channels_backward and
+sh_visibility_backward.  ``--workload envmap``: the lighting of a synthetic
+3 x 512 x 1024 equirectangular map projected onto 8 bands (Eq. 9) through
+sh_envmap_project; throughput in map pixels per second.
+
 ``--workload batched64``: 64 independent scenes (P ~ U{5k..50k}, S ~
 U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b); one step = the batched forward +
 backward over all 64, replayed from one captured graph; the same 64 scenes
@@ -46,7 +53,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="body", choices=["body", "gbuffer", "icosphere", "batched64", "serve"])
+    ap.add_argument("--workload", default="body",
+                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap"])
+    ap.add_argument("--channels", type=int, default=3, help="rgb / envmap: colour channels")
+    ap.add_argument("--map", default="512x1024", help="envmap: H x W of the equirectangular map")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--k", type=int, default=4)
@@ -425,6 +435,114 @@ def bench_serve(args):
     }
 
 
+def bench_rgb(args):
+    """Three colour channels sharing one visibility, body-like scene."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import _lib, ops, workmodel
+
+    sc = scenegen.scene_body()
+    C = args.channels
+    ch = scenegen.colour_channels(sc, C, seed=5)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    n, k = int(sc["n_bands"]), args.k
+    N, P, S = n * n, sc["points"].shape[0], sc["spheres"].shape[0]
+    prm = _lib.params(n, 3.0, k, args.flags)
+
+    def t(a):
+        return torch.as_tensor(np.ascontiguousarray(a)).to(dev)
+
+    pts, nrm, sph = t(sc["points"].T), t(sc["normals"].T), t(sc["spheres"])
+    alb, lig, gB = t(ch["albedo"].T), t(ch["light"]), t(ch["grad_radiance"].T)
+    vis = torch.empty(N, P, device=dev)
+    saved = torch.empty(_lib.shv_saved_floats(P, prm), device=dev)
+    rad = torch.empty(C, P, device=dev)
+    gV, gN, gA = torch.empty(N, P, device=dev), torch.empty(3, P, device=dev), torch.empty(C, P, device=dev)
+    gL, gP, gS = torch.empty(C, N, device=dev), torch.empty(3, P, device=dev), torch.empty(S, 4, device=dev)
+    nb = max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    st = stream.cuda_stream
+
+    def step():
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+        _lib.sh_shade_channels(vis, nrm, alb, lig, C, P, prm, rad, ws, nb, st)
+        _lib.sh_shade_channels_backward(gB, vis, nrm, alb, lig, C, P, prm, gV, gN, gA, gL, ws, nb, st)
+        _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
+
+    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    kernels = kernel_table(prof)
+    roof = roofline(kernels, sampled_steps(args.steps),
+                    lambda name: workmodel.kernel_work(name, n, k, P, S, channels=C))
+    if roof is not None:
+        roof["traffic"] = measured_traffic("rgb", roof["kernel"])
+    return {
+        "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"body-like scene, {C} colour channels sharing one visibility: 20000 receivers x "
+                               "128 spheres, 8 bands, k=4, fwd+bwd", "receivers": P, "spheres": S, "n_bands": n,
+                   "n_squarings": k, "channels": C},
+        "roofline": roof, "cpu_baseline": None, "kernels": finish_kernels(kernels),
+    }
+
+
+def bench_envmap(args):
+    """Eq. 9 on a synthetic equirectangular HDR map."""
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import _lib, ops, workmodel
+
+    H, W = (int(v) for v in args.map.lower().split("x"))
+    C, n = args.channels, 8
+    img_h = scenegen.envmap_image(seed=0, C=C, H=H, W=W)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    prm = _lib.params(n)
+    img = torch.as_tensor(img_h).to(dev)
+    out = torch.empty(C, n * n, device=dev)
+    nb = _lib.shv_envmap_workspace_bytes(C, H, W, prm)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    st = stream.cuda_stream
+
+    def step():
+        _lib.sh_envmap_project(img, C, H, W, prm, out, ws, nb, st)
+
+    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    kernels = kernel_table(prof)
+    pixels = C * H * W
+    roof = roofline(kernels, sampled_steps(args.steps),
+                    lambda name: workmodel.kernel_work(name, n, 0, 0, 0, pixels=pixels))
+    cpu = None
+    if args.cpu_seconds > 0:
+        from oracle import sh
+        t0 = time.perf_counter()
+        reps = 0
+        small = img_h[:, :H // 4]          # a quarter of the rows per repetition
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0):
+            sh.envmap_to_sh(small, n)
+            reps += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": reps * small.size / dt, "unit": "pixels/s", "cores": torch.get_num_threads(),
+               "kind": "oracle", "sample": f"{reps} projections of the map's first {H // 4} rows "
+                                           f"({small.size} pixels), FP64, {dt:.1f} s"}
+    return {
+        "metric": "environment-map pixels projected/s", "value": pixels / (ms * 1e-3), "unit": "pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"equirectangular map {C} x {H} x {W} -> {n} bands (Eq. 9)", "channels": C,
+                   "rows": H, "cols": W, "n_bands": n},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -435,6 +553,10 @@ def main():
         out = bench_batched(args)
     elif args.workload == "serve":
         out = bench_serve(args)
+    elif args.workload == "rgb":
+        out = bench_rgb(args)
+    elif args.workload == "envmap":
+        out = bench_envmap(args)
     else:
         out = bench_single(args)
     print(json.dumps(out))

@@ -216,7 +216,8 @@ size_t channels_bytes(int64_t P, int channels, int nb, ChannelWs* o = nullptr) {
   }
   return m + lp;
 }
-// Environment map: the per-row partial sums [channels][H][N].
+// Environment map: the per-row-block partial sums [channels][row blocks][N]
+// (at most one block per row).
 size_t envmap_bytes(int channels, int64_t H, int nb) {
   return align_up((size_t)channels * (size_t)H * nb * nb * 4);
 }
@@ -567,9 +568,10 @@ shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_
   float* part = (float*)ws;
   SHV_TRY(launch("envmap_rows", stream,
                  [&] { return shv::launch_envmap_rows(nb, image, channels, H, W, part, stream); }));
+  const int rows = (int)shv::envmap_row_blocks(H, W);
   for (int c = 0; c < channels; ++c)
     SHV_TRY(launch("reduce_envmap", stream, [&] {
-      return shv::launch_reduce_rows(part + (size_t)c * H * N, (int)H, N, light + (size_t)c * N, stream);
+      return shv::launch_reduce_rows(part + (size_t)c * rows * N, rows, N, light + (size_t)c * N, stream);
     }));
   return SHV_OK;
 }

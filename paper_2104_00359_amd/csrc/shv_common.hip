@@ -281,6 +281,11 @@ hipError_t launch_shade_ch_bwd(int nb, const float* gB, const float* vis, const 
 #undef C
 }
 
+int64_t envmap_row_blocks(int64_t H, int64_t W) {
+  const int64_t R = envmap_rows_per_block(W);
+  return (H + R - 1) / R;
+}
+
 hipError_t launch_envmap_rows(int nb, const float* img, int channels, int64_t H, int64_t W, float* part,
                               hipStream_t st) {
 #define C(N) envmap_rows_nb<N>(img, channels, H, W, part, st)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "shv_config.h"
+
 namespace shv {
 
 // Split of the sphere set into chunks for the pair kernels ("split-S"): the
@@ -39,9 +41,16 @@ hipError_t launch_shade_ch_fwd(int nb, const float* vis, const float* nrm, const
 hipError_t launch_shade_ch_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
                                const float* M, int channels, int64_t P, float* gV, float* gN, float* gA,
                                float* Lpart, hipStream_t st);
-// Per-row partial sums of Eq. 9 over an equirectangular map [channels][H][W] -> part [channels][H][N].
+// Partial sums of Eq. 9 over an equirectangular map [channels][H][W], one per block of
+// envmap_row_blocks(H, W) row blocks -> part [channels][row blocks][N].
 hipError_t launch_envmap_rows(int nb, const float* img, int channels, int64_t H, int64_t W, float* part,
                               hipStream_t st);
+int64_t envmap_row_blocks(int64_t H, int64_t W);
+// Rows per block of that projection: about 4096 pixels per block.
+inline int envmap_rows_per_block(int64_t W) {
+  const int64_t r = (4096 + W - 1) / W;
+  return (int)(r < 1 ? 1 : (r > SHV_ENV_MAX_ROWS ? SHV_ENV_MAX_ROWS : r));
+}
 hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P,
                           float eps, int k, float* W, uint32_t flags, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,

@@ -84,14 +84,20 @@ __device__ __forceinline__ void stage_M(const float* __restrict__ M, float* Ms, 
 __device__ __forceinline__ constexpr bool h_support(int l) { return l <= 2 || (l % 2) == 0; }
 
 // H_lm = A_l y_lm(n_hat) on the support (0 elsewhere); returns 1/|n|.
-template <int NB>
-__device__ __forceinline__ float transfer(float nx, float ny, float nz, float (&H)[NB * NB], float& ux, float& uy,
-                                          float& uz) {
+// n / |n| and 1 / |n|.
+__device__ __forceinline__ float unit_normal(float nx, float ny, float nz, float& ux, float& uy, float& uz) {
   const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
   const float inv = fast_rsqrt(n2);
   ux = nx * inv;
   uy = ny * inv;
   uz = nz * inv;
+  return inv;
+}
+
+template <int NB>
+__device__ __forceinline__ float transfer(float nx, float ny, float nz, float (&H)[NB * NB], float& ux, float& uy,
+                                          float& uz) {
+  const float inv = unit_normal(nx, ny, nz, ux, uy, uz);
   sh_eval<NB>(ux, uy, uz, H);
 #pragma unroll
   for (int l = 0; l < NB; ++l) {
@@ -108,6 +114,18 @@ template <int NB, int G, bool ADJ, bool ACC = false>
 __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const float (&H)[NB * NB],
                                                const float* Ms, float w, float (&Hb)[NB * NB]) {
   constexpr int N = NB * NB;
+  constexpr int CPG = MSupp<NB>::CPG;
+  constexpr int NC = (MTab<NB>::HS - G + 3) / 4;  // this group's columns kk = G, G + 4, ...
+  // t_kk = sum_j M_jk V_j, j in index order for every column; the group's
+  // columns of one row are contiguous in Ms (vector LDS reads)
+  float t[CPG];
+#pragma unroll
+  for (int c = 0; c < CPG; ++c) t[c] = 0.0f;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = fmaf(Ms[MSupp<NB>::at(j, 4 * c + G)], V[j], t[c]);
+  }
   float s = 0.0f;
   int kk = 0;
 #pragma unroll
@@ -118,12 +136,10 @@ __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const 
       const int k = idx(l, m);
       const int col = kk++;
       if ((col & 3) != G) continue;
-      float t = 0.0f;
-#pragma unroll
-      for (int j = 0; j < N; ++j) t = fmaf(Ms[MSupp<NB>::at(j, col)], V[j], t);
-      s = fmaf(H[k], t, s);
-      if (ADJ && ACC) Hb[k] += w * t * SHV_AHAT[l];
-      if (ADJ && !ACC) Hb[k] = w * t * SHV_AHAT[l];
+      const float tc = t[col >> 2];
+      s = fmaf(H[k], tc, s);
+      if (ADJ && ACC) Hb[k] += w * tc * SHV_AHAT[l];
+      if (ADJ && !ACC) Hb[k] = w * tc * SHV_AHAT[l];
     }
   }
   return s;
@@ -194,9 +210,11 @@ struct alignas(16) LightTile {
 // Q[j][kk] = sum_x Vt[x][j] Ht[x][kk] (x in order; thread (jj, kq) owns
 // j = 2jj, 2jj+1 and kk = 4kq .. 4kq+3), then Lbar partial
 // out[i] = sum_{(j,kk)} C_{i j k} Q[j][kk] (4 strided partials per i).
-// Ends with a barrier, so the tile may be refilled afterwards.
+// Ends with a barrier, so the tile may be refilled afterwards.  Q is staged
+// in the V rows unless a separate Qbuf (N x 32 floats) is given, in which
+// case the V rows are left intact.
 template <int NB>
-__device__ __forceinline__ void tile_light_partial(LightTile& T, float* __restrict__ out) {
+__device__ __forceinline__ void tile_light_partial(LightTile& T, float* __restrict__ out, float* Qbuf = nullptr) {
   constexpr int N = NB * NB;
   constexpr int HS = MTab<NB>::HS;
   const int tid = threadIdx.x;
@@ -220,7 +238,7 @@ __device__ __forceinline__ void tile_light_partial(LightTile& T, float* __restri
     }
   }
   __syncthreads();
-  float* Qs = T.Vt;  // N x 32, reuses the V rows
+  float* Qs = Qbuf ? Qbuf : T.Vt;  // N x 32
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
 #pragma unroll

@@ -108,98 +108,194 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict
 }
 
 // Several channels (CH of them, 1 .. SHV_MAX_CHANNELS): channel c's light
-// matrix at M + c N^2, albedo and radiance at alb + c P, rad + c P.
+// matrix at M + c N^2, albedo / radiance / cotangents at + c P.
+//
+// Layout: 64 receivers per block, four waves.  The V rows are loaded by the
+// four waves together (row i by wave i mod 4, coalesced over the 64
+// receivers) and exchanged through LDS; wave g then forms the shading
+// partial over support columns kk = g (mod 4) of every channel, exactly the
+// partial g of the canonical order, so the block adds them in that order.
 template <int NB, int CH>
-__global__ __launch_bounds__(SHV_BLOCK) void k_shade_ch_fwd(const float* __restrict__ vis,
+struct ShadeCh4Shared {
+  float X[NB * NB][64];        // V exchange (row i, receiver lane)
+  float Ms[CH * MSupp<NB>::SIZE];
+  float Bx[CH][4][64];         // shading partials per channel and column group
+};
+
+// Wave G's column group of every channel's shading value (the channel loop
+// inside the wave's branch, so only the group's columns of H stay live).
+template <int NB, int G, int CH>
+__device__ __forceinline__ void shade_ch_fwd_group(ShadeCh4Shared<NB, CH>& sh, const float (&V)[NB * NB],
+                                                   const float (&H)[NB * NB], int lane) {
+  float Hb[NB * NB];
+#pragma nounroll
+  for (int c = 0; c < CH; ++c)
+    sh.Bx[c][G][lane] = shade_partial<NB, G, false>(V, H, sh.Ms + c * MSupp<NB>::SIZE, 0.0f, Hb);
+}
+
+template <int NB, int CH>
+__global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_fwd(const float* __restrict__ vis,
                                                             const float* __restrict__ nrm,
                                                             const float* __restrict__ alb,
                                                             const float* __restrict__ M, int64_t P,
                                                             float* __restrict__ rad) {
   constexpr int N = NB * NB;
   constexpr int SZ = MSupp<NB>::SIZE;
-  __shared__ float Ms[CH * SZ];
+  __shared__ ShadeCh4Shared<NB, CH> sh;
+  const int G = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = p < P;
 #pragma unroll
-  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, Ms + c * SZ, threadIdx.x, SHV_BLOCK);
+  for (int i = 0; i < N; ++i)
+    if ((i & 3) == G) sh.X[i][lane] = ok ? vis[(int64_t)i * P + p] : 0.0f;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x, SHV_BLOCK);
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
-  if (p >= P) return;
-  float V[N], H[N], Hb[N];
+  float V[N], H[N], ux, uy, uz;
 #pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = vis[(int64_t)i * P + p];
-  float ux, uy, uz;
-  transfer<NB>(nrm[p], nrm[P + p], nrm[2 * P + p], H, ux, uy, uz);
+  for (int i = 0; i < N; ++i) V[i] = sh.X[i][lane];
+  transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
+  switch (G) {
+    case 0: shade_ch_fwd_group<NB, 0, CH>(sh, V, H, lane); break;
+    case 1: shade_ch_fwd_group<NB, 1, CH>(sh, V, H, lane); break;
+    case 2: shade_ch_fwd_group<NB, 2, CH>(sh, V, H, lane); break;
+    default: shade_ch_fwd_group<NB, 3, CH>(sh, V, H, lane); break;
+  }
+  __syncthreads();
+  if (!ok) return;
 #pragma unroll
   for (int c = 0; c < CH; ++c)
-    rad[c * P + p] = alb[c * P + p] * shade_value<NB, false>(V, H, Ms + c * SZ, 0.0f, Hb);
+    if ((c & 3) == G)
+      rad[c * P + p] = alb[c * P + p] * (((sh.Bx[c][0][lane] + sh.Bx[c][1][lane]) + sh.Bx[c][2][lane]) +
+                                         sh.Bx[c][3][lane]);
+}
+
+template <int NB, int CH>
+struct ShadeCh4BwdShared {
+  LightTile LT;                // its V rows hold the block's V (tile layout) throughout
+  float Ms[CH * MSupp<NB>::SIZE];
+  float Sx[CH][4][64];         // shading partials per channel and column group
+  union {
+    float HbX[32][64];         // y_k cotangents (summed over channels) on the transfer support
+    float Q[NB * NB * 32];     // later: the lighting GEMM's Q (apart from the V rows, which survive)
+  };
+  float HsX[32][64];           // H on the transfer support
+  float W[CH][64];             // w = Bbar a per channel and receiver
+};
+
+// Wave G's part of the adjoint: its column group of the shading value and of
+// the y_k cotangents (summed over channels), its column group of H kept in
+// LDS, and the V cotangent rows j = G (mod 4), each summed over the channels
+// in channel order.
+template <int NB, int G, int CH>
+__device__ __forceinline__ void shade_ch_bwd_group(ShadeCh4BwdShared<NB, CH>& sh, int lane, int64_t p, bool ok,
+                                                   int64_t P, const float* __restrict__ nrm,
+                                                   float* __restrict__ gV) {
+  constexpr int N = NB * NB;
+  constexpr int SZ = MSupp<NB>::SIZE;
+  float V[N], H[N], Hb[N], ux, uy, uz;
+#pragma unroll
+  for (int i = 0; i < N; ++i) V[i] = sh.LT.Vt[lane * kTileVS + i];
+  transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
+#pragma unroll
+  for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
+#pragma nounroll
+  for (int c = 0; c < CH; ++c)
+    sh.Sx[c][G][lane] = shade_partial<NB, G, true, true>(V, H, sh.Ms + c * SZ, sh.W[c][lane], Hb);
+  int kk = 0;
+#pragma unroll
+  for (int l = 0; l < NB; ++l) {
+    if (!h_support(l)) continue;
+#pragma unroll
+    for (int m = -l; m <= l; ++m) {
+      if ((kk & 3) == G) {
+        sh.HbX[kk][lane] = Hb[idx(l, m)];
+        sh.HsX[kk][lane] = H[idx(l, m)];
+      }
+      ++kk;
+    }
+  }
+  if (ok && gV) {
+#pragma nounroll
+    for (int j = G; j < N; j += 4) {
+      float acc = vbar_entry<NB>(j, H, sh.Ms, sh.W[0][lane]);
+#pragma nounroll
+      for (int c = 1; c < CH; ++c) acc += vbar_entry<NB>(j, H, sh.Ms + c * SZ, sh.W[c][lane]);
+      gV[(int64_t)j * P + p] = acc;
+    }
+  }
 }
 
 // Adjoint of k_shade_ch_fwd.  gB, gA [CH][P]; gV [N][P] and gN [3][P] summed
-// over the channels; Lpart [CH][ceil(P / 64)][N] tile partials.
+// over the channels; Lpart [CH][ceil(P / 64)][N]: one lighting-gradient
+// partial per block (tile of 64 receivers) and channel.
 template <int NB, int CH>
-__global__ __launch_bounds__(SHV_BLOCK) void k_shade_ch_bwd(const float* __restrict__ gB,
-                                                            const float* __restrict__ vis,
-                                                            const float* __restrict__ nrm,
-                                                            const float* __restrict__ alb,
-                                                            const float* __restrict__ M, int64_t P,
-                                                            float* __restrict__ gV, float* __restrict__ gN,
-                                                            float* __restrict__ gA, float* __restrict__ Lpart) {
+__global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_bwd(const float* __restrict__ gB,
+                                                               const float* __restrict__ vis,
+                                                               const float* __restrict__ nrm,
+                                                               const float* __restrict__ alb,
+                                                               const float* __restrict__ M, int64_t P,
+                                                               float* __restrict__ gV, float* __restrict__ gN,
+                                                               float* __restrict__ gA, float* __restrict__ Lpart) {
   constexpr int N = NB * NB;
   constexpr int SZ = MSupp<NB>::SIZE;
-  __shared__ LightTile T;
-  __shared__ float Ms[CH * SZ];
-#pragma unroll
-  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, Ms + c * SZ, threadIdx.x, SHV_BLOCK);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  constexpr int HS = MTab<NB>::HS;
+  __shared__ ShadeCh4BwdShared<NB, CH> sh;
+  const int G = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t tile = blockIdx.x;
+  const int64_t p = tile * 64 + lane;
   const bool ok = p < P;
-  float V[N], H[N], Hb[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = ok ? vis[(int64_t)i * P + p] : 0.0f;
-  float ux, uy, uz;
-  const float inv = transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
+  for (int i = 0; i < N; ++i)
+    if ((i & 3) == G) sh.LT.Vt[lane * kTileVS + i] = ok ? vis[(int64_t)i * P + p] : 0.0f;
 #pragma unroll
-  for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
-  float w[CH];
+  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x, SHV_BLOCK);
+  if (G == 0) {
 #pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const float bb = ok ? gB[c * P + p] : 0.0f;
-    w[c] = bb * (ok ? alb[c * P + p] : 0.0f);
-    const float s = shade_value_acc<NB>(V, H, Ms + c * SZ, w[c], Hb);
-    if (ok && gA) gA[c * P + p] = bb * s;
+    for (int c = 0; c < CH; ++c) sh.W[c][lane] = ok ? gB[c * P + p] * alb[c * P + p] : 0.0f;
   }
-  if (ok) {
-    if (gV) {
+  __syncthreads();
+  switch (G) {
+    case 0: shade_ch_bwd_group<NB, 0, CH>(sh, lane, p, ok, P, nrm, gV); break;
+    case 1: shade_ch_bwd_group<NB, 1, CH>(sh, lane, p, ok, P, nrm, gV); break;
+    case 2: shade_ch_bwd_group<NB, 2, CH>(sh, lane, p, ok, P, nrm, gV); break;
+    default: shade_ch_bwd_group<NB, 3, CH>(sh, lane, p, ok, P, nrm, gV); break;
+  }
+  __syncthreads();  // Sx, HbX, HsX complete
+  if (G == 0 && ok && gA) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        float acc = vbar_entry<NB>(j, H, Ms, w[0]);
+    for (int c = 0; c < CH; ++c)
+      gA[c * P + p] = gB[c * P + p] *
+                      (((sh.Sx[c][0][lane] + sh.Sx[c][1][lane]) + sh.Sx[c][2][lane]) + sh.Sx[c][3][lane]);
+  }
+  if (G == 1 && ok && gN) {
+    float Hb[N], ux, uy, uz;
+    const float inv = unit_normal(nrm[p], nrm[P + p], nrm[2 * P + p], ux, uy, uz);
 #pragma unroll
-        for (int c = 1; c < CH; ++c) acc += vbar_entry<NB>(j, H, Ms + c * SZ, w[c]);
-        gV[(int64_t)j * P + p] = acc;
-      }
+    for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
+    int kk = 0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      if (!h_support(l)) continue;
+#pragma unroll
+      for (int m = -l; m <= l; ++m) Hb[idx(l, m)] = sh.HbX[kk++][lane];
     }
-    if (gN) {
-      float gx, gy, gz;
-      normal_grad<NB>(Hb, ux, uy, uz, inv, gx, gy, gz);
-      gN[p] = gx;
-      gN[P + p] = gy;
-      gN[2 * P + p] = gz;
-    }
+    float gx, gy, gz;
+    normal_grad<NB>(Hb, ux, uy, uz, inv, gx, gy, gz);
+    gN[p] = gx;
+    gN[P + p] = gy;
+    gN[2 * P + p] = gz;
   }
   if (!Lpart) return;  // uniform
+  // Q overlays HbX: wave 1 has read HbX before it reaches the first barrier
+  // below, and Q is written only after the GEMM's own barrier.
   const int64_t tiles = (P + 63) / 64;
-  for (int r = 0; r < SHV_WAVES_PER_BLOCK; ++r) {
-    const int64_t tile = (int64_t)blockIdx.x * SHV_WAVES_PER_BLOCK + r;
-    if (tile * 64 >= P) break;  // uniform
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      if (wave == r) {  // the V rows too: tile_light_partial reuses them for Q
-        tile_put_v<NB>(T, lane, V);
-        tile_put_wh<NB>(T, lane, H, w[c]);
-      }
-      __syncthreads();
-      tile_light_partial<NB>(T, Lpart + (c * tiles + tile) * N);
-    }
+#pragma nounroll
+  for (int c = 0; c < CH; ++c) {
+    // w H rows of this channel (the V rows are already in place)
+    for (int kk = G; kk < HS; kk += 4) sh.LT.Ht[lane * kTileHS + kk] = sh.W[c][lane] * sh.HsX[kk][lane];
+    __syncthreads();
+    tile_light_partial<NB>(sh.LT, Lpart + (c * tiles + tile) * N, sh.Q);
   }
 }
 
@@ -207,48 +303,59 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_ch_bwd(const float* __restr
 // angles [r, r + 1] pi / H from +z, column x azimuths [x, x + 1] 2 pi / W;
 // a pixel's solid angle is (cos th_r - cos th_{r+1}) 2 pi / W, evaluated as
 // 2 sin(th_centre) sin(pi / 2H) 2 pi / W (no cancellation near the poles).
-// Block (r, c) writes part[(c H + r) N + i] = sum over the row's pixels of
-// value * y_i(centre direction) * solid angle.  Lanes stride over the row,
-// the 64 lanes of a wave are summed by a fixed butterfly and the four waves
-// in order.
+// Block (b, c) covers rows [b R, b R + R) of channel c: each lane takes the
+// columns x = lane, lane + 256, ... (the azimuth's sine and cosine once per
+// column) over those rows and accumulates value * solid angle * y_i; the
+// block's 256 x N sums are then added through LDS in a fixed order (64-lane
+// quarters, then the four quarters in order) into
+// part[(c * gridDim.x + b) * N + i].
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_envmap_rows(const float* __restrict__ img, int64_t H, int64_t W,
-                                                           float* __restrict__ part) {
+                                                           int R, float* __restrict__ part) {
   constexpr int N = NB * NB;
-  __shared__ float red[SHV_WAVES_PER_BLOCK][N];
-  const int64_t r = blockIdx.x;
+  __shared__ float red[SHV_BLOCK * (N + 1)];
+  __shared__ float rs[SHV_ENV_MAX_ROWS], rc[SHV_ENV_MAX_ROWS], rw[SHV_ENV_MAX_ROWS];
   const int c = blockIdx.y;
-  const double th = (double)M_PI * ((double)r + 0.5) / (double)H;
-  const float st = (float)sin(th), ct = (float)cos(th);
-  const float wrow = (float)(2.0 * sin(th) * sin(M_PI / (2.0 * (double)H)) * (2.0 * M_PI / (double)W));
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)((H - r0) < R ? (H - r0) : R);
+  const int tid = threadIdx.x;
+  if (tid < nr) {
+    const double th = (double)M_PI * ((double)(r0 + tid) + 0.5) / (double)H;
+    rs[tid] = (float)sin(th);
+    rc[tid] = (float)cos(th);
+    rw[tid] = (float)(2.0 * sin(th) * sin(M_PI / (2.0 * (double)H)) * (2.0 * M_PI / (double)W));
+  }
+  __syncthreads();
   const float dphi = (float)(2.0 * M_PI / (double)W);
-  const float* row = img + ((int64_t)c * H + r) * W;
+  const float* base = img + ((int64_t)c * H + r0) * W;
   float acc[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) acc[i] = 0.0f;
-  for (int64_t x = threadIdx.x; x < W; x += SHV_BLOCK) {
+  for (int64_t x = tid; x < W; x += SHV_BLOCK) {
     float sp, cp;
     sincosf(((float)x + 0.5f) * dphi, &sp, &cp);
-    float Y[N];
-    sh_eval<NB>(st * cp, st * sp, ct, Y);
-    const float v = row[x];
+    for (int r = 0; r < nr; ++r) {
+      const float st = rs[r];
+      float Y[N];
+      sh_eval<NB>(st * cp, st * sp, rc[r], Y);
+      const float v = base[(int64_t)r * W + x] * rw[r];
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = fmaf(v, Y[i], acc[i]);
+      for (int i = 0; i < N; ++i) acc[i] = fmaf(v, Y[i], acc[i]);
+    }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const float t = wave_sum(acc[i]);
-    if (lane == 0) red[wave][i] = t;
+  for (int i = 0; i < N; ++i) red[tid * (N + 1) + i] = acc[i];
+  __syncthreads();
+  const int i = tid & 63, q = tid >> 6;
+  float s = 0.0f;
+  if (i < N) {
+    for (int x = 0; x < 64; ++x) s += red[(q * 64 + x) * (N + 1) + i];
   }
   __syncthreads();
-  if (threadIdx.x < N) {
-    const int i = threadIdx.x;
-    float s = red[0][i];
-#pragma unroll
-    for (int g = 1; g < SHV_WAVES_PER_BLOCK; ++g) s += red[g][i];
-    part[((int64_t)c * H + r) * N + i] = s * wrow;
-  }
+  if (i < N) red[q * 64 + i] = s;
+  __syncthreads();
+  if (tid < N)
+    part[((int64_t)c * gridDim.x + blockIdx.x) * N + tid] = ((red[tid] + red[64 + tid]) + red[128 + tid]) + red[192 + tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -278,7 +385,7 @@ hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, con
 template <int NB>
 hipError_t shade_ch_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int channels,
                            int64_t P, float* rad, hipStream_t st) {
-  const unsigned g = (unsigned)point_blocks(P);
+  const unsigned g = (unsigned)pair_blocks(P);
   switch (channels) {
     case 1: k_shade_ch_fwd<NB, 1><<<g, SHV_BLOCK, 0, st>>>(vis, nrm, alb, M, P, rad); break;
     case 2: k_shade_ch_fwd<NB, 2><<<g, SHV_BLOCK, 0, st>>>(vis, nrm, alb, M, P, rad); break;
@@ -292,7 +399,7 @@ hipError_t shade_ch_fwd_nb(const float* vis, const float* nrm, const float* alb,
 template <int NB>
 hipError_t shade_ch_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
                            int channels, int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st) {
-  const unsigned g = (unsigned)point_blocks(P);
+  const unsigned g = (unsigned)pair_blocks(P);
   switch (channels) {
 #define SHV_CH_BWD(c) \
   case c: k_shade_ch_bwd<NB, c><<<g, SHV_BLOCK, 0, st>>>(gB, vis, nrm, alb, M, P, gV, gN, gA, Lpart); break;
@@ -308,7 +415,9 @@ hipError_t shade_ch_bwd_nb(const float* gB, const float* vis, const float* nrm, 
 
 template <int NB>
 hipError_t envmap_rows_nb(const float* img, int channels, int64_t H, int64_t W, float* part, hipStream_t st) {
-  k_envmap_rows<NB><<<dim3((unsigned)H, (unsigned)channels), SHV_BLOCK, 0, st>>>(img, H, W, part);
+  const int R = envmap_rows_per_block(W);
+  const unsigned nblk = (unsigned)((H + R - 1) / R);
+  k_envmap_rows<NB><<<dim3(nblk, (unsigned)channels), SHV_BLOCK, 0, st>>>(img, H, W, R, part);
   return hipGetLastError();
 }
 

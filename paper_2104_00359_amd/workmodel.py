@@ -97,6 +97,36 @@ def shade_bwd_flops(n: int) -> int:
     return h + mv + vbar + nbar + lbar
 
 
+def shade_ch_fwd_flops(n: int, channels: int) -> int:
+    """Several channels: the transfer once, V^T M_c H per channel."""
+    c = _gaunt_counts(n)
+    N = n * n
+    return 12 + 3 * N + channels * (c["supp"] * (2 * N + 2) + 1)
+
+
+def shade_ch_bwd_flops(n: int, channels: int) -> int:
+    """Several channels: the transfer and the normal cotangent once, the
+    shading value, V and H cotangents and the lighting GEMM per channel (the
+    channel sums of the V and H cotangents are one add per entry)."""
+    c = _gaunt_counts(n)
+    N = n * n
+    h = 12 + 3 * N
+    mv = c["supp"] * (2 * N + 4)
+    vbar = N * (2 * c["supp"] + 2)
+    nbar = 10 * N + 15
+    lbar = c["supp"] + 2 * N * c["supp"]
+    return h + nbar + channels * (mv + vbar + lbar)
+
+
+def envmap_pixel_flops(n: int) -> int:
+    """One map pixel: sin and cos of its azimuth, the direction (3), the
+    polynomial SH basis (powers of x + i y, three-term recurrences in z, one
+    normalising multiply per coefficient) and one FMA per coefficient."""
+    N = n * n
+    basis = 6 * max(n - 1, 0) + 3 * n * (n - 1) // 2 + N
+    return 2 + 3 + basis + 2 * N
+
+
 # Bytes each kernel must move to / from HBM per unit (FP32).
 def exp_fwd_bytes(n: int, k: int, nchunks: int) -> int:
     N = n * n
@@ -107,8 +137,16 @@ def pair_fwd_bytes_per_receiver(n: int, nchunks: int) -> int:
     return 4 * (3 * nchunks + n * n * nchunks)
 
 
-def kernel_work(name: str, n: int, k: int, P: int, S: int):
-    """(flops, unit count) of one launch of kernel ``name``."""
+def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pixels: int = 0):
+    """(flops, unit count) of one launch of kernel ``name`` (``channels``
+    for the multi-channel shading kernels, ``pixels`` = C H W for the
+    environment-map projection)."""
+    if name == "shade_ch_fwd":
+        return shade_ch_fwd_flops(n, channels) * P, P
+    if name == "shade_ch_bwd":
+        return shade_ch_bwd_flops(n, channels) * P, P
+    if name == "envmap_rows":
+        return envmap_pixel_flops(n) * pixels, pixels
     if name == "pair_fwd":
         return pair_fwd_flops(n) * P * S, P * S
     if name == "pair_bwd":
