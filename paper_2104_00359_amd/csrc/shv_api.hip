@@ -485,13 +485,10 @@ shv_status sh_shade_channels(const float* vis, const float* normals, const float
   SHV_TRY(need(light, "light"));
   SHV_TRY(need(radiance, "radiance"));
   const int nb = prm->n_bands;
-  const int N = nb * nb;
   ChannelWs L;
   SHV_TRY(check_ws(ws, ws_bytes, channels_bytes(P, channels, nb, &L)));
   float* M = (float*)((char*)ws + L.M);
-  for (int c = 0; c < channels; ++c)
-    SHV_TRY(launch("build_M", stream,
-                   [&] { return shv::launch_build_M(nb, light + (size_t)c * N, M + (size_t)c * N * N, stream); }));
+  SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream, channels); }));
   SHV_TRY(launch("shade_ch_fwd", stream, [&] {
     return shv::launch_shade_ch_fwd(nb, vis, normals, albedo, M, channels, P, radiance, stream);
   }));
@@ -524,19 +521,15 @@ shv_status sh_shade_channels_backward(const float* grad_radiance, const float* v
   SHV_TRY(check_ws(ws, ws_bytes, channels_bytes(P, channels, nb, &L)));
   float* M = (float*)((char*)ws + L.M);
   float* Lpart = grad_light ? (float*)((char*)ws + L.lpart) : nullptr;
-  for (int c = 0; c < channels; ++c)
-    SHV_TRY(launch("build_M", stream,
-                   [&] { return shv::launch_build_M(nb, light + (size_t)c * N, M + (size_t)c * N * N, stream); }));
+  SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream, channels); }));
   SHV_TRY(launch("shade_ch_bwd", stream, [&] {
     return shv::launch_shade_ch_bwd(nb, grad_radiance, vis, normals, albedo, M, channels, P, grad_vis,
                                     grad_normals, grad_albedo, Lpart, stream);
   }));
   if (grad_light) {
-    const int rows = (int)shv::pair_blocks(P);
-    for (int c = 0; c < channels; ++c)
-      SHV_TRY(launch("reduce_light", stream, [&] {
-        return shv::launch_reduce_rows(Lpart + (size_t)c * rows * N, rows, N, grad_light + (size_t)c * N, stream);
-      }));
+    SHV_TRY(launch("reduce_light", stream, [&] {
+      return shv::launch_reduce_rows(Lpart, (int)shv::pair_blocks(P), N, grad_light, stream, channels);
+    }));
   }
   return SHV_OK;
 }
@@ -568,11 +561,9 @@ shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_
   float* part = (float*)ws;
   SHV_TRY(launch("envmap_rows", stream,
                  [&] { return shv::launch_envmap_rows(nb, image, channels, H, W, part, stream); }));
-  const int rows = (int)shv::envmap_row_blocks(H, W);
-  for (int c = 0; c < channels; ++c)
-    SHV_TRY(launch("reduce_envmap", stream, [&] {
-      return shv::launch_reduce_rows(part + (size_t)c * rows * N, rows, N, light + (size_t)c * N, stream);
-    }));
+  SHV_TRY(launch("reduce_envmap", stream, [&] {
+    return shv::launch_reduce_rows(part, (int)shv::envmap_row_blocks(H, W), N, light, stream, channels);
+  }));
   return SHV_OK;
 }
 

@@ -102,10 +102,12 @@ __device__ __forceinline__ void reduce_columns(const float* __restrict__ part, i
 // Blocks of kColsPerBlock columns.
 __host__ __device__ __forceinline__ int column_blocks(int cols) { return (cols + kColsPerBlock - 1) / kColsPerBlock; }
 
+// Batch y = blockIdx.y reduces part + y rows cols into out + y cols.
 __global__ __launch_bounds__(SHV_BLOCK) void k_reduce_rows(const float* __restrict__ part, int rows, int cols,
                                                            float* __restrict__ out) {
   __shared__ float buf[SHV_BLOCK];
-  reduce_columns(part, rows, cols, blockIdx.x, out, buf);
+  const int64_t y = blockIdx.y;
+  reduce_columns(part + y * rows * cols, rows, cols, blockIdx.x, out + y * cols, buf);
 }
 
 // All reductions that close a backward pass, in one launch: blocks
@@ -152,9 +154,9 @@ hipError_t launch_finalize(const float* gp_part, int nchunks, int64_t P, float* 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st) {
-  if (cols <= 0) return hipSuccess;
-  k_reduce_rows<<<(unsigned)column_blocks(cols), SHV_BLOCK, 0, st>>>(part, rows, cols, out);
+hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st, int batch) {
+  if (cols <= 0 || batch <= 0) return hipSuccess;
+  k_reduce_rows<<<dim3((unsigned)column_blocks(cols), (unsigned)batch), SHV_BLOCK, 0, st>>>(part, rows, cols, out);
   return hipGetLastError();
 }
 
@@ -245,8 +247,8 @@ hipError_t launch_render_exp_bwd(int nb, const float* gB, const float* vis, cons
 #undef C
 }
 
-hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st) {
-#define C(N) build_M_nb<N>(light, M, st)
+hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st, int channels) {
+#define C(N) build_M_nb<N>(light, M, channels, st)
   SHV_NB_SWITCH(nb, C)
 #undef C
 }

@@ -129,6 +129,12 @@ __device__ __forceinline__ void sh_grad(float x, float y, float z, const float (
   }
 }
 
+// v on an in-range lane, `other` on a tail lane.  The load that produces v
+// reads a clamped, always valid address (receiver 0 instead of a receiver
+// past the end), so the compiler places no branch around it and a group of
+// such loads is in flight together.
+__device__ __forceinline__ float sel0(bool ok, float v, float other = 0.0f) { return ok ? v : other; }
+
 // Sum over the 64 lanes of a wave; every lane receives the total.  Fixed
 // butterfly order, so the result is deterministic.
 __device__ __forceinline__ float wave_sum(float v) {

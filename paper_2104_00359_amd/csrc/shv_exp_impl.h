@@ -184,9 +184,10 @@ struct ShadeArgs {
 
 __device__ __forceinline__ void load_normal(const float* nrm, int64_t P, int64_t p, bool ok, float& x, float& y,
                                             float& z) {
-  x = ok ? nrm[p] : 0.0f;
-  y = ok ? nrm[P + p] : 0.0f;
-  z = ok ? nrm[2 * P + p] : 1.0f;
+  const int64_t q = ok ? p : 0;
+  x = sel0(ok, nrm[q]);
+  y = sel0(ok, nrm[P + q]);
+  z = sel0(ok, nrm[2 * P + q], 1.0f);
 }
 
 // ===========================================================================
@@ -199,7 +200,7 @@ __device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, i
                                               const ShadeArgs& sa, int64_t bx, float* Ms) {
   constexpr int N = NB * NB;
   if constexpr (SHADE) {
-    stage_M<NB>(sa.M, Ms, threadIdx.x, SHV_BLOCK);
+    stage_M<NB>(sa.M, Ms, threadIdx.x);
     __syncthreads();
   }
   const int64_t p = bx * SHV_BLOCK + threadIdx.x;
@@ -258,14 +259,15 @@ __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, con
   constexpr int N = NB * NB;
   const int64_t p = bx * SHV_BLOCK + threadIdx.x;
   const bool ok = p < P;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
   if (!SHADE && !ok) return;  // no barriers in the unfused kernel
   if constexpr (SHADE) {
-    stage_M<NB>(sa.M, Ms, threadIdx.x, SHV_BLOCK);
+    stage_M<NB>(sa.M, Ms, threadIdx.x);
     __syncthreads();
   }
   float Eb[N], E[N], T[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) E[i] = ok ? vis[(int64_t)i * P + p] : 0.0f;  // V
+  for (int i = 0; i < N; ++i) E[i] = sel0(ok, vis[(int64_t)i * P + q]);  // V
   if constexpr (SHADE) {
     // gIn is the radiance cotangent: shading adjoint first (Vbar into Eb).
     LightTile& LT = *LTp;
@@ -275,8 +277,8 @@ __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, con
     for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
     load_normal(sa.nrm, P, p, ok, nx, ny, nz);
     const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
-    const float bb = ok ? gIn[p] : 0.0f;
-    const float w = bb * (ok ? sa.alb[p] : 0.0f);
+    const float bb = sel0(ok, gIn[q]);
+    const float w = bb * sel0(ok, sa.alb[q]);
     const float s = shade_value<NB, true>(E, H, Ms, w, Hb);
     if (ok && sa.gA) sa.gA[p] = bb * s;
     if (ok && sa.gN) {
@@ -346,17 +348,18 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
                                               int k, float* __restrict__ vis, float* __restrict__ saved,
                                               const ShadeArgs& sa) {
   constexpr int N = NB * NB;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
   // Sphere-chunk partials of this wave's group, summed in chunk order; the
   // loads of one chunk are issued together.
   float F[N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    if (fgroup_of<NB>(i) == G) F[i] = ok ? Fpart[(int64_t)i * P + p] : 0.0f;
+    if (fgroup_of<NB>(i) == G) F[i] = sel0(ok, Fpart[(int64_t)i * P + q]);
   for (int c = 1; c < nchunks; ++c) {
-    const float* src = Fpart + (int64_t)c * N * P + p;
+    const float* src = Fpart + (int64_t)c * N * P + q;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (fgroup_of<NB>(i) == G) F[i] += ok ? src[(int64_t)i * P] : 0.0f;
+      if (fgroup_of<NB>(i) == G) F[i] += sel0(ok, src[(int64_t)i * P]);
   }
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -395,7 +398,7 @@ __device__ __forceinline__ void exp_fwd_group(float (*X)[NB * NB][64], float (*B
     // After the last barrier above every wave has read its final squares:
     // the other exchange buffer is free for the staged M.
     float* Ms = &X[(k + 1) & 1][0][0];
-    stage_M<NB>(sa.M, Ms, G * 64 + lane, SHV_BLOCK);
+    stage_M<NB>(sa.M, Ms, G * 64 + lane);
     float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
     load_normal(sa.nrm, P, p, ok, nx, ny, nz);
     transfer<NB>(nx, ny, nz, H, ux, uy, uz);
@@ -449,7 +452,8 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
                                               int64_t P, float eps, int k, float* __restrict__ Wout,
                                               const ShadeArgs& sa) {
   constexpr int N = NB * NB;
-  const float c = ok ? saved[p] : 0.0f;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  const float c = sel0(ok, saved[q]);
   const float ec = expf(c);
   float Eb[N], E[N], T[N];
   if constexpr (!SHADE) {
@@ -458,8 +462,8 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       if (group_of<NB>(i) != G) continue;
-      const float vb = ok ? gIn[(int64_t)i * P + p] : 0.0f;
-      const float v = ok ? vis[(int64_t)i * P + p] : 0.0f;
+      const float vb = sel0(ok, gIn[(int64_t)i * P + q]);
+      const float v = sel0(ok, vis[(int64_t)i * P + q]);
       part = fmaf(vb, v, part);
       X[1][i][lane] = vb;
       X[0][i][lane] = v;
@@ -471,16 +475,16 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     // the waves
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) X[0][i][lane] = ok ? vis[(int64_t)i * P + p] : 0.0f;
-    stage_M<NB>(sa.M, Ms, G * 64 + lane, SHV_BLOCK);
+      if (group_of<NB>(i) == G) X[0][i][lane] = sel0(ok, vis[(int64_t)i * P + q]);
+    stage_M<NB>(sa.M, Ms, G * 64 + lane);
     __syncthreads();
     float V[N], H[N], Hb[N], nx, ny, nz, ux, uy, uz;
 #pragma unroll
     for (int i = 0; i < N; ++i) V[i] = X[0][i][lane];
     load_normal(sa.nrm, P, p, ok, nx, ny, nz);
     const float inv = transfer<NB>(nx, ny, nz, H, ux, uy, uz);
-    const float bb = ok ? gIn[p] : 0.0f;
-    const float w = bb * (ok ? sa.alb[p] : 0.0f);
+    const float bb = sel0(ok, gIn[q]);
+    const float w = bb * sel0(ok, sa.alb[q]);
     sh.Sx[G][lane] = shade_partial<NB, G, true>(V, H, Ms, w, Hb);
     {
       int kk = 0;
@@ -536,10 +540,10 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
   // flight during the previous step's product (barriers wait on LDS only).
   float pre[N];
   if (k > 0) {
-    const float* src = saved + (int64_t)(1 + (k - 1) * N) * P + p;
+    const float* src = saved + (int64_t)(1 + (k - 1) * N) * P + q;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) pre[i] = ok ? src[(int64_t)i * P] : 0.0f;
+      if (group_of<NB>(i) == G) pre[i] = sel0(ok, src[(int64_t)i * P]);
   }
   for (int j = k - 1; j >= 0; --j) {
     __syncthreads();  // everyone has read X[0] / X[1] of the previous step
@@ -547,10 +551,10 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     for (int i = 0; i < N; ++i)
       if (group_of<NB>(i) == G) X[0][i][lane] = pre[i];
     if (j > 0) {
-      const float* src = saved + (int64_t)(1 + (j - 1) * N) * P + p;
+      const float* src = saved + (int64_t)(1 + (j - 1) * N) * P + q;
 #pragma unroll
       for (int i = 0; i < N; ++i)
-        if (group_of<NB>(i) == G) pre[i] = ok ? src[(int64_t)i * P] : 0.0f;
+        if (group_of<NB>(i) == G) pre[i] = sel0(ok, src[(int64_t)i * P]);
     }
     __syncthreads();
 #pragma unroll

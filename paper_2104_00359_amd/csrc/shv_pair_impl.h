@@ -74,9 +74,10 @@ __device__ __forceinline__ void pair_fwd_item(const float* __restrict__ pts, int
   const bool ok = p < P;
   const int s0 = by * chunk;
   const int s1 = min(S, s0 + chunk);
-  const float px = ok ? pts[p] : 0.0f;
-  const float py = ok ? pts[P + p] : 0.0f;
-  const float pz = ok ? pts[2 * P + p] : 0.0f;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  const float px = sel0(ok, pts[q]);
+  const float py = sel0(ok, pts[P + q]);
+  const float pz = sel0(ok, pts[2 * P + q]);
 
   float acc[N];
 #pragma unroll
@@ -167,9 +168,10 @@ __device__ __forceinline__ void pair_bwd_item(const float* __restrict__ Wg, cons
   const bool ok = p < P;
   const int s0 = by * chunk;
   const int s1 = min(S, s0 + chunk);
-  const float px = ok ? pts[p] : 0.0f;
-  const float py = ok ? pts[P + p] : 0.0f;
-  const float pz = ok ? pts[2 * P + p] : 0.0f;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  const float px = sel0(ok, pts[q]);
+  const float py = sel0(ok, pts[P + q]);
+  const float pz = sel0(ok, pts[2 * P + q]);
 
   // W_lm and its z-derivative weights RHO[l][|m|] W_lm (zero on tail lanes,
   // so they contribute nothing to the sphere sums).
@@ -178,7 +180,7 @@ __device__ __forceinline__ void pair_bwd_item(const float* __restrict__ Wg, cons
   for (int l = 0; l < NB; ++l) {
 #pragma unroll
     for (int m = -l; m <= l; ++m) {
-      const float w = ok ? Wg[(int64_t)idx(l, m) * P + p] : 0.0f;
+      const float w = sel0(ok, Wg[(int64_t)idx(l, m) * P + q]);
       W[idx(l, m)] = w;
       Wz[idx(l, m)] = w * SHV_RHO[l][m < 0 ? -m : m];
     }

@@ -68,20 +68,51 @@ struct MSupp {
   static __device__ __forceinline__ constexpr int at(int j, int kk) { return ((kk & 3) * N + j) * CPG + (kk >> 2); }
 };
 
-// Fill Ms from M (global) with the threads tid = 0 .. nthreads-1 of a block;
-// the caller synchronises before reading it.
-template <int NB>
-__device__ __forceinline__ void stage_M(const float* __restrict__ M, float* Ms, int tid, int nthreads) {
-  constexpr int N = NB * NB, CPG = MSupp<NB>::CPG, HS = MTab<NB>::HS;
-  for (int e = tid; e < MSupp<NB>::SIZE; e += nthreads) {
-    const int c = e % CPG, j = (e / CPG) % N, g = e / (CPG * N);
-    const int kk = 4 * c + g;
-    Ms[e] = kk < HS ? M[j * N + MTab<NB>::supp(kk)] : 0.0f;
-  }
-}
-
 // The clamped cosine's odd bands above 1 vanish.
 __device__ __forceinline__ constexpr bool h_support(int l) { return l <= 2 || (l % 2) == 0; }
+
+// The coefficient index k of support column kk of the clamped cosine (its
+// bands l <= 2 and even l, each in m order), by arithmetic rather than a
+// table lookup.
+template <int NB>
+__device__ __forceinline__ int support_index(int kk) {
+  int k = 0, base = 0;
+#pragma unroll
+  for (int l = 0; l < NB; ++l) {
+    if (!h_support(l)) continue;
+    const int w = 2 * l + 1;
+    k = (kk >= base && kk < base + w) ? l * l + (kk - base) : k;
+    base += w;
+  }
+  return k;
+}
+
+// Fill Ms from M (global) with the SHV_BLOCK threads tid of a block; the
+// caller synchronises before reading it.  Every thread computes all of its
+// source addresses first and then issues all of its loads (no per-element
+// branch), so their latencies overlap.
+template <int NB>
+__device__ __forceinline__ void stage_M(const float* __restrict__ M, float* Ms, int tid) {
+  constexpr int N = NB * NB, CPG = MSupp<NB>::CPG, HS = MTab<NB>::HS, SIZE = MSupp<NB>::SIZE;
+  constexpr int IT = (SIZE + SHV_BLOCK - 1) / SHV_BLOCK;
+  int src[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e0 = tid + it * SHV_BLOCK;
+    const int e = e0 < SIZE ? e0 : SIZE - 1;
+    const int c = e % CPG, j = (e / CPG) % N, g = e / (CPG * N);
+    const int kk = 4 * c + g;
+    src[it] = j * N + support_index<NB>(kk < HS ? kk : HS - 1);
+  }
+  float v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) v[it] = M[src[it]];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = tid + it * SHV_BLOCK;
+    if (e < SIZE) Ms[e] = (4 * (e % CPG) + e / (CPG * N)) < HS ? v[it] : 0.0f;
+  }
+}
 
 // H_lm = A_l y_lm(n_hat) on the support (0 elsewhere); returns 1/|n|.
 // n / |n| and 1 / |n|.

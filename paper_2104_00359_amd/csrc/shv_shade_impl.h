@@ -34,9 +34,12 @@
 namespace shv {
 
 
+// Channel y = blockIdx.y: M + y N^2 from L + y N.
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_build_M(const float* __restrict__ L, float* __restrict__ M) {
-  build_M_range<NB>(L, M, blockIdx.x * SHV_BLOCK + threadIdx.x, gridDim.x * SHV_BLOCK);
+  constexpr int N = NB * NB;
+  const int y = blockIdx.y;
+  build_M_range<NB>(L + y * N, M + y * N * N, blockIdx.x * SHV_BLOCK + threadIdx.x, gridDim.x * SHV_BLOCK);
 }
 
 template <int NB>
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_fwd(const float* __restrict
                                                          int64_t P, float* __restrict__ rad) {
   constexpr int N = NB * NB;
   __shared__ float Ms[MSupp<NB>::SIZE];
-  stage_M<NB>(M, Ms, threadIdx.x, SHV_BLOCK);
+  stage_M<NB>(M, Ms, threadIdx.x);
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   if (p >= P) return;
@@ -67,18 +70,19 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict
   constexpr int N = NB * NB;
   __shared__ LightTile T;
   __shared__ float Ms[MSupp<NB>::SIZE];
-  stage_M<NB>(M, Ms, threadIdx.x, SHV_BLOCK);
+  stage_M<NB>(M, Ms, threadIdx.x);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   const bool ok = p < P;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
   float V[N], H[N], Hb[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = ok ? vis[(int64_t)i * P + p] : 0.0f;
+  for (int i = 0; i < N; ++i) V[i] = sel0(ok, vis[(int64_t)i * P + q]);
   float ux, uy, uz;
-  const float inv = transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
-  const float bb = ok ? gB[p] : 0.0f;
-  const float w = bb * (ok ? alb[p] : 0.0f);
+  const float inv = transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
+  const float bb = sel0(ok, gB[q]);
+  const float w = bb * sel0(ok, alb[q]);
   const float s = shade_value<NB, true>(V, H, Ms, w, Hb);
   if (ok) {
     if (gA) gA[p] = bb * s;
@@ -115,6 +119,29 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict
 // receivers) and exchanged through LDS; wave g then forms the shading
 // partial over support columns kk = g (mod 4) of every channel, exactly the
 // partial g of the canonical order, so the block adds them in that order.
+// Rows i = G, G + 4, ... of a row-major [N][P] array at receiver p into LDS
+// dst[i * row_pitch + lane * lane_pitch] (0 when !ok).  The row index is
+// formed at run time from the wave number, so every load is issued before
+// the first wait (no per-row branch).
+template <int N>
+__device__ __forceinline__ void load_rows_by_wave(const float* __restrict__ src, int64_t P, int64_t p, bool ok, int G,
+                                                  float* dst, int row_pitch, int lane_pitch, int lane) {
+  constexpr int T = (N + 3) / 4;
+  float v[T];
+  const int64_t pp = ok ? p : 0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int i = 4 * t + G;
+    const int ii = i < N ? i : N - 1;  // in bounds; the value is dropped below
+    v[t] = src[(int64_t)ii * P + pp];
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int i = 4 * t + G;
+    if (i < N) dst[i * row_pitch + lane * lane_pitch] = ok ? v[t] : 0.0f;
+  }
+}
+
 template <int NB, int CH>
 struct ShadeCh4Shared {
   float X[NB * NB][64];        // V exchange (row i, receiver lane)
@@ -122,15 +149,44 @@ struct ShadeCh4Shared {
   float Bx[CH][4][64];         // shading partials per channel and column group
 };
 
-// Wave G's column group of every channel's shading value (the channel loop
-// inside the wave's branch, so only the group's columns of H stay live).
+// Wave G's column group of every channel's shading value: shade_partial's
+// sums (each column over j in index order, then the group's columns in
+// order), for all channels in one pass over the rows, with V_j read from the
+// LDS exchange (Xl[j * 64]) as it is consumed rather than held in registers.
 template <int NB, int G, int CH>
-__device__ __forceinline__ void shade_ch_fwd_group(ShadeCh4Shared<NB, CH>& sh, const float (&V)[NB * NB],
-                                                   const float (&H)[NB * NB], int lane) {
-  float Hb[NB * NB];
-#pragma nounroll
+__device__ __forceinline__ void shade_ch_fwd_group(ShadeCh4Shared<NB, CH>& sh, const float (&H)[NB * NB], int lane) {
+  constexpr int N = NB * NB;
+  constexpr int CPG = MSupp<NB>::CPG;
+  constexpr int SZ = MSupp<NB>::SIZE;
+  constexpr int NC = (MTab<NB>::HS - G + 3) / 4;
+  float t[CH][CPG];
+#pragma unroll
   for (int c = 0; c < CH; ++c)
-    sh.Bx[c][G][lane] = shade_partial<NB, G, false>(V, H, sh.Ms + c * MSupp<NB>::SIZE, 0.0f, Hb);
+#pragma unroll
+    for (int cc = 0; cc < CPG; ++cc) t[c][cc] = 0.0f;
+#pragma unroll 8
+  for (int j = 0; j < N; ++j) {
+    const float v = sh.X[j][lane];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) t[c][cc] = fmaf(sh.Ms[c * SZ + MSupp<NB>::at(j, 4 * cc + G)], v, t[c][cc]);
+  }
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    float s = 0.0f;
+    int kk = 0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      if (!h_support(l)) continue;
+#pragma unroll
+      for (int m = -l; m <= l; ++m) {
+        const int col = kk++;
+        if ((col & 3) == G) s = fmaf(H[idx(l, m)], t[c][col >> 2], s);
+      }
+    }
+    sh.Bx[c][G][lane] = s;
+  }
 }
 
 template <int NB, int CH>
@@ -145,21 +201,18 @@ __global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_fwd(const float* __re
   const int G = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
   const bool ok = p < P;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  load_rows_by_wave<N>(vis, P, p, ok, G, &sh.X[0][0], 64, 1, lane);
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    if ((i & 3) == G) sh.X[i][lane] = ok ? vis[(int64_t)i * P + p] : 0.0f;
-#pragma unroll
-  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x, SHV_BLOCK);
+  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x);
+  float H[N], ux, uy, uz;
+  transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
   __syncthreads();
-  float V[N], H[N], ux, uy, uz;
-#pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = sh.X[i][lane];
-  transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
   switch (G) {
-    case 0: shade_ch_fwd_group<NB, 0, CH>(sh, V, H, lane); break;
-    case 1: shade_ch_fwd_group<NB, 1, CH>(sh, V, H, lane); break;
-    case 2: shade_ch_fwd_group<NB, 2, CH>(sh, V, H, lane); break;
-    default: shade_ch_fwd_group<NB, 3, CH>(sh, V, H, lane); break;
+    case 0: shade_ch_fwd_group<NB, 0, CH>(sh, H, lane); break;
+    case 1: shade_ch_fwd_group<NB, 1, CH>(sh, H, lane); break;
+    case 2: shade_ch_fwd_group<NB, 2, CH>(sh, H, lane); break;
+    default: shade_ch_fwd_group<NB, 3, CH>(sh, H, lane); break;
   }
   __syncthreads();
   if (!ok) return;
@@ -193,10 +246,11 @@ __device__ __forceinline__ void shade_ch_bwd_group(ShadeCh4BwdShared<NB, CH>& sh
                                                    float* __restrict__ gV) {
   constexpr int N = NB * NB;
   constexpr int SZ = MSupp<NB>::SIZE;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
   float V[N], H[N], Hb[N], ux, uy, uz;
 #pragma unroll
   for (int i = 0; i < N; ++i) V[i] = sh.LT.Vt[lane * kTileVS + i];
-  transfer<NB>(ok ? nrm[p] : 0.0f, ok ? nrm[P + p] : 0.0f, ok ? nrm[2 * P + p] : 1.0f, H, ux, uy, uz);
+  transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
 #pragma unroll
   for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
 #pragma nounroll
@@ -245,14 +299,13 @@ __global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_bwd(const float* __re
   const int64_t tile = blockIdx.x;
   const int64_t p = tile * 64 + lane;
   const bool ok = p < P;
+  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  load_rows_by_wave<N>(vis, P, p, ok, G, sh.LT.Vt, 1, kTileVS, lane);
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    if ((i & 3) == G) sh.LT.Vt[lane * kTileVS + i] = ok ? vis[(int64_t)i * P + p] : 0.0f;
-#pragma unroll
-  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x, SHV_BLOCK);
+  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x);
   if (G == 0) {
 #pragma unroll
-    for (int c = 0; c < CH; ++c) sh.W[c][lane] = ok ? gB[c * P + p] * alb[c * P + p] : 0.0f;
+    for (int c = 0; c < CH; ++c) sh.W[c][lane] = sel0(ok, gB[c * P + q] * alb[c * P + q]);
   }
   __syncthreads();
   switch (G) {
@@ -362,9 +415,10 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_envmap_rows(const float* __restri
 // Launchers for one band count (instantiated per band count in shv_nb.hip).
 
 template <int NB>
-hipError_t build_M_nb(const float* light, float* M, hipStream_t st) {
+hipError_t build_M_nb(const float* light, float* M, int channels, hipStream_t st) {
   constexpr int NN = NB * NB * NB * NB;
-  k_build_M<NB><<<(unsigned)((NN + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(light, M);
+  k_build_M<NB><<<dim3((unsigned)((NN + SHV_BLOCK - 1) / SHV_BLOCK), (unsigned)channels), SHV_BLOCK, 0, st>>>(light,
+                                                                                                              M);
   return hipGetLastError();
 }
 
