@@ -431,7 +431,8 @@ def emit_gaunt(path):
         L.append(f"__device__ const float shv_mtab_val_{n}[{max(len(ec), 1)}] = {{" + ",".join(flit(c) for c in (ec or [0.0])) + "};")
     L.append("")
     L.append("// Lighting-gradient contraction Lbar_i = sum_{j, kk} C_{i j k(kk)} Q[j][kk],")
-    L.append("// Q over the transfer support (kk indexes the support); CSR over i, entries j * 32 + kk.")
+    L.append("// Q over the transfer support (kk indexes the support); entries j * 32 + kk, row i's")
+    L.append("// entries split over 4 threads (entry e of the row to thread e mod 4), padded per thread.")
     for n in range(1, MAX_BANDS + 1):
         N = n * n
         C = real_gaunt(n)
@@ -447,9 +448,22 @@ def emit_gaunt(path):
                 ent.append(e)
                 val.append(c)
             ptr.append(len(ent))
-        L.append(f"__device__ const int shv_ltab_ptr_{n}[{len(ptr)}] = {{" + ",".join(map(str, ptr)) + "};")
-        L.append(f"__device__ const unsigned short shv_ltab_ent_{n}[{max(len(ent), 1)}] = {{" + ",".join(map(str, ent or [0])) + "};")
-        L.append(f"__device__ const float shv_ltab_val_{n}[{max(len(val), 1)}] = {{" + ",".join(flit(c) for c in (val or [0.0])) + "};")
+        # Padded per-thread layout: thread (i, part) of the contraction takes
+        # the entries ptr[i] + part, + 4, ... in order, as slots 0, 1, ...;
+        # every (i, part) gets the same slot count (unused slots: entry 0,
+        # value 0, beyond the count) so its loads can all be issued at once.
+        slots = max([(ptr[i + 1] - ptr[i] - part + 3) // 4 for i in range(N) for part in range(4)] + [1])
+        pent, pval, pcnt = [], [], []
+        for i in range(N):
+            for part in range(4):
+                es = list(range(ptr[i] + part, ptr[i + 1], 4))
+                pcnt.append(len(es))
+                pent += [ent[e] for e in es] + [0] * (slots - len(es))
+                pval += [val[e] for e in es] + [0.0] * (slots - len(es))
+        L.append(f"static constexpr int SHV_LTAB_SLOTS_{n} = {slots};")
+        L.append(f"__device__ const int shv_ltab_cnt_{n}[{len(pcnt)}] = {{" + ",".join(map(str, pcnt)) + "};")
+        L.append(f"__device__ const unsigned short shv_ltab_pent_{n}[{len(pent)}] = {{" + ",".join(map(str, pent)) + "};")
+        L.append(f"__device__ const float shv_ltab_pval_{n}[{len(pval)}] = {{" + ",".join(flit(c) for c in pval) + "};")
     L.append("")
     for n in range(1, MAX_BANDS + 1):
         supp = transfer_support(n)

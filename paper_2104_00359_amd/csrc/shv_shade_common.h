@@ -27,9 +27,10 @@ struct MTab;
     static __device__ __forceinline__ const int* ptr() { return shv_mtab_ptr_##n; }            \
     static __device__ __forceinline__ const unsigned char* ind() { return shv_mtab_idx_##n; }  \
     static __device__ __forceinline__ const float* val() { return shv_mtab_val_##n; }          \
-    static __device__ __forceinline__ const int* lptr() { return shv_ltab_ptr_##n; }           \
-    static __device__ __forceinline__ const unsigned short* lent() { return shv_ltab_ent_##n; } \
-    static __device__ __forceinline__ const float* lval() { return shv_ltab_val_##n; }         \
+    static __device__ __forceinline__ const int* lcnt() { return shv_ltab_cnt_##n; }           \
+    static __device__ __forceinline__ const unsigned short* lent() { return shv_ltab_pent_##n; }\
+    static __device__ __forceinline__ const float* lval() { return shv_ltab_pval_##n; }        \
+    static constexpr int LSLOTS = SHV_LTAB_SLOTS_##n;                                          \
     static __device__ __forceinline__ int supp(int kk) { return SHV_HSUPP_##n[kk]; }           \
     static constexpr int HS = SHV_HSUPP_COUNT_##n;                                             \
   };
@@ -282,11 +283,24 @@ __device__ __forceinline__ void tile_light_partial(LightTile& T, float* __restri
   {
     const int i = tid >> 2, part = tid & 3;
     if (i < N) {
-      const int* ptr = MTab<NB>::lptr();
-      const unsigned short* ent = MTab<NB>::lent();
-      const float* val = MTab<NB>::lval();
+      // this thread's entries of row i (every 4th, in order), all loaded first
+      constexpr int SL = MTab<NB>::LSLOTS;
+      const int cnt = MTab<NB>::lcnt()[tid];
+      const unsigned short* ent = MTab<NB>::lent() + tid * SL;
+      const float* val = MTab<NB>::lval() + tid * SL;
+      int e[SL];
+      float v[SL];
+#pragma unroll
+      for (int t = 0; t < SL; ++t) {
+        e[t] = ent[t];
+        v[t] = val[t];
+      }
       float acc = 0.0f;
-      for (int e = ptr[i] + part; e < ptr[i + 1]; e += 4) acc = fmaf(val[e], Qs[ent[e]], acc);
+#pragma unroll
+      for (int t = 0; t < SL; ++t) {
+        const float f = fmaf(v[t], Qs[e[t]], acc);
+        acc = t < cnt ? f : acc;
+      }
       T.Lp[part][i] = acc;
     }
   }
