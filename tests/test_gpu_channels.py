@@ -42,7 +42,7 @@ def _vis(L, sc, prm, dev, st):
     return vis
 
 
-@pytest.mark.parametrize("n,C", [(3, 3), (8, 3), (8, 1), (6, 4)])
+@pytest.mark.parametrize("n,C", [(3, 3), (8, 3), (8, 1), (6, 4), (8, 2), (1, 4)])
 def test_each_channel_is_the_one_channel_call(n, C):
     """Radiance, albedo and lighting gradients of channel c are bitwise those
     of sh_shade / sh_shade_backward with that channel's albedo and light; the
@@ -142,6 +142,16 @@ def test_channels_body_scene_full_size_sampled():
     _check(h, {k: v.detach().double().numpy() for k, v in o.items()}, idx=idx)
 
 
+@pytest.mark.parametrize("P", [1, 63, 65])
+def test_channels_tiny_receiver_sets(P):
+    """Fewer receivers than one 64-receiver block, and one more than a block."""
+    sc = scenegen.scene_random_shell(90 + P, P, 9, 8)
+    ch = scenegen.colour_channels(sc, 2, seed=P)
+    h = _run_op(sc, ch, ch["grad_radiance"])
+    o = method.run_forward_backward_channels(sc, ch["albedo"], ch["light"], ch["grad_radiance"])
+    _check(h, {k: v.detach().double().numpy() for k, v in o.items()})
+
+
 def test_channels_empty_receiver_set():
     L = lib()
     dev, st = _setup(None)
@@ -167,10 +177,11 @@ def _project(img, n):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,H,W", [(8, 96, 300), (4, 37, 64), (1, 5, 7), (8, 512, 1024)])
+@pytest.mark.parametrize("n,H,W", [(8, 96, 300), (4, 37, 64), (1, 5, 7), (8, 512, 1024), (6, 3, 5000)])
 def test_envmap_projection_parity(n, H, W):
-    """Ragged rows (300 = 256 + 44 columns), odd sizes, one band, and a
-    512 x 1024 RGB map."""
+    """Ragged rows (300 = 256 + 44 columns), odd sizes, one band, a
+    512 x 1024 RGB map, and rows wider than one block's pixel budget (one
+    row per block)."""
     img = scenegen.envmap_image(seed=H, C=3, H=H, W=W)
     g = _project(img, n)
     o = sh.envmap_to_sh(img, n).numpy()
