@@ -18,5 +18,8 @@ come from autograd rather than from a hand-derived adjoint:
             shading (Sec. 3.3.2, Eqs. 8, 10-13), and its gradients
   brute     reference integrals used only to pin the above (Eq. 2 with the
             binary blocker function, exact function-space exponential)
+  deform    the scene parameterisation upstream of the spheres: rigid pose
+            and embedded deformation driven by the spheres (Sec. 3.3.1,
+            Sec. 3.5)
 """
-from . import sh, method, brute  # noqa: F401
+from . import sh, method, brute, deform  # noqa: F401
