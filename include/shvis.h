@@ -170,6 +170,70 @@ size_t shv_envmap_workspace_bytes(int channels, int64_t H, int64_t W, const shv_
 shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_t W, const shv_params* prm,
                              float* light, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- Scene parameterisation upstream of the spheres (Sec. 3.3.1, Sec. 3.5) ----
+ * The sphere centres g_k are the nodes of an embedded deformation graph:
+ * sphere k is attached to its K nearest template vertices and carries an
+ * axis-angle rotation a_k (rotation by |a_k| about a_k / |a_k|, Rodrigues'
+ * formula) and a translation t_k; a global rigid pose (a_0, t_0) follows:
+ *   y_j = sum_k w_jk (R_k (v_j - g_k) + g_k + t_k) + (1 - sum_k w_jk) v_j
+ *   points  x_j = R_0 y_j + t_0
+ *   normals n_j = R_0 (sum_k w_jk R_k m_j + (1 - sum_k w_jk) m_j)  (not renormalised)
+ *   spheres c_k = R_0 (g_k + t_k) + t_0, radius unchanged.
+ * params [S + 1][6]: row k < S is (a_k, t_k), row S is (a_0, t_0).
+ * Weights: u_jk = (1 - |v_j - g_k| / d_k)^2, d_k the distance from g_k to its
+ * (K+1)-th nearest vertex (K-th when K = P), normalised over the spheres
+ * attached to vertex j (0 when that sum is 0). */
+typedef struct shv_deform_graph {
+  const float* vertices;   /* [3][P] template vertex positions v_j (device) */
+  const float* normals;    /* [3][P] template normals m_j (device) */
+  const float* spheres;    /* [S][4] template spheres (g_k, r_k) (device) */
+  const int32_t* vert_ptr; /* [P + 1] per-vertex ranges of the two arrays below (device) */
+  const int32_t* vert_sph; /* [S K] spheres attached to each vertex, ascending (device) */
+  const float* vert_w;     /* [S K] their normalised weights w_jk (device) */
+  const int32_t* sph_vert; /* [S][K] the vertices attached to each sphere, nearest first (device) */
+  const float* sph_w;      /* [S][K] their normalised weights (device) */
+  int64_t P;
+  int64_t S;
+  int32_t K;
+} shv_deform_graph;
+
+/* Builds the attachment on the host (a one-time preprocessing of the
+ * template): vertices [3][P] and spheres [S][4] are host arrays; the outputs
+ * are host arrays of the sizes above (vert_ptr P + 1, vert_sph / vert_w /
+ * sph_vert / sph_w S K).  Distances are compared as squared FP64 distances of
+ * the FP32 inputs, ties to the lower vertex index.  1 <= K <= P, S >= 1,
+ * S K < 2^31. */
+shv_status shv_deform_graph_build(const float* vertices, int64_t P, const float* spheres, int64_t S, int32_t K,
+                                  int32_t* vert_ptr, int32_t* vert_sph, float* vert_w, int32_t* sph_vert,
+                                  float* sph_w);
+
+/* Workspace bytes of sh_deform_forward / sh_deform_backward (0 if invalid). */
+size_t shv_deform_workspace_bytes(int64_t P, int64_t S);
+
+/* Deformed points [3][P], normals [3][P] and spheres [S][4] (device) from
+ * params [S + 1][6] (device); the outputs feed the visibility and shading
+ * entry points directly. */
+shv_status sh_deform_forward(const shv_deform_graph* graph, const float* params, float* points, float* normals,
+                             float* spheres, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of sh_deform_forward: from the cotangents of the deformed points
+ * [3][P], normals [3][P] and spheres [S][4] (any may be NULL: zero; the
+ * radius column is ignored) to grad_params [S + 1][6].  Deterministic. */
+shv_status sh_deform_backward(const shv_deform_graph* graph, const float* params, const float* grad_points,
+                              const float* grad_normals, const float* grad_spheres, float* grad_params, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* The rendering loss of Sec. 3.5 on receiver values: loss[0] = mean_i
+ * (value_i - target_i)^2 and grad_i = 2 (value_i - target_i) / n (grad may be
+ * NULL).  ws must hold shv_l2_workspace_bytes(n) bytes.  n >= 1. */
+size_t shv_l2_workspace_bytes(int64_t n);
+shv_status sh_l2_loss(const float* value, const float* target, int64_t n, float* grad, float* loss, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* One gradient-descent step x_i -= lr g_i over n floats (the optimiser of
+ * Sec. 3.5). */
+shv_status sh_sgd_step(float* x, const float* grad, int64_t n, float lr, hipStream_t stream);
+
 /* Adjoint of sh_visibility_forward for the cotangent grad_vis [N][P]:
  *   vis, saved  the forward's outputs for the same inputs and parameters
  *   grad_points [3][P], grad_spheres [S][4] (d/d(cx, cy, cz, r), summed over

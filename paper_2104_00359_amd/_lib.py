@@ -33,6 +33,8 @@ EXPORTED = [
     "sh_visibility_forward", "sh_shade", "sh_shade_backward", "sh_visibility_backward",
     "shv_channels_workspace_bytes", "sh_shade_channels", "sh_shade_channels_backward",
     "shv_envmap_workspace_bytes", "sh_envmap_project",
+    "shv_deform_graph_build", "shv_deform_workspace_bytes", "sh_deform_forward", "sh_deform_backward",
+    "shv_l2_workspace_bytes", "sh_l2_loss", "sh_sgd_step",
     "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
     "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
     "sh_render_batched_forward", "sh_render_batched_backward",
@@ -61,6 +63,13 @@ class shv_scene(ctypes.Structure):
         ("range_begin", ctypes.c_int64), ("range_end", ctypes.c_int64), ("defer_reductions", ctypes.c_int32)]
 
 
+class shv_deform_graph(ctypes.Structure):
+    """Device pointers of an attachment graph (field order as in the C struct)."""
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "vertices", "normals", "spheres", "vert_ptr", "vert_sph", "vert_w", "sph_vert", "sph_w")] + [
+        ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("K", ctypes.c_int32)]
+
+
 class shv_batch_grid(ctypes.Structure):
     """Block counts of the batched launches (see the C header)."""
     _fields_ = [("pair", ctypes.c_int64 * 9), ("exp", (ctypes.c_int64 * 9) * 2), ("finalize", ctypes.c_int64)]
@@ -87,6 +96,13 @@ _sig = {
                                                     _P, _SZ, _P]),
     "shv_envmap_workspace_bytes": (_SZ, [ctypes.c_int, _I64, _I64, _PRM]),
     "sh_envmap_project": (ctypes.c_int32, [_P, ctypes.c_int, _I64, _I64, _PRM, _P, _P, _SZ, _P]),
+    "shv_deform_graph_build": (ctypes.c_int32, [_P, _I64, _P, _I64, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "shv_deform_workspace_bytes": (_SZ, [_I64, _I64]),
+    "sh_deform_forward": (ctypes.c_int32, [ctypes.POINTER(shv_deform_graph), _P, _P, _P, _P, _P, _SZ, _P]),
+    "sh_deform_backward": (ctypes.c_int32, [ctypes.POINTER(shv_deform_graph), _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "shv_l2_workspace_bytes": (_SZ, [_I64]),
+    "sh_l2_loss": (ctypes.c_int32, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "sh_sgd_step": (ctypes.c_int32, [_P, _P, _I64, ctypes.c_float, _P]),
     "shv_render_saved_floats": (_I64, [_I64, _PRM]),
     "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
     "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -192,6 +208,43 @@ def shv_envmap_workspace_bytes(channels: int, H: int, W: int, prm: shv_params) -
 def sh_envmap_project(image, channels, H, W, prm, light, ws, ws_bytes, stream):
     _check(_lib.sh_envmap_project(ptr(image), int(channels), int(H), int(W), ctypes.byref(prm), ptr(light),
                                   ptr(ws), int(ws_bytes), stream), "sh_envmap_project")
+
+
+def shv_deform_graph_build(vertices, P, spheres, S, K, vert_ptr, vert_sph, vert_w, sph_vert, sph_w):
+    """Host arrays (numpy, C-contiguous): vertices float32 [3][P], spheres
+    float32 [S][4]; outputs int32 / float32 arrays of the documented sizes."""
+    def hp(a):
+        return ctypes.c_void_p(a.ctypes.data)
+    _check(_lib.shv_deform_graph_build(hp(vertices), int(P), hp(spheres), int(S), int(K), hp(vert_ptr),
+                                       hp(vert_sph), hp(vert_w), hp(sph_vert), hp(sph_w)), "shv_deform_graph_build")
+
+
+def shv_deform_workspace_bytes(P: int, S: int) -> int:
+    return int(_lib.shv_deform_workspace_bytes(int(P), int(S)))
+
+
+def sh_deform_forward(graph, params, points, normals, spheres, ws, ws_bytes, stream):
+    _check(_lib.sh_deform_forward(ctypes.byref(graph), ptr(params), ptr(points), ptr(normals), ptr(spheres),
+                                  ptr(ws), int(ws_bytes), stream), "sh_deform_forward")
+
+
+def sh_deform_backward(graph, params, grad_points, grad_normals, grad_spheres, grad_params, ws, ws_bytes, stream):
+    _check(_lib.sh_deform_backward(ctypes.byref(graph), ptr(params), ptr(grad_points), ptr(grad_normals),
+                                   ptr(grad_spheres), ptr(grad_params), ptr(ws), int(ws_bytes), stream),
+           "sh_deform_backward")
+
+
+def shv_l2_workspace_bytes(n: int) -> int:
+    return int(_lib.shv_l2_workspace_bytes(int(n)))
+
+
+def sh_l2_loss(value, target, n, grad, loss, ws, ws_bytes, stream):
+    _check(_lib.sh_l2_loss(ptr(value), ptr(target), int(n), ptr(grad), ptr(loss), ptr(ws), int(ws_bytes), stream),
+           "sh_l2_loss")
+
+
+def sh_sgd_step(x, grad, n, lr, stream):
+    _check(_lib.sh_sgd_step(ptr(x), ptr(grad), int(n), float(lr), stream), "sh_sgd_step")
 
 
 def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, grad_points, grad_spheres, ws,

@@ -228,6 +228,39 @@ shv_status check_channels(int channels) {
   return SHV_OK;
 }
 
+// Deformation: rotation matrices, the cotangents ybar / zbar, the global
+// partials and their sum.
+struct DeformWs {
+  size_t rm, yb, gpart, g;
+};
+size_t deform_bytes(int64_t P, int64_t S, DeformWs* o = nullptr) {
+  const size_t rm = align_up((size_t)(S + 1) * 9 * 4);
+  const size_t yb = align_up((size_t)6 * P * 4);
+  const size_t gp = align_up((size_t)(shv::deform_vert_blocks(P) + S) * 12 * 4);
+  const size_t g = align_up(12 * 4);
+  if (o) {
+    o->rm = 0;
+    o->yb = rm;
+    o->gpart = rm + yb;
+    o->g = rm + yb + gp;
+  }
+  return rm + yb + gp + g;
+}
+
+shv_status check_graph(const shv_deform_graph* gr, shv::DeformGraphDev* g) {
+  if (!gr) return set_error(SHV_ERR_INVALID_ARG, "graph is NULL");
+  if (gr->P < 1 || gr->S < 1 || gr->K < 1 || gr->K > gr->P || gr->P > ((int64_t)1 << 31) - 256 ||
+      gr->S * (int64_t)gr->K >= ((int64_t)1 << 31))
+    return set_error(SHV_ERR_INVALID_ARG, "invalid graph sizes (P=%lld, S=%lld, K=%d)", (long long)gr->P,
+                     (long long)gr->S, gr->K);
+  if (!gr->vertices || !gr->normals || !gr->spheres || !gr->vert_ptr || !gr->vert_sph || !gr->vert_w ||
+      !gr->sph_vert || !gr->sph_w)
+    return set_error(SHV_ERR_INVALID_ARG, "graph has a NULL array");
+  *g = shv::DeformGraphDev{gr->vertices, gr->normals, gr->spheres, gr->vert_ptr, gr->vert_sph, gr->vert_w,
+                           gr->sph_vert, gr->sph_w, gr->P, gr->S, gr->K};
+  return SHV_OK;
+}
+
 shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
   if (needed == 0) return SHV_OK;
   if (!ws) return set_error(SHV_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", needed);
@@ -565,6 +598,89 @@ shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_
     return shv::launch_reduce_rows(part, (int)shv::envmap_row_blocks(H, W), N, light, stream, channels);
   }));
   return SHV_OK;
+}
+
+shv_status shv_deform_graph_build(const float* vertices, int64_t P, const float* spheres, int64_t S, int32_t K,
+                                  int32_t* vert_ptr, int32_t* vert_sph, float* vert_w, int32_t* sph_vert,
+                                  float* sph_w) {
+  if (P < 1 || S < 1 || K < 1 || K > P || P > ((int64_t)1 << 31) - 256 || S * (int64_t)K >= ((int64_t)1 << 31))
+    return set_error(SHV_ERR_INVALID_ARG, "invalid attachment sizes (P=%lld, S=%lld, K=%d)", (long long)P,
+                     (long long)S, K);
+  SHV_TRY(need(vertices, "vertices"));
+  SHV_TRY(need(spheres, "spheres"));
+  SHV_TRY(need(vert_ptr, "vert_ptr"));
+  SHV_TRY(need(vert_sph, "vert_sph"));
+  SHV_TRY(need(vert_w, "vert_w"));
+  SHV_TRY(need(sph_vert, "sph_vert"));
+  SHV_TRY(need(sph_w, "sph_w"));
+  shv::deform_graph_build(vertices, P, spheres, S, K, vert_ptr, vert_sph, vert_w, sph_vert, sph_w);
+  return SHV_OK;
+}
+
+size_t shv_deform_workspace_bytes(int64_t P, int64_t S) {
+  if (P < 1 || S < 1) return 0;
+  DeformWs L;
+  return deform_bytes(P, S, &L);
+}
+
+shv_status sh_deform_forward(const shv_deform_graph* graph, const float* params, float* points, float* normals,
+                             float* spheres, void* ws, size_t ws_bytes, hipStream_t stream) {
+  shv::DeformGraphDev g;
+  SHV_TRY(check_graph(graph, &g));
+  SHV_TRY(check_device());
+  SHV_TRY(need(params, "params"));
+  SHV_TRY(need(points, "points"));
+  SHV_TRY(need(normals, "normals"));
+  SHV_TRY(need(spheres, "spheres"));
+  DeformWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, deform_bytes(g.P, g.S, &L)));
+  float* Rm = (float*)((char*)ws + L.rm);
+  return launch("deform_fwd", stream,
+                [&] { return shv::launch_deform_forward(g, params, Rm, points, normals, spheres, stream); });
+}
+
+shv_status sh_deform_backward(const shv_deform_graph* graph, const float* params, const float* grad_points,
+                              const float* grad_normals, const float* grad_spheres, float* grad_params, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  shv::DeformGraphDev g;
+  SHV_TRY(check_graph(graph, &g));
+  SHV_TRY(check_device());
+  SHV_TRY(need(params, "params"));
+  SHV_TRY(need(grad_params, "grad_params"));
+  DeformWs L;
+  SHV_TRY(check_ws(ws, ws_bytes, deform_bytes(g.P, g.S, &L)));
+  char* b = (char*)ws;
+  return launch("deform_bwd", stream, [&] {
+    return shv::launch_deform_backward(g, params, grad_points, grad_normals, grad_spheres, (float*)(b + L.rm),
+                                       (float*)(b + L.yb), (float*)(b + L.gpart), (float*)(b + L.g), grad_params,
+                                       stream);
+  });
+}
+
+size_t shv_l2_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  return align_up((size_t)((n + SHV_BLOCK - 1) / SHV_BLOCK) * 4);
+}
+
+shv_status sh_l2_loss(const float* value, const float* target, int64_t n, float* grad, float* loss, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (n < 1 || n > ((int64_t)1 << 31) - 256) return set_error(SHV_ERR_INVALID_ARG, "invalid size n=%lld", (long long)n);
+  SHV_TRY(check_device());
+  SHV_TRY(need(value, "value"));
+  SHV_TRY(need(target, "target"));
+  SHV_TRY(need(loss, "loss"));
+  SHV_TRY(check_ws(ws, ws_bytes, shv_l2_workspace_bytes(n)));
+  return launch("l2_loss", stream, [&] { return shv::launch_l2(value, target, n, grad, (float*)ws, loss, stream); });
+}
+
+shv_status sh_sgd_step(float* x, const float* grad, int64_t n, float lr, hipStream_t stream) {
+  if (n < 0) return set_error(SHV_ERR_INVALID_ARG, "negative size");
+  if (!(lr == lr)) return set_error(SHV_ERR_INVALID_ARG, "lr is NaN");
+  SHV_TRY(check_device());
+  if (n == 0) return SHV_OK;
+  SHV_TRY(need(x, "x"));
+  SHV_TRY(need(grad, "grad"));
+  return launch("sgd", stream, [&] { return shv::launch_sgd(x, grad, n, lr, stream); });
 }
 
 shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const float* points, int64_t P,

@@ -121,4 +121,33 @@ hipError_t batch_exp_bwd_nb(const void* table, bool four, int64_t blocks, hipStr
 
 bool exp_four_waves(int64_t P, uint32_t flags);
 
+// Scene parameterisation upstream of the spheres (embedded deformation graph
+// and global pose).  Device pointers as in shv_deform_graph.
+struct DeformGraphDev {
+  const float* vertices;
+  const float* normals;
+  const float* spheres;
+  const int32_t* vert_ptr;
+  const int32_t* vert_sph;
+  const float* vert_w;
+  const int32_t* sph_vert;
+  const float* sph_w;
+  int64_t P, S;
+  int K;
+};
+int deform_graph_build(const float* vertices, int64_t P, const float* spheres, int64_t S, int K, int32_t* vert_ptr,
+                       int32_t* vert_sph, float* vert_w, int32_t* sph_vert, float* sph_w);
+int64_t deform_vert_blocks(int64_t P);
+// Rm [(S + 1) * 9] scratch; pts / nrm [3][P], sph [S][4] out.
+hipError_t launch_deform_forward(const DeformGraphDev& g, const float* params, float* Rm, float* pts, float* nrm,
+                                 float* sph, hipStream_t st);
+// Rm as above, Yb [6][P], Gpart [(deform_vert_blocks(P) + S) * 12], G [12] scratch; gp [S + 1][6] out.
+hipError_t launch_deform_backward(const DeformGraphDev& g, const float* params, const float* gx, const float* gn,
+                                  const float* gs, float* Rm, float* Yb, float* Gpart, float* G, float* gp,
+                                  hipStream_t st);
+// part [ceil(n / 256)] scratch; loss [1] and grad [n] out.
+hipError_t launch_l2(const float* v, const float* t, int64_t n, float* grad, float* part, float* loss,
+                     hipStream_t st);
+hipError_t launch_sgd(float* x, const float* g, int64_t n, float lr, hipStream_t st);
+
 }  // namespace shv

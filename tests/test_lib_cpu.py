@@ -187,3 +187,57 @@ def test_batch_receiver_range_validation(L):
     g = L.shv_batch_table_grid(buf)
     assert g.finalize == 0
     assert np.ctypeslib.as_array(g.exp)[1][4] == (1000 + 63) // 64 - 256 // 64
+
+
+def _attach_host(L, sc, K):
+    P, S = sc["points"].shape[0], sc["spheres"].shape[0]
+    v = np.ascontiguousarray(sc["points"].T.astype(np.float32))
+    s = np.ascontiguousarray(sc["spheres"].astype(np.float32))
+    out = dict(vert_ptr=np.zeros(P + 1, np.int32), vert_sph=np.zeros(S * K, np.int32),
+               vert_w=np.zeros(S * K, np.float32), sph_vert=np.zeros(S * K, np.int32),
+               sph_w=np.zeros(S * K, np.float32))
+    L.shv_deform_graph_build(v, P, s, S, K, out["vert_ptr"], out["vert_sph"], out["vert_w"], out["sph_vert"],
+                             out["sph_w"])
+    return out
+
+
+@pytest.mark.parametrize("P,S,K", [(300, 12, 40), (500, 7, 500), (64, 20, 3)])
+def test_attachment_graph_matches_the_oracle_bit_for_bit(L, P, S, K):
+    """The host builder's attachment (index work) equals the oracle's exactly;
+    its FP32 weights are the oracle's FP64 weights rounded once."""
+    import scenegen
+    from oracle import deform
+    sc = scenegen.scene_random_shell(P + S, P, S, 4)
+    g = _attach_host(L, sc, K)
+    idx, u = deform.attach(sc["points"], sc["spheres"][:, :3], K)
+    w = deform.normalised_weights(idx, u, P)
+    assert np.array_equal(g["sph_vert"].reshape(S, K), idx)
+    assert np.array_equal(g["sph_w"].reshape(S, K), w.astype(np.float32))
+    # the vertex-major view lists the same attachments, spheres ascending
+    ptr = g["vert_ptr"]
+    assert ptr[0] == 0 and ptr[-1] == S * K
+    for j in range(P):
+        ks = g["vert_sph"][ptr[j]:ptr[j + 1]]
+        assert list(ks) == sorted(ks)
+        for k, wj in zip(ks, g["vert_w"][ptr[j]:ptr[j + 1]]):
+            q = list(idx[k]).index(j)
+            assert wj == np.float32(w[k, q])
+
+
+def test_deform_arguments_rejected_before_any_device_call(L):
+    st = None
+    z = np.zeros(16, np.float32)
+    zi = np.zeros(16, np.int32)
+    hp = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    f = L.raw("shv_deform_graph_build")
+    assert f(hp(z), 4, hp(z), 1, 5, hp(zi), hp(zi), hp(z), hp(zi), hp(z)) == L.SHV_ERR_INVALID_ARG   # K > P
+    assert f(hp(z), 4, hp(z), 0, 1, hp(zi), hp(zi), hp(z), hp(zi), hp(z)) == L.SHV_ERR_INVALID_ARG   # S = 0
+    assert f(None, 4, hp(z), 1, 1, hp(zi), hp(zi), hp(z), hp(zi), hp(z)) == L.SHV_ERR_INVALID_ARG
+    g = L.shv_deform_graph(1, 1, 1, 1, 1, 1, 1, 1, 10, 2, 11)                                          # K > P
+    assert L.raw("sh_deform_forward")(ctypes.byref(g), None, None, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert "graph" in L.shv_last_error()
+    assert L.raw("sh_deform_backward")(None, None, None, None, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert L.raw("sh_l2_loss")(None, None, 0, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert L.raw("sh_sgd_step")(None, None, -1, ctypes.c_float(0.1), st) == L.SHV_ERR_INVALID_ARG
+    assert L.shv_deform_workspace_bytes(0, 5) == 0 and L.shv_deform_workspace_bytes(100, 5) > 0
+    assert L.shv_l2_workspace_bytes(0) == 0 and L.shv_l2_workspace_bytes(1000) >= 4 * 4
