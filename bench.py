@@ -20,6 +20,12 @@ sh_visibility_backward.  ``--workload envmap``: the lighting of a synthetic
 3 x 512 x 1024 equirectangular map projected onto 8 bands (Eq. 9) through
 sh_envmap_project; throughput in map pixels per second.
 
+``--workload inverse``: one gradient-descent iteration of the inverse problem
+on the body-like scene, every step in the library: the embedded deformation
+driven by the spheres (each attached to its 625 nearest receivers) and a global
+pose, visibility and shading, the mean-squared loss against a target rendered
+from a perturbed scene, their adjoints, and the parameter update.
+
 ``--workload batched64``: 64 independent scenes (P ~ U{5k..50k}, S ~
 U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b); one step = the batched forward +
 backward over all 64, replayed from one captured graph; the same 64 scenes
@@ -54,7 +60,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="body",
-                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap"])
+                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap", "inverse"])
     ap.add_argument("--channels", type=int, default=3, help="rgb / envmap: colour channels")
     ap.add_argument("--map", default="512x1024", help="envmap: H x W of the equirectangular map")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -543,6 +549,51 @@ def bench_envmap(args):
     }
 
 
+def bench_inverse(args):
+    """One gradient-descent iteration of the inverse problem, body-like scene."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import inverse, ops, workmodel
+
+    sc = scenegen.scene_body()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    n, k = int(sc["n_bands"]), args.k
+    P, S = sc["points"].shape[0], sc["spheres"].shape[0]
+    K = int(np.ceil(4 * P / S))
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        graph = inverse.DeformGraph(sc["points"], sc["normals"], sc["spheres"], K, dev)
+        rng = np.random.default_rng(0)
+        true = np.zeros((S + 1, 6), np.float32)
+        true[:S, :3] = rng.standard_normal((S, 3)) * 0.1
+        true[:S, 3:] = rng.standard_normal((S, 3)) * 0.01
+        make = inverse.InverseProblem(graph, sc["albedo"], sc["light"], np.zeros(P, np.float32), n, lr=0.0, init=true,
+                                      n_squarings=k)
+        make.step()
+        target = make.rad.clone()
+        ip = inverse.InverseProblem(graph, sc["albedo"], sc["light"], target, n, lr=1e-2, n_squarings=k)
+    torch.cuda.synchronize()
+    ms, prof = timed(ip.step, stream, args.warmup, args.steps, True)
+    kernels = kernel_table(prof)
+    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
+    if roof is not None:
+        roof["traffic"] = measured_traffic("inverse", roof["kernel"])
+    return {
+        "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"inverse problem on the body-like scene: {P} receivers x {S} spheres, 8 bands, k={k}; "
+                               f"one gradient-descent iteration (deformation with K={K}, render, loss, adjoints, "
+                               "update)", "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "K": K,
+                   "iterations_per_s": 1e3 / ms, "lr": 1e-2},
+        "roofline": roof, "cpu_baseline": None, "kernels": finish_kernels(kernels),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -557,6 +608,8 @@ def main():
         out = bench_rgb(args)
     elif args.workload == "envmap":
         out = bench_envmap(args)
+    elif args.workload == "inverse":
+        out = bench_inverse(args)
     else:
         out = bench_single(args)
     print(json.dumps(out))

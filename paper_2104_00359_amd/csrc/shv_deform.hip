@@ -246,6 +246,22 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// The same for 12 values at once (one pair of barriers); thread e < 12 of the
+// block receives the total of value e in tot.
+__device__ __forceinline__ void block_sum12(const float (&v)[12], float (*red)[12], float& tot) {
+  const int wave = threadIdx.x >> 6;
+  float w[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) w[e] = wave_sum(v[e]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) red[wave][e] = w[e];
+  }
+  __syncthreads();
+  const int e = threadIdx.x < 12 ? threadIdx.x : 0;
+  tot = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
 // Per vertex: ybar, zbar into Yb [6][P]; the vertex terms of the global
 // gradient (Rbar_0 row-major, then tbar_0) summed per block into
 // Gpart[block][12].
@@ -254,7 +270,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_deform_bwd_vert(DeformGraphDev g,
                                                                const float* __restrict__ gx,
                                                                const float* __restrict__ gn, float* __restrict__ Yb,
                                                                float* __restrict__ Gpart) {
-  __shared__ float red[SHV_WAVES_PER_BLOCK];
+  __shared__ float red[SHV_WAVES_PER_BLOCK][12];
   const int64_t j = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   const int64_t P = g.P, S = g.S;
   const float* R0 = Rm + 9 * S;
@@ -272,12 +288,11 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_deform_bwd_vert(DeformGraphDev g,
       Yb[(3 + c) * P + j] = fmaf(R0[c], nb[0], fmaf(R0[3 + c], nb[1], R0[6 + c] * nb[2]));
     }
   }
+  float v[12], tot;
 #pragma unroll
-  for (int e = 0; e < 12; ++e) {
-    const float v = e < 9 ? fmaf(xb[e / 3], y[e % 3], nb[e / 3] * z[e % 3]) : xb[e - 9];
-    const float s = block_sum(v, red);
-    if (threadIdx.x == 0) Gpart[(int64_t)blockIdx.x * 12 + e] = s;
-  }
+  for (int e = 0; e < 12; ++e) v[e] = e < 9 ? fmaf(xb[e / 3], y[e % 3], nb[e / 3] * z[e % 3]) : xb[e - 9];
+  block_sum12(v, red, tot);
+  if (threadIdx.x < 12) Gpart[(int64_t)blockIdx.x * 12 + threadIdx.x] = tot;
 }
 
 // Block k: sphere k's gradient (abar_k, tbar_k) into gp[6 k ..] and its
@@ -287,7 +302,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_deform_bwd_sphere(DeformGraphDev 
                                                                  const float* __restrict__ gs,
                                                                  const float* __restrict__ Yb, int64_t row0,
                                                                  float* __restrict__ Gpart, float* __restrict__ gp) {
-  __shared__ float red[SHV_WAVES_PER_BLOCK];
+  __shared__ float red[SHV_WAVES_PER_BLOCK][12];
+  __shared__ float tot_s[12];
   const int64_t k = blockIdx.x;
   const int64_t P = g.P, S = g.S;
   const int K = g.K;
@@ -307,10 +323,14 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_deform_bwd_sphere(DeformGraphDev 
 #pragma unroll
     for (int r = 0; r < 3; ++r) acc[9 + r] += yb[r];
   }
+  float te;
+  block_sum12(acc, red, te);
+  if (threadIdx.x < 12) tot_s[threadIdx.x] = te;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   float tot[12];
 #pragma unroll
-  for (int e = 0; e < 12; ++e) tot[e] = block_sum(acc[e], red);
-  if (threadIdx.x != 0) return;
+  for (int e = 0; e < 12; ++e) tot[e] = tot_s[e];
   const float* R0 = Rm + 9 * S;
   const float* tk = params + 6 * k + 3;
   const float cb[3] = {gs ? gs[4 * k] : 0.0f, gs ? gs[4 * k + 1] : 0.0f, gs ? gs[4 * k + 2] : 0.0f};
