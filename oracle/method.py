@@ -114,6 +114,22 @@ def sh_exponential(F: torch.Tensor, C: torch.Tensor, n_squarings: int):
     return V, c, Es
 
 
+def sh_exponential_quadrature(F: torch.Tensor, n_bands: int, degree: int | None = None):
+    """The exponential as the projection Proj_n[exp(F~)] of the pointwise
+    exponential (the function-space quantity the scaling and squaring scheme
+    stands in for), taken with the product rule of degree 8n - 1 (4n
+    Gauss-Legendre nodes in z times 8n azimuths).  The DC term is split off
+    exactly as in sh_exponential: V = exp(c) sum_q w_q exp(F^~(w_q)) y(w_q)
+    with c = F_0 / sqrt(4 pi) and F^ = F without its DC coefficient."""
+    degree = 8 * n_bands - 1 if degree is None else degree
+    d, w = sh.sphere_quadrature(degree)
+    Y = sh.real_sh(d, n_bands).to(F.dtype)
+    c = F[..., 0] / SQRT_4PI
+    Fh = torch.cat([torch.zeros_like(F[..., :1]), F[..., 1:]], dim=-1)
+    V = torch.exp(c)[..., None] * ((torch.exp(Fh @ Y.T) * w.to(F.dtype)) @ Y)
+    return V
+
+
 # ---------------------------------------------------------------- step 6
 
 def transfer(normals: torch.Tensor, n_bands: int) -> torch.Tensor:
@@ -142,13 +158,17 @@ def shade_channels(V, H, albedo, light, C):
 # ---------------------------------------------------------------- pipeline
 
 def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0,
-            n_squarings: int = 4, keep=False):
+            n_squarings: int = 4, keep=False, exp_mode: str = "squaring"):
     """Whole forward path on one chunk of receivers (FP64 tensors; FP32
     tensors give the oracle's FP32 twin, used only to measure how much error
-    FP32 arithmetic alone introduces)."""
+    FP32 arithmetic alone introduces).  ``exp_mode`` "quadrature" takes the
+    exponential by sh_exponential_quadrature instead."""
     C = sh.gaunt_tensor(n_bands).to(points.dtype)
     F = log_visibility(points, spheres, n_bands, eps)
-    V, c, Es = sh_exponential(F, C, n_squarings)
+    if exp_mode == "quadrature":
+        V, c, Es = sh_exponential_quadrature(F, n_bands), F[..., 0] / SQRT_4PI, []
+    else:
+        V, c, Es = sh_exponential(F, C, n_squarings)
     H = transfer(normals, n_bands)
     B = shade(V, H, albedo, light, C)
     out = dict(F=F, V=V, B=B, H=H, c=c)
@@ -162,7 +182,7 @@ def scene_tensors(scene, dtype=DT):
     return {k: torch.as_tensor(scene[k]).to(dtype) for k in ("points", "normals", "albedo", "spheres", "light")}
 
 
-def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None, dtype=DT):
+def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None, dtype=DT, exp_mode="squaring"):
     """Forward over a scene (optionally a subset of receivers), chunked."""
     T = scene_tensors(scene, dtype)
     n = int(scene["n_bands"])
@@ -173,7 +193,7 @@ def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None, dtype=DT):
         for s in range(0, len(sel), chunk):
             j = sel[s:s + chunk]
             o = forward(T["points"][j], T["normals"][j], T["albedo"][j], T["spheres"],
-                        T["light"], n, eps, n_squarings)
+                        T["light"], n, eps, n_squarings, exp_mode=exp_mode)
             for k in outs:
                 outs[k].append(o[k])
     N = n * n
@@ -181,7 +201,8 @@ def run_forward(scene, eps=3.0, n_squarings=4, chunk=1024, idx=None, dtype=DT):
             for k, v in outs.items()}
 
 
-def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=None, dtype=DT):
+def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=None, dtype=DT,
+                         exp_mode="squaring"):
     """Forward plus gradients of sum_p grad_B[p] * B[p].
 
     ``idx`` restricts the receivers to a subset (grad_B then has that
@@ -204,7 +225,7 @@ def run_forward_backward(scene, grad_B, eps=3.0, n_squarings=4, chunk=512, idx=N
         p = T["points"][j].clone().requires_grad_(True)
         nrm = T["normals"][j].clone().requires_grad_(True)
         a = T["albedo"][j].clone().requires_grad_(True)
-        o = forward(p, nrm, a, spheres, light, n, eps, n_squarings)
+        o = forward(p, nrm, a, spheres, light, n, eps, n_squarings, exp_mode=exp_mode)
         loss = (o["B"] * gB[s:s + chunk]).sum()
         ins = [p, nrm, a, spheres, light]
         g = torch.autograd.grad(loss, ins, allow_unused=True)

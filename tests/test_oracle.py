@@ -522,3 +522,45 @@ def test_channel_gradients_are_per_channel_and_summed_where_shared():
             acc[k] = acc[k] + m[k]
     for k in acc:
         assert torch.allclose(o[k], acc[k], rtol=1e-11, atol=1e-11), k
+
+
+# ------------------------------------------------------- quadrature exponential
+
+def test_quadrature_exponential_exact_cases():
+    for n in (1, 3, 8):
+        N = n * n
+        z = torch.zeros(2, N, dtype=DT)
+        V = method.sh_exponential_quadrature(z, n)
+        e0 = torch.zeros(N, dtype=DT)
+        e0[0] = math.sqrt(4 * PI)
+        assert torch.allclose(V, e0.expand(2, N), rtol=0, atol=1e-13)       # exp(0) = 1
+        F = torch.zeros(1, N, dtype=DT)
+        F[0, 0] = -2.5
+        V = method.sh_exponential_quadrature(F, n)
+        assert torch.allclose(V[0], math.exp(-2.5 / math.sqrt(4 * PI)) * e0, rtol=1e-13, atol=1e-14)
+
+
+def test_quadrature_exponential_converges_to_the_projected_exponential():
+    """The rule of degree 8n - 1 against a far finer one (brute force, degree
+    120): spectral convergence for smooth moderate F."""
+    g = torch.Generator().manual_seed(3)
+    for n, tol in ((2, 1e-12), (4, 1e-8), (8, 1e-4)):
+        F = torch.randn(4, n * n, dtype=DT, generator=g) * 0.5
+        F[:, 0] = -3.0
+        V = method.sh_exponential_quadrature(F, n)
+        ref = brute.exact_exponential(F, n, degree=120)
+        assert float((V - ref).norm() / ref.norm()) < tol, n
+
+
+def test_quadrature_exponential_gradient_matches_central_differences():
+    g = torch.Generator().manual_seed(4)
+    F = (torch.randn(3, 16, dtype=DT, generator=g) * 0.4).requires_grad_(True)
+    W = torch.randn(3, 16, dtype=DT, generator=g)
+    f = lambda x: (method.sh_exponential_quadrature(x, 4) * W).sum()  # noqa: E731
+    gr = torch.autograd.grad(f(F), F)[0]
+    h = 1e-6
+    for (a, b) in ((0, 0), (1, 5), (2, 15), (0, 9)):
+        e = torch.zeros_like(F)
+        e[a, b] = h
+        fd = (f(F.detach() + e) - f(F.detach() - e)) / (2 * h)
+        assert abs(float(gr[a, b] - fd)) < 1e-7 * max(1.0, abs(float(fd)))
