@@ -67,11 +67,18 @@ typedef int32_t shv_status;
  * n = 8 (Sec. 3.2).  n_squarings: k, the number of squarings of the SH
  * exponential (fixed per call; 4 by default).  eps: depth of the log-blocker,
  * log V' = -eps inside a sphere's cone (Eq. 13; the paper uses 3).  flags:
- * 0 or one of the SHV_FLAG_* values below (they select a kernel variant,
- * never the result: both variants are bitwise identical). */
+ * 0 or one of the SHV_FLAG_* values below.  The first two select a kernel
+ * variant, never the result (both variants are bitwise identical); the
+ * quadrature flag selects a different exponential. */
 #define SHV_FLAG_EXP_ONE_WAVE 1u   /* exponential: one receiver per lane, one wave per 64 receivers */
 #define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves
                                       (the default; both layouts give identical bits) */
+#define SHV_FLAG_EXP_QUADRATURE 4u /* a different exponential (this flag changes the result): the
+                                      projection of the pointwise exponential, V = exp(c) sum_q w_q
+                                      exp(Fhat~(w_q)) y(w_q), over the product rule of degree 8n - 1
+                                      (4n Gauss-Legendre nodes in z times 8n azimuths), on MFMA.
+                                      n_squarings is unused.  Only sh_visibility_forward /
+                                      sh_visibility_backward accept it; saved then holds F [N][P]. */
 typedef struct shv_params {
   int32_t n_bands;
   int32_t n_squarings;
@@ -90,7 +97,8 @@ const char* shv_status_string(shv_status s);
 const char* shv_last_error(void);
 
 /* Number of FP32 values the forward saves for the backward, per call:
- * (1 + k * N) * P  (the DC value c and E_0 .. E_{k-1} of the exponential). */
+ * (1 + k * N) * P  (the DC value c and E_0 .. E_{k-1} of the exponential);
+ * with SHV_FLAG_EXP_QUADRATURE the larger of that and N * P (F itself). */
 int64_t shv_saved_floats(int64_t P, const shv_params* prm);
 
 /* Workspace bytes that every entry point below needs for P receivers and S

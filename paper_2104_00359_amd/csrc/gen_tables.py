@@ -25,6 +25,8 @@ Run:  python gen_tables.py <out_dir>
 from __future__ import annotations
 
 import math
+
+import numpy as np
 import os
 import sys
 from fractions import Fraction
@@ -464,6 +466,13 @@ def emit_gaunt(path):
         L.append(f"__device__ const int shv_ltab_cnt_{n}[{len(pcnt)}] = {{" + ",".join(map(str, pcnt)) + "};")
         L.append(f"__device__ const unsigned short shv_ltab_pent_{n}[{len(pent)}] = {{" + ",".join(map(str, pent)) + "};")
         L.append(f"__device__ const float shv_ltab_pval_{n}[{len(pval)}] = {{" + ",".join(flit(c) for c in pval) + "};")
+    L.append("")
+    L.append("// Quadrature of the projected exponential: Gauss-Legendre nodes and weights in z,")
+    L.append("// 4n of them for n bands (the rule of degree 8n - 1 with 8n uniform azimuths).")
+    for n in range(1, MAX_BANDS + 1):
+        z, wz = np.polynomial.legendre.leggauss(4 * n)
+        L.append(f"__device__ const float shv_quad_z_{n}[{4 * n}] = {{" + ",".join(flit(v) for v in z) + "};")
+        L.append(f"__device__ const float shv_quad_w_{n}[{4 * n}] = {{" + ",".join(flit(v) for v in wz) + "};")
     L.append("")
     for n in range(1, MAX_BANDS + 1):
         supp = transfer_support(n)

@@ -99,10 +99,23 @@ shv_status check_params(const shv_params* prm) {
     return set_error(SHV_ERR_UNSUPPORTED, "n_squarings=%d outside [0, %d]", prm->n_squarings, SHV_MAX_SQUARINGS);
   if (!(prm->eps == prm->eps) || prm->eps < 0.0f)
     return set_error(SHV_ERR_INVALID_ARG, "eps must be a non-negative number");
-  const uint32_t known = SHV_FLAG_EXP_ONE_WAVE | SHV_FLAG_EXP_FOUR_WAVES;
+  const uint32_t layouts = SHV_FLAG_EXP_ONE_WAVE | SHV_FLAG_EXP_FOUR_WAVES;
+  const uint32_t known = layouts | SHV_FLAG_EXP_QUADRATURE;
   if (prm->flags & ~known) return set_error(SHV_ERR_INVALID_ARG, "unknown flags 0x%x", prm->flags);
-  if ((prm->flags & known) == known)
+  if ((prm->flags & layouts) == layouts)
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_ONE_WAVE and SHV_FLAG_EXP_FOUR_WAVES are exclusive");
+  if ((prm->flags & SHV_FLAG_EXP_QUADRATURE) && (prm->flags & layouts))
+    return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_QUADRATURE takes no layout flag");
+  return SHV_OK;
+}
+
+bool quadrature(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_QUADRATURE) != 0; }
+
+// Entry points built on the squaring exponential only.
+shv_status no_quadrature(const shv_params* prm) {
+  if (quadrature(prm))
+    return set_error(SHV_ERR_UNSUPPORTED,
+                     "SHV_FLAG_EXP_QUADRATURE is supported by sh_visibility_forward / sh_visibility_backward only");
   return SHV_OK;
 }
 
@@ -303,7 +316,9 @@ const char* shv_last_error(void) { return g_last_error.c_str(); }
 
 int64_t shv_saved_floats(int64_t P, const shv_params* prm) {
   if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || prm->n_squarings < 0 || P < 0) return 0;
-  return (1 + (int64_t)prm->n_squarings * prm->n_bands * prm->n_bands) * P;
+  const int64_t N = (int64_t)prm->n_bands * prm->n_bands;
+  const int64_t squaring = (1 + (int64_t)prm->n_squarings * N) * P;
+  return (prm->flags & SHV_FLAG_EXP_QUADRATURE) ? std::max(squaring, N * P) : squaring;
 }
 
 size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm) {
@@ -327,6 +342,7 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
                              const float* light, int64_t P, int64_t S, const shv_params* prm, float* vis,
                              float* radiance, float* saved, void* ws, size_t ws_bytes, hipStream_t stream) {
   SHV_TRY(check_params(prm));
+  SHV_TRY(no_quadrature(prm));
   SHV_TRY(check_sizes(P, S));
   SHV_TRY(check_device());
   if (P == 0) return SHV_OK;
@@ -362,6 +378,7 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
                               float* grad_albedo, float* grad_spheres, float* grad_light, void* ws, size_t ws_bytes,
                               hipStream_t stream) {
   SHV_TRY(check_params(prm));
+  SHV_TRY(no_quadrature(prm));
   SHV_TRY(check_sizes(P, S));
   SHV_TRY(check_device());
   const int nb = prm->n_bands;
@@ -432,6 +449,12 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
   SHV_TRY(launch("pair_fwd", stream, [&] {
     return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, nullptr, nullptr, stream);
   }));
+  if (quadrature(prm)) {
+    SHV_TRY(launch("exp_quad_fwd", stream, [&] {
+      return shv::launch_exp_quad_fwd(nb, Fpart, sp.nchunks, P, prm->eps, vis, saved, stream);
+    }));
+    return SHV_OK;
+  }
   SHV_TRY(launch("exp_fwd", stream, [&] {
     return shv::launch_exp_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, vis, saved, prm->flags,
                                stream);
@@ -710,9 +733,15 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   float* gp = (float*)((char*)ws + L.gp);
   float* gs = (float*)((char*)ws + L.gs);
   const shv::Split sp = shv::choose_split(P, S);
-  SHV_TRY(launch("exp_bwd", stream, [&] {
-    return shv::launch_exp_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, W, prm->flags, stream);
-  }));
+  if (quadrature(prm)) {
+    SHV_TRY(launch("exp_quad_bwd", stream, [&] {
+      return shv::launch_exp_quad_bwd(nb, grad_vis, vis, saved, P, prm->eps, W, stream);
+    }));
+  } else {
+    SHV_TRY(launch("exp_bwd", stream, [&] {
+      return shv::launch_exp_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, W, prm->flags, stream);
+    }));
+  }
   SHV_TRY(launch("pair_bwd", stream, [&] {
     return shv::launch_pair_bwd(nb, W, points, P, spheres, (int)S, sp, gp, gs, stream);
   }));
@@ -750,6 +779,7 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     const shv_scene& in = scenes[i];
     const shv_params* prm = &in.params;
     shv_status st = check_params(prm);
+    if (st == SHV_OK) st = no_quadrature(prm);
     if (st == SHV_OK) st = check_sizes(in.P, in.S);
     const char* what = nullptr;
     if (st == SHV_OK && in.P > 0) {

@@ -268,6 +268,20 @@ hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const flo
 #undef C
 }
 
+hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, float* vis,
+                               float* saved, hipStream_t st) {
+#define C(N) exp_quad_fwd_nb<N>(Fpart, nchunks, P, eps, vis, saved, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
+                               float* W, hipStream_t st) {
+#define C(N) exp_quad_bwd_nb<N>(gV, vis, saved, P, eps, W, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
 hipError_t launch_shade_ch_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
                                int channels, int64_t P, float* rad, hipStream_t st) {
 #define C(N) shade_ch_fwd_nb<N>(vis, nrm, alb, M, channels, P, rad, st)

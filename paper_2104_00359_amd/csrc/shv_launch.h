@@ -55,6 +55,11 @@ inline int envmap_rows_per_block(int64_t W) {
 }
 hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P,
                           float eps, int k, float* W, uint32_t flags, hipStream_t st);
+// The exponential by quadrature projection (SHV_FLAG_EXP_QUADRATURE); saved holds F [N][P].
+hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, float* vis,
+                               float* saved, hipStream_t st);
+hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
+                               float* W, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,
                            Split sp, float* gp_part, float* gs_part, hipStream_t st);
 // Zero n floats with a plain kernel (safe inside captured graphs).
@@ -110,6 +115,12 @@ hipError_t shade_ch_bwd_nb(const float* gB, const float* vis, const float* nrm, 
                            int channels, int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
 template <int NB>
 hipError_t envmap_rows_nb(const float* img, int channels, int64_t H, int64_t W, float* part, hipStream_t st);
+template <int NB>
+hipError_t exp_quad_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, float* vis, float* saved,
+                           hipStream_t st);
+template <int NB>
+hipError_t exp_quad_bwd_nb(const float* gV, const float* vis, const float* saved, int64_t P, float eps, float* W,
+                           hipStream_t st);
 template <int NB>
 hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>

@@ -5,10 +5,11 @@
 
 #include "shv_exp_impl.h"
 #include "shv_pair_impl.h"
+#include "shv_quad_impl.h"
 #include "shv_shade_impl.h"
 
 #if !defined(SHV_NB) || !defined(SHV_PART)
-#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..5>"
+#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..6>"
 #endif
 
 namespace shv {
@@ -47,6 +48,10 @@ template hipError_t exp_bwd_nb<SHV_NB, true>(const float*, const float*, const f
 template hipError_t batch_exp_fwd_nb<SHV_NB>(const void*, bool, int64_t, hipStream_t);
 #elif SHV_PART == 5
 template hipError_t batch_exp_bwd_nb<SHV_NB>(const void*, bool, int64_t, hipStream_t);
+#elif SHV_PART == 6
+template hipError_t exp_quad_fwd_nb<SHV_NB>(const float*, int, int64_t, float, float*, float*, hipStream_t);
+template hipError_t exp_quad_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, float, float*,
+                                            hipStream_t);
 #endif
 
 }  // namespace shv
