@@ -479,7 +479,7 @@ shv_status sh_shade(const float* vis, const float* normals, const float* albedo,
   float* M = (float*)((char*)ws + L.M);
   SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream); }));
   SHV_TRY(launch("shade_fwd", stream, [&] {
-    return shv::launch_shade_fwd(nb, vis, normals, albedo, M, P, radiance, stream);
+    return shv::launch_shade_ch_fwd(nb, vis, normals, albedo, M, 1, P, radiance, stream);
   }));
   return SHV_OK;
 }
@@ -509,8 +509,8 @@ shv_status sh_shade_backward(const float* grad_radiance, const float* vis, const
   float* Lpart = grad_light ? (float*)((char*)ws + L.lpart) : nullptr;
   SHV_TRY(launch("build_M", stream, [&] { return shv::launch_build_M(nb, light, M, stream); }));
   SHV_TRY(launch("shade_bwd", stream, [&] {
-    return shv::launch_shade_bwd(nb, grad_radiance, vis, normals, albedo, M, P, grad_vis, grad_normals, grad_albedo,
-                                 Lpart, stream);
+    return shv::launch_shade_ch_bwd(nb, grad_radiance, vis, normals, albedo, M, 1, P, grad_vis, grad_normals,
+                                    grad_albedo, Lpart, stream);
   }));
   if (grad_light) {
     SHV_TRY(launch("reduce_light", stream, [&] {

@@ -253,21 +253,6 @@ hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st, 
 #undef C
 }
 
-hipError_t launch_shade_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M, int64_t P,
-                            float* rad, hipStream_t st) {
-#define C(N) shade_fwd_nb<N>(vis, nrm, alb, M, P, rad, st)
-  SHV_NB_SWITCH(nb, C)
-#undef C
-}
-
-hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
-                            const float* M, int64_t P, float* gV, float* gN, float* gA, float* Lpart,
-                            hipStream_t st) {
-#define C(N) shade_bwd_nb<N>(gB, vis, nrm, alb, M, P, gV, gN, gA, Lpart, st)
-  SHV_NB_SWITCH(nb, C)
-#undef C
-}
-
 hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, float* vis,
                                float* saved, hipStream_t st) {
 #define C(N) exp_quad_fwd_nb<N>(Fpart, nchunks, P, eps, vis, saved, st)

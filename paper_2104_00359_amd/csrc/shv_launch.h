@@ -29,11 +29,6 @@ hipError_t launch_exp_fwd(int nb, const float* Fpart, int nchunks, int64_t P, fl
                           float* vis, float* saved, uint32_t flags, hipStream_t st);
 // M(L) for `channels` lights light + c N into M + c N^2.
 hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st, int channels = 1);
-hipError_t launch_shade_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
-                            int64_t P, float* rad, hipStream_t st);
-hipError_t launch_shade_bwd(int nb, const float* gB, const float* vis, const float* nrm, const float* alb,
-                            const float* M, int64_t P, float* gV, float* gN, float* gA, float* Lpart,
-                            hipStream_t st);
 // out[y][c] = sum over r of part[y][r][c] (rows in order; y < batch).
 hipError_t launch_reduce_rows(const float* part, int rows, int cols, float* out, hipStream_t st, int batch = 1);
 // Several colour channels sharing V (channel c's data at M + c N^2, alb / rad / gB / gA + c P,
@@ -101,12 +96,6 @@ hipError_t exp_bwd_nb(const float* gIn, const float* vis, const float* saved, in
                       uint32_t flags, hipStream_t st);
 template <int NB>
 hipError_t build_M_nb(const float* light, float* M, int channels, hipStream_t st);
-template <int NB>
-hipError_t shade_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int64_t P, float* rad,
-                        hipStream_t st);
-template <int NB>
-hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
-                        int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st);
 template <int NB>
 hipError_t shade_ch_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int channels,
                            int64_t P, float* rad, hipStream_t st);

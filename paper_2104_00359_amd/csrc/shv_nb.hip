@@ -20,10 +20,6 @@ template hipError_t pair_fwd_nb<SHV_NB>(const float*, int64_t, const float*, int
 template hipError_t pair_bwd_nb<SHV_NB>(const float*, const float*, int64_t, const float*, int, Split, float*, float*,
                                         hipStream_t);
 template hipError_t build_M_nb<SHV_NB>(const float*, float*, int, hipStream_t);
-template hipError_t shade_fwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, int64_t, float*,
-                                         hipStream_t);
-template hipError_t shade_bwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, const float*, int64_t,
-                                         float*, float*, float*, float*, hipStream_t);
 template hipError_t shade_ch_fwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, int, int64_t,
                                             float*, hipStream_t);
 template hipError_t shade_ch_bwd_nb<SHV_NB>(const float*, const float*, const float*, const float*, const float*, int,

@@ -7,16 +7,17 @@
 // the columns of M on H's support are ever read (31 of 64 at n = 8).
 // Each block first copies those columns of M into LDS (stage_M).
 //
-// Several colour channels (one light L_c and albedo a_c per channel, one
+// One to four colour channels (one light L_c and albedo a_c per channel, one
 // shared visibility, Eq. 8 per channel) are shaded by one launch that stages
-// every channel's M and reads V and H once; channel c's radiance, albedo
-// gradient and lighting gradient are bitwise those of a one-channel call, and
-// the V and normal cotangents are summed over the channels in channel order.
+// every channel's M and reads V and H once; sh_shade is the one-channel case.
+// Channel c's radiance, albedo gradient and lighting gradient are bitwise
+// those of a one-channel call, and the V and normal cotangents are summed
+// over the channels in channel order.
 //
 // Environment-map projection (Eq. 9): L_i = integral of L(w) y_i(w) dw over
 // an equirectangular map, as the sum over pixels of value * y_i(pixel centre)
-// * pixel solid angle; one block per (row, channel) forms the row's sum, the
-// rows are then added in row order.
+// * pixel solid angle; a block covers several rows of one channel, and the
+// block partials are then added in row order.
 //
 // Adjoint for the cotangent Bbar, w = Bbar a:
 //   abar = Bbar (V^T M H),  Vbar = w M H,  Hbar = w M V  -> nbar through the
@@ -33,7 +34,6 @@
 
 namespace shv {
 
-
 // Channel y = blockIdx.y: M + y N^2 from L + y N.
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_build_M(const float* __restrict__ L, float* __restrict__ M) {
@@ -42,83 +42,6 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_build_M(const float* __restrict__
   build_M_range<NB>(L + y * N, M + y * N * N, blockIdx.x * SHV_BLOCK + threadIdx.x, gridDim.x * SHV_BLOCK);
 }
 
-template <int NB>
-__global__ __launch_bounds__(SHV_BLOCK) void k_shade_fwd(const float* __restrict__ vis, const float* __restrict__ nrm,
-                                                         const float* __restrict__ alb, const float* __restrict__ M,
-                                                         int64_t P, float* __restrict__ rad) {
-  constexpr int N = NB * NB;
-  __shared__ float Ms[MSupp<NB>::SIZE];
-  stage_M<NB>(M, Ms, threadIdx.x);
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
-  if (p >= P) return;
-  float V[N], H[N], Hb[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = vis[(int64_t)i * P + p];
-  float ux, uy, uz;
-  transfer<NB>(nrm[p], nrm[P + p], nrm[2 * P + p], H, ux, uy, uz);
-  rad[p] = alb[p] * shade_value<NB, false>(V, H, Ms, 0.0f, Hb);
-}
-
-// One receiver per lane, 256 receivers per block (4 tiles of 64).
-template <int NB>
-__global__ __launch_bounds__(SHV_BLOCK) void k_shade_bwd(const float* __restrict__ gB, const float* __restrict__ vis,
-                                                         const float* __restrict__ nrm, const float* __restrict__ alb,
-                                                         const float* __restrict__ M, int64_t P,
-                                                         float* __restrict__ gV, float* __restrict__ gN,
-                                                         float* __restrict__ gA, float* __restrict__ Lpart) {
-  constexpr int N = NB * NB;
-  __shared__ LightTile T;
-  __shared__ float Ms[MSupp<NB>::SIZE];
-  stage_M<NB>(M, Ms, threadIdx.x);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
-  const bool ok = p < P;
-  const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
-  float V[N], H[N], Hb[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = sel0(ok, vis[(int64_t)i * P + q]);
-  float ux, uy, uz;
-  const float inv = transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
-  const float bb = sel0(ok, gB[q]);
-  const float w = bb * sel0(ok, alb[q]);
-  const float s = shade_value<NB, true>(V, H, Ms, w, Hb);
-  if (ok) {
-    if (gA) gA[p] = bb * s;
-    if (gV) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) gV[(int64_t)j * P + p] = vbar_entry<NB>(j, H, Ms, w);
-    }
-    if (gN) {
-      float gx, gy, gz;
-      normal_grad<NB>(Hb, ux, uy, uz, inv, gx, gy, gz);
-      gN[p] = gx;
-      gN[P + p] = gy;
-      gN[2 * P + p] = gz;
-    }
-  }
-  if (!Lpart) return;  // uniform
-  for (int r = 0; r < SHV_WAVES_PER_BLOCK; ++r) {
-    const int64_t tile = (int64_t)blockIdx.x * SHV_WAVES_PER_BLOCK + r;
-    if (tile * 64 >= P) break;  // uniform
-    if (wave == r) {
-      tile_put_v<NB>(T, lane, V);
-      tile_put_wh<NB>(T, lane, H, w);
-    }
-    __syncthreads();
-    tile_light_partial<NB>(T, Lpart + tile * N);
-  }
-}
-
-// Several channels (CH of them, 1 .. SHV_MAX_CHANNELS): channel c's light
-// matrix at M + c N^2, albedo / radiance / cotangents at + c P.
-//
-// Layout: 64 receivers per block, four waves.  The V rows are loaded by the
-// four waves together (row i by wave i mod 4, coalesced over the 64
-// receivers) and exchanged through LDS; wave g then forms the shading
-// partial over support columns kk = g (mod 4) of every channel, exactly the
-// partial g of the canonical order, so the block adds them in that order.
 // Rows i = G, G + 4, ... of a row-major [N][P] array at receiver p into LDS
 // dst[i * row_pitch + lane * lane_pitch] (0 when !ok).  The row index is
 // formed at run time from the wave number, so every load is issued before
@@ -419,20 +342,6 @@ hipError_t build_M_nb(const float* light, float* M, int channels, hipStream_t st
   constexpr int NN = NB * NB * NB * NB;
   k_build_M<NB><<<dim3((unsigned)((NN + SHV_BLOCK - 1) / SHV_BLOCK), (unsigned)channels), SHV_BLOCK, 0, st>>>(light,
                                                                                                               M);
-  return hipGetLastError();
-}
-
-template <int NB>
-hipError_t shade_fwd_nb(const float* vis, const float* nrm, const float* alb, const float* M, int64_t P, float* rad,
-                        hipStream_t st) {
-  k_shade_fwd<NB><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(vis, nrm, alb, M, P, rad);
-  return hipGetLastError();
-}
-
-template <int NB>
-hipError_t shade_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
-                        int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st) {
-  k_shade_bwd<NB><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(gB, vis, nrm, alb, M, P, gV, gN, gA, Lpart);
   return hipGetLastError();
 }
 

@@ -118,6 +118,25 @@ def shade_ch_bwd_flops(n: int, channels: int) -> int:
     return h + nbar + channels * (mv + vbar + lbar)
 
 
+def quad_nodes(n: int) -> int:
+    """Nodes of the quadrature exponential's rule (4n x 8n)."""
+    return 32 * n * n
+
+
+def exp_quad_fwd_flops(n: int) -> int:
+    """Per receiver: f = Fhat Y over the nodes and V = (w exp f) Y^T, two
+    N x Q products, plus one exponential and one weight multiply per node."""
+    N, Q = n * n, quad_nodes(n)
+    return 2 * (2 * N * Q) + 2 * Q
+
+
+def exp_quad_bwd_flops(n: int) -> int:
+    """Per receiver: f and g = Vbar Y, then Fbar = (w exp f g) Y^T: three
+    N x Q products, plus the exponential and two multiplies per node."""
+    N, Q = n * n, quad_nodes(n)
+    return 3 * (2 * N * Q) + 3 * Q
+
+
 def envmap_pixel_flops(n: int) -> int:
     """One map pixel: sin and cos of its azimuth, the direction (3), the
     polynomial SH basis (powers of x + i y, three-term recurrences in z, one
@@ -147,6 +166,10 @@ def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pi
         return shade_ch_bwd_flops(n, channels) * P, P
     if name == "envmap_rows":
         return envmap_pixel_flops(n) * pixels, pixels
+    if name == "exp_quad_fwd":
+        return exp_quad_fwd_flops(n) * P, P
+    if name == "exp_quad_bwd":
+        return exp_quad_bwd_flops(n) * P, P
     if name == "pair_fwd":
         return pair_fwd_flops(n) * P * S, P * S
     if name == "pair_bwd":
