@@ -160,6 +160,13 @@ size_t fwd_bytes(int64_t P, int64_t S, int nb, FwdWs* o = nullptr) {
   if (o) o->fpart = 0;
   return fpart;
 }
+// The quadrature exponential's basis table and partial sums (after the
+// phase's own workspace).
+size_t quad_table_bytes(int nb) { return align_up((size_t)shv::quad_table_floats(nb) * 4); }
+size_t quad_bytes(int nb, int64_t P) {
+  return quad_table_bytes(nb) + align_up((size_t)shv::quad_part_floats(nb, P) * 4);
+}
+
 size_t shade_bytes(int64_t P, int nb, ShadeWs* o = nullptr) {
   const size_t N = (size_t)nb * nb;
   const size_t m = align_up(N * N * 4);
@@ -329,6 +336,10 @@ size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm) {
   b = std::max(b, visbwd_bytes(P, S, nb));
   b = std::max(b, render_fwd_bytes(P, S, nb));
   b = std::max(b, render_bwd_bytes(P, S, nb));
+  if (prm->flags & SHV_FLAG_EXP_QUADRATURE) {
+    b = std::max(b, fwd_bytes(P, S, nb) + quad_bytes(nb, P));
+    b = std::max(b, visbwd_bytes(P, S, nb) + quad_bytes(nb, P));
+  }
   return b;
 }
 
@@ -442,8 +453,8 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
     SHV_TRY(aligned16(spheres, "spheres"));
   }
   const int nb = prm->n_bands;
-  const size_t needed = fwd_bytes(P, S, nb);
-  SHV_TRY(check_ws(ws, ws_bytes, needed));
+  const size_t base = fwd_bytes(P, S, nb);
+  SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
   float* Fpart = (float*)ws;
   const shv::Split sp = shv::choose_split(P, S);
   SHV_TRY(launch("pair_fwd", stream, [&] {
@@ -451,7 +462,8 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
   }));
   if (quadrature(prm)) {
     SHV_TRY(launch("exp_quad_fwd", stream, [&] {
-      return shv::launch_exp_quad_fwd(nb, Fpart, sp.nchunks, P, prm->eps, vis, saved, stream);
+      return shv::launch_exp_quad_fwd(nb, Fpart, sp.nchunks, P, prm->eps, vis, saved, (float*)((char*)ws + base),
+                                      (float*)((char*)ws + base + quad_table_bytes(nb)), stream);
     }));
     return SHV_OK;
   }
@@ -728,14 +740,16 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   }
   const int nb = prm->n_bands;
   VisBwdWs L;
-  SHV_TRY(check_ws(ws, ws_bytes, visbwd_bytes(P, S, nb, &L)));
+  const size_t base = visbwd_bytes(P, S, nb, &L);
+  SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
   float* W = (float*)((char*)ws + L.W);
   float* gp = (float*)((char*)ws + L.gp);
   float* gs = (float*)((char*)ws + L.gs);
   const shv::Split sp = shv::choose_split(P, S);
   if (quadrature(prm)) {
     SHV_TRY(launch("exp_quad_bwd", stream, [&] {
-      return shv::launch_exp_quad_bwd(nb, grad_vis, vis, saved, P, prm->eps, W, stream);
+      return shv::launch_exp_quad_bwd(nb, grad_vis, vis, saved, P, prm->eps, W, (float*)((char*)ws + base),
+                                      (float*)((char*)ws + base + quad_table_bytes(nb)), stream);
     }));
   } else {
     SHV_TRY(launch("exp_bwd", stream, [&] {

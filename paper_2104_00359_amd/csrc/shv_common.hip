@@ -254,15 +254,15 @@ hipError_t launch_build_M(int nb, const float* light, float* M, hipStream_t st, 
 }
 
 hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, float* vis,
-                               float* saved, hipStream_t st) {
-#define C(N) exp_quad_fwd_nb<N>(Fpart, nchunks, P, eps, vis, saved, st)
+                               float* saved, float* table, float* part, hipStream_t st) {
+#define C(N) exp_quad_fwd_nb<N>(Fpart, nchunks, P, eps, vis, saved, table, part, st)
   SHV_NB_SWITCH(nb, C)
 #undef C
 }
 
 hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
-                               float* W, hipStream_t st) {
-#define C(N) exp_quad_bwd_nb<N>(gV, vis, saved, P, eps, W, st)
+                               float* W, float* table, float* part, hipStream_t st) {
+#define C(N) exp_quad_bwd_nb<N>(gV, vis, saved, P, eps, W, table, part, st)
   SHV_NB_SWITCH(nb, C)
 #undef C
 }

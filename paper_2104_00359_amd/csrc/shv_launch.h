@@ -50,11 +50,15 @@ inline int envmap_rows_per_block(int64_t W) {
 }
 hipError_t launch_exp_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P,
                           float eps, int k, float* W, uint32_t flags, hipStream_t st);
-// The exponential by quadrature projection (SHV_FLAG_EXP_QUADRATURE); saved holds F [N][P].
+// The exponential by quadrature projection (SHV_FLAG_EXP_QUADRATURE); saved holds F [N][P];
+// table is scratch of quad_table_floats(nb) floats (the rule's basis and weights), part of
+// quad_part_floats(nb, P) (partial sums over two interleaved halves of the nodes).
+inline int64_t quad_table_floats(int nb) { return (int64_t)((32 * nb * nb + 63) / 64 * 64) * 65; }
+inline int64_t quad_part_floats(int nb, int64_t P) { return 2 * (int64_t)nb * nb * P; }
 hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, float* vis,
-                               float* saved, hipStream_t st);
+                               float* saved, float* table, float* part, hipStream_t st);
 hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
-                               float* W, hipStream_t st);
+                               float* W, float* table, float* part, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,
                            Split sp, float* gp_part, float* gs_part, hipStream_t st);
 // Zero n floats with a plain kernel (safe inside captured graphs).
@@ -106,10 +110,10 @@ template <int NB>
 hipError_t envmap_rows_nb(const float* img, int channels, int64_t H, int64_t W, float* part, hipStream_t st);
 template <int NB>
 hipError_t exp_quad_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, float* vis, float* saved,
-                           hipStream_t st);
+                           float* table, float* part, hipStream_t st);
 template <int NB>
 hipError_t exp_quad_bwd_nb(const float* gV, const float* vis, const float* saved, int64_t P, float eps, float* W,
-                           hipStream_t st);
+                           float* table, float* part, hipStream_t st);
 template <int NB>
 hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>

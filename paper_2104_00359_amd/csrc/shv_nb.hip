@@ -45,9 +45,10 @@ template hipError_t batch_exp_fwd_nb<SHV_NB>(const void*, bool, int64_t, hipStre
 #elif SHV_PART == 5
 template hipError_t batch_exp_bwd_nb<SHV_NB>(const void*, bool, int64_t, hipStream_t);
 #elif SHV_PART == 6
-template hipError_t exp_quad_fwd_nb<SHV_NB>(const float*, int, int64_t, float, float*, float*, hipStream_t);
-template hipError_t exp_quad_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, float, float*,
+template hipError_t exp_quad_fwd_nb<SHV_NB>(const float*, int, int64_t, float, float*, float*, float*, float*,
                                             hipStream_t);
+template hipError_t exp_quad_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, float, float*, float*,
+                                            float*, hipStream_t);
 #endif
 
 }  // namespace shv

@@ -84,21 +84,38 @@ struct QuadShared {
   float cs[64];               // c of each receiver
 };
 
-// Y of the tile's 64 nodes into Yt (coefficients >= N zero) and their weights.
+// The rule's basis table: Ytab[q * 64 + t] = y_t(w_q) (0 for t >= N) and
+// wtab[q], one thread per node (once per call; every block then reads it).
 template <int NB>
-__device__ __forceinline__ void quad_tile_basis(QuadShared& sh, int q0) {
+__global__ __launch_bounds__(SHV_BLOCK) void k_quad_table(float* __restrict__ Ytab, float* __restrict__ wtab) {
   constexpr int N = NB * NB;
-  const int node = threadIdx.x & 63, quarter = threadIdx.x >> 6;
+  const int q = blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (q >= QuadRule<NB>::QP) return;
   float x, y, z, w;
-  quad_node<NB>(q0 + node, x, y, z, w);
+  quad_node<NB>(q, x, y, z, w);
   float Y[N];
   sh_eval<NB>(x, y, z, Y);
 #pragma unroll
-  for (int t = 0; t < 64; ++t) {
-    if ((t >> 4) != quarter) continue;  // wave-uniform
-    sh.Yt[t * kQuadPitch + node] = t < N ? Y[t < N ? t : 0] : 0.0f;
+  for (int t = 0; t < 64; ++t) Ytab[(int64_t)q * 64 + t] = t < N ? Y[t < N ? t : 0] : 0.0f;
+  wtab[q] = w;
+}
+
+// The tile's 64 nodes from the table into Yt [coef][node] and wq: thread t
+// copies 16 coefficients (t % 4) of node t / 4 (float4 loads).
+__device__ __forceinline__ void quad_tile_load(QuadShared& sh, const float* __restrict__ Ytab,
+                                               const float* __restrict__ wtab, int q0) {
+  const int node = threadIdx.x >> 2, part = threadIdx.x & 3;
+  const float4* src = reinterpret_cast<const float4*>(Ytab + (int64_t)(q0 + node) * 64 + 16 * part);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float4 y = src[v];
+    const int c = 16 * part + 4 * v;
+    sh.Yt[(c + 0) * kQuadPitch + node] = y.x;
+    sh.Yt[(c + 1) * kQuadPitch + node] = y.y;
+    sh.Yt[(c + 2) * kQuadPitch + node] = y.z;
+    sh.Yt[(c + 3) * kQuadPitch + node] = y.w;
   }
-  if (quarter == 0) sh.wq[node] = w;
+  if (part == 0) sh.wq[node] = wtab[q0 + node];
 }
 
 // 32 x 32 quadrant (rows ra.., cols cb..) of A [64 x 64 K] * B [64 K x 64]
@@ -149,11 +166,15 @@ __device__ __forceinline__ void quad_load_rows(const float* __restrict__ X, int 
   }
 }
 
-// Forward: Fpart [nchunks][N][P] -> vis [N][P]; saved (may be NULL) <- F [N][P].
+// Forward: Fpart [nchunks][N][P] -> vis [gridDim.y][N][P], the partial sums of
+// V over the node tiles y, y + gridDim.y, ... (added afterwards in order);
+// saved (may be NULL) <- F [N][P].
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_fwd(const float* __restrict__ Fpart, int nchunks, int64_t P,
                                                             float eps, float* __restrict__ vis,
-                                                            float* __restrict__ saved) {
+                                                            float* __restrict__ saved,
+                                                            const float* __restrict__ Ytab,
+                                                            const float* __restrict__ wtab) {
   constexpr int N = NB * NB;
   __shared__ QuadShared sh;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -165,7 +186,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_fwd(const float* __restr
   quad_load_rows<NB>(Fpart, nchunks, (int64_t)N * P, P, p, ok, a);
 #pragma unroll
   for (int s = 0; s < 32; ++s) a[s] *= eps * coef_lambda(2 * s + half < N ? 2 * s + half : 0);
-  if (cb == 0 && ok && saved) {
+  if (cb == 0 && ok && saved && blockIdx.y == 0) {
 #pragma unroll
     for (int s = 0; s < 32; ++s)
       if (2 * s + half < N) saved[(int64_t)(2 * s + half) * P + p] = a[s];
@@ -175,8 +196,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_fwd(const float* __restr
   mfma_f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int q0 = 0; q0 < QuadRule<NB>::QP; q0 += 64) {
-    quad_tile_basis<NB>(sh, q0);
+  for (int q0 = 64 * blockIdx.y; q0 < QuadRule<NB>::QP; q0 += 64 * gridDim.y) {
+    quad_tile_load(sh, Ytab, wtab, q0);
     __syncthreads();
     mfma_f32x16 f;
 #pragma unroll
@@ -196,16 +217,18 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_fwd(const float* __restr
   for (int r = 0; r < 16; ++r) {
     const int rec = ra + quad_row(r);
     const int64_t pr = (int64_t)blockIdx.x * 64 + rec;
-    if (pr < P) vis[(int64_t)coef * P + pr] = expf(sh.cs[rec]) * acc[r];
+    if (pr < P) vis[blockIdx.y * (int64_t)N * P + (int64_t)coef * P + pr] = expf(sh.cs[rec]) * acc[r];
   }
 }
 
-// Adjoint: gV, vis, saved F [N][P] -> W [N][P] = eps lambda Fbar.
+// Adjoint: gV, vis, saved F [N][P] -> W [gridDim.y][N][P], partial sums of
+// eps lambda Fbar over the node tiles as in the forward.
 template <int NB>
 __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_bwd(const float* __restrict__ gV,
                                                             const float* __restrict__ vis,
                                                             const float* __restrict__ saved, int64_t P, float eps,
-                                                            float* __restrict__ W) {
+                                                            float* __restrict__ W, const float* __restrict__ Ytab,
+                                                            const float* __restrict__ wtab) {
   constexpr int N = NB * NB;
   __shared__ QuadShared sh;
   __shared__ float cbar[64];
@@ -230,8 +253,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_bwd(const float* __restr
   mfma_f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int q0 = 0; q0 < QuadRule<NB>::QP; q0 += 64) {
-    quad_tile_basis<NB>(sh, q0);
+  for (int q0 = 64 * blockIdx.y; q0 < QuadRule<NB>::QP; q0 += 64 * gridDim.y) {
+    quad_tile_load(sh, Ytab, wtab, q0);
     __syncthreads();
     mfma_f32x16 f, gq;
 #pragma unroll
@@ -257,23 +280,41 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_exp_quad_bwd(const float* __restr
     const int rec = ra + quad_row(r);
     const int64_t pr = (int64_t)blockIdx.x * 64 + rec;
     if (pr >= P) continue;
-    const float fb = coef == 0 ? cbar[rec] * SHV_INV_SQRT_4PI : expf(sh.cs[rec]) * acc[r];
-    W[(int64_t)coef * P + pr] = lam * fb;
+    const float fb = coef == 0 ? (blockIdx.y == 0 ? cbar[rec] * SHV_INV_SQRT_4PI : 0.0f) : expf(sh.cs[rec]) * acc[r];
+    W[blockIdx.y * (int64_t)N * P + (int64_t)coef * P + pr] = lam * fb;
   }
 }
 
+// table: QuadRule<NB>::QP * 65 floats (the basis, then the weights); part:
+// kQuadSplits * N * P floats, the per-split partial sums added in split order.
+constexpr int kQuadSplits = 2;  // blocks per 64-receiver tile (node tiles interleaved)
+
 template <int NB>
 hipError_t exp_quad_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, float* vis, float* saved,
-                           hipStream_t st) {
-  k_exp_quad_fwd<NB><<<(unsigned)pair_blocks(P), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, vis, saved);
-  return hipGetLastError();
+                           float* table, float* part, hipStream_t st) {
+  constexpr int QP = QuadRule<NB>::QP, N = NB * NB;
+  float* Ytab = table;
+  float* wtab = table + (int64_t)QP * 64;
+  k_quad_table<NB><<<(QP + SHV_BLOCK - 1) / SHV_BLOCK, SHV_BLOCK, 0, st>>>(Ytab, wtab);
+  k_exp_quad_fwd<NB><<<dim3((unsigned)pair_blocks(P), kQuadSplits), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, part,
+                                                                                        saved, Ytab, wtab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_chunks(part, kQuadSplits, (int64_t)N * P, vis, st);
 }
 
 template <int NB>
 hipError_t exp_quad_bwd_nb(const float* gV, const float* vis, const float* saved, int64_t P, float eps, float* W,
-                           hipStream_t st) {
-  k_exp_quad_bwd<NB><<<(unsigned)pair_blocks(P), SHV_BLOCK, 0, st>>>(gV, vis, saved, P, eps, W);
-  return hipGetLastError();
+                           float* table, float* part, hipStream_t st) {
+  constexpr int QP = QuadRule<NB>::QP, N = NB * NB;
+  float* Ytab = table;
+  float* wtab = table + (int64_t)QP * 64;
+  k_quad_table<NB><<<(QP + SHV_BLOCK - 1) / SHV_BLOCK, SHV_BLOCK, 0, st>>>(Ytab, wtab);
+  k_exp_quad_bwd<NB><<<dim3((unsigned)pair_blocks(P), kQuadSplits), SHV_BLOCK, 0, st>>>(gV, vis, saved, P, eps, part,
+                                                                                        Ytab, wtab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_chunks(part, kQuadSplits, (int64_t)N * P, W, st);
 }
 
 }  // namespace shv
