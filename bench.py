@@ -6,7 +6,8 @@ spheres, 8 bands, k = 4), synthetic and seeded, through the fused
 sh_render_forward (visibility + shading) and sh_render_backward (gradients
 for receivers, normals, albedo, spheres and lighting) of the C ABI
 (``--path separate`` uses the four separate entry points instead; the results
-are bit-identical).
+are bit-identical; ``--path separate --flags 4`` takes the exponential by
+quadrature projection on MFMA instead of scaling and squaring).
 
 ``--workload serve``: Poisson arrivals of forward + backward requests (90%
 from the 64-scene distribution, 10% at 262,144 receivers x 512 spheres)
@@ -67,7 +68,9 @@ def parse():
                     help="target duration of the oracle CPU baseline sample (0 disables it)")
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--path", default="render", choices=["render", "separate"])
-    ap.add_argument("--flags", type=int, default=0, help="shv_params.flags (kernel-variant selection)")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="shv_params.flags: 1 / 2 select the exponential's kernel layout; 4 selects the "
+                         "quadrature exponential (a different approximation; separate entry points only)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched64: time eager batched calls instead of graph replays")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
