@@ -7,7 +7,8 @@ sh_render_forward (visibility + shading) and sh_render_backward (gradients
 for receivers, normals, albedo, spheres and lighting) of the C ABI
 (``--path separate`` uses the four separate entry points instead; the results
 are bit-identical; ``--path separate --flags 4`` takes the exponential by
-quadrature projection on MFMA instead of scaling and squaring).
+quadrature projection on MFMA instead of scaling and squaring, and
+``--path separate --flags 8`` forms V by the direct product chain of Eq. 12).
 
 ``--workload serve``: Poisson arrivals of forward + backward requests (90%
 from the 64-scene distribution, 10% at 262,144 receivers x 512 spheres)
@@ -70,7 +71,8 @@ def parse():
     ap.add_argument("--path", default="render", choices=["render", "separate"])
     ap.add_argument("--flags", type=int, default=0,
                     help="shv_params.flags: 1 / 2 select the exponential's kernel layout; 4 selects the "
-                         "quadrature exponential (a different approximation; separate entry points only)")
+                         "quadrature exponential, 8 the direct product chain of Eq. 12 (different "
+                         "approximations; separate entry points only)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched64: time eager batched calls instead of graph replays")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
@@ -103,7 +105,7 @@ def make_scene(name):
     return sc, desc
 
 
-def cpu_baseline(scenes, k, seconds):
+def cpu_baseline(scenes, k, seconds, exp_mode="squaring"):
     """The FP64 oracle (autograd for the backward) on seeded samples of
     receivers (chunks of 256, all spheres), cycling over ``scenes`` until
     ``seconds`` have elapsed or every receiver is done."""
@@ -121,7 +123,7 @@ def cpu_baseline(scenes, k, seconds):
         sc = scenes[j]
         if done[j] < sc["points"].shape[0]:
             idx = np.sort(perms[j][done[j]:done[j] + 256])
-            method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=k, idx=idx)
+            method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=k, idx=idx, exp_mode=exp_mode)
             done[j] += len(idx)
             pairs += len(idx) * sc["spheres"].shape[0]
         elif all(d >= s["points"].shape[0] for d, s in zip(done, scenes)):
@@ -133,7 +135,8 @@ def cpu_baseline(scenes, k, seconds):
              f"{sum(done)} of {tot} receivers over {sum(1 for d in done if d)} of {len(scenes)} scenes "
              "(seeded permutations, 256 per scene in turn)")
     return {"value": pairs / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{where} x all spheres, FP64 forward + autograd backward, {dt:.1f} s"}
+            "sample": f"{where} x all spheres, FP64 forward + autograd backward"
+                      f"{'' if exp_mode == 'squaring' else f' ({exp_mode} mode)'}, {dt:.1f} s"}
 
 
 def kernel_table(prof):
@@ -307,7 +310,8 @@ def bench_single(args):
     roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
     if roof is not None:
         roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
-    cpu = cpu_baseline([sc], k, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    mode = {4: "quadrature", 8: "product"}.get(args.flags, "squaring")
+    cpu = cpu_baseline([sc], k, args.cpu_seconds, mode) if args.cpu_seconds > 0 else None
     return {
         "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -69,7 +69,7 @@ typedef int32_t shv_status;
  * log V' = -eps inside a sphere's cone (Eq. 13; the paper uses 3).  flags:
  * 0 or one of the SHV_FLAG_* values below.  The first two select a kernel
  * variant, never the result (both variants are bitwise identical); the
- * quadrature flag selects a different exponential. */
+ * quadrature and product flags select a different way of forming V. */
 #define SHV_FLAG_EXP_ONE_WAVE 1u   /* exponential: one receiver per lane, one wave per 64 receivers */
 #define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves
                                       (the default; both layouts give identical bits) */
@@ -79,6 +79,16 @@ typedef int32_t shv_status;
                                       (4n Gauss-Legendre nodes in z times 8n azimuths), on MFMA.
                                       n_squarings is unused.  Only sh_visibility_forward /
                                       sh_visibility_backward accept it; saved then holds F [N][P]. */
+#define SHV_FLAG_EXP_PRODUCT 8u    /* V without logarithms (this flag changes the result): the chain of
+                                      truncated SH products of Eq. 12, V = V'_1 * V'_2 * ... * V'_S,
+                                      left to right in sphere order, of the projected floored
+                                      blockers of Eq. 13 (e^-eps on each sphere's cone, 1 elsewhere;
+                                      a large eps gives Eq. 12's binary blockers).  Costs one Gaunt
+                                      product per pair forward and three in the adjoint (which runs
+                                      the chain again to record its states in the workspace,
+                                      S * N * P floats).  n_squarings is unused; no other flag may
+                                      be set.  Only sh_visibility_forward / sh_visibility_backward
+                                      accept it; nothing is saved and saved may be NULL. */
 typedef struct shv_params {
   int32_t n_bands;
   int32_t n_squarings;
@@ -98,7 +108,8 @@ const char* shv_last_error(void);
 
 /* Number of FP32 values the forward saves for the backward, per call:
  * (1 + k * N) * P  (the DC value c and E_0 .. E_{k-1} of the exponential);
- * with SHV_FLAG_EXP_QUADRATURE the larger of that and N * P (F itself). */
+ * with SHV_FLAG_EXP_QUADRATURE the larger of that and N * P (F itself); with
+ * SHV_FLAG_EXP_PRODUCT 0. */
 int64_t shv_saved_floats(int64_t P, const shv_params* prm);
 
 /* Workspace bytes that every entry point below needs for P receivers and S

@@ -8,6 +8,9 @@ or identities it must satisfy:
   * radiance_unshadowed: Eq. 1 (V = 1) by quadrature exact on the hemisphere;
   * exact_exponential: the SH projection of exp(F~), i.e. what the
     scaling/squaring/linear-approximation scheme stands in for;
+  * projected_visibility: the SH projection of the exact product of the
+    floored blockers (Eq. 13), the quantity that the log-space scheme's
+    exponential variants and the direct product chain of Eq. 12 approximate;
   * rotation_matrix: the SH rotation used for rotation-invariance checks,
     computed as an exact projection integral.
 """
@@ -64,6 +67,30 @@ def exact_exponential(F, n_bands, degree=120):
     Y = sh.real_sh(d, n_bands)
     vals = torch.exp(F @ Y.T)
     return (vals * w) @ Y
+
+
+def projected_visibility(points, spheres, n_bands, eps=3.0, degree=240):
+    """Proj_n[prod_i V'_i] for each receiver: the SH projection of the exact
+    product of the floored blockers of Eq. 13 (e^-eps on each sphere's cone, 1
+    elsewhere), evaluated pointwise in direction space.  This is the visibility
+    vector that every variant of step 5 approximates.  The integrand is
+    discontinuous, so a dense rule gives about 1e-3."""
+    d, w = sh.sphere_quadrature(degree)
+    Y = sh.real_sh(d, n_bands)
+    floor = math.exp(-eps)
+    out = []
+    for p in points:
+        vis = torch.ones(d.shape[0], dtype=DT)
+        for c in spheres:
+            v = c[:3] - p
+            dist = torch.linalg.norm(v)
+            if float(dist) == 0.0:
+                continue
+            s = min(float(c[3] / dist), 1.0)
+            cos_a = math.sqrt(max(0.0, 1.0 - s * s))
+            vis = vis * torch.where(d @ (v / dist) >= cos_a, floor, 1.0).to(DT)
+        out.append((w * vis) @ Y)
+    return torch.stack(out)
 
 
 def rotation_matrix(R, n_bands):

@@ -130,6 +130,43 @@ def sh_exponential_quadrature(F: torch.Tensor, n_bands: int, degree: int | None 
     return V
 
 
+def projected_blocker(points, spheres, n_bands: int, eps: float) -> torch.Tensor:
+    """SH vectors of the floored blocker functions V'_i (Eq. 13: e^-eps inside
+    the sphere's cone, 1 elsewhere), one per (receiver, sphere) -> [P, S, n^2].
+
+    V'_i = 1 - (1 - e^-eps) 1[w . s >= t]; by Funk-Hecke its coefficients
+    about s are (4 pi delta_l0 - (1 - e^-eps) 2 pi int_t^1 P_l) y_lm(s), the
+    constant 1 having coefficient sqrt(4 pi) on y_00.  A sphere centred on the
+    receiver blocks nothing (the constant 1)."""
+    s_hat, t, live = pair_geometry(points, spheres)
+    beta = -math.expm1(-eps)
+    lam = torch.stack([(4.0 * math.pi if l == 0 else 0.0) - beta * sh.funk_hecke_cap(t, l)
+                       for l in range(n_bands)], dim=-1)              # [P, S, n]
+    b = lam[..., band_of_index(n_bands)] * sh.real_sh(s_hat, n_bands)
+    one = torch.zeros(n_bands * n_bands, dtype=points.dtype)
+    one[0] = SQRT_4PI
+    return torch.where(live[..., None], b, one)
+
+
+def sh_direct_product(points, spheres, n_bands: int, eps: float, C: torch.Tensor) -> torch.Tensor:
+    """V = V'_1 * V'_2 * ... * V'_S (Eq. 12): the chain of truncated SH
+    products (Eqs. 6-7) of the projected blockers, taken left to right in
+    sphere order (truncated products are commutative but not associative, so
+    the order is part of the definition).  The chain starts from the constant
+    1, so no spheres give V = 1.  The blockers are the floored ones of Eq. 13,
+    the same functions whose logarithms the log-space scheme sums; a large eps
+    (e^-eps below FP32 resolution) gives Eq. 12's binary blockers."""
+    P = points.shape[0]
+    V = torch.zeros(P, n_bands * n_bands, dtype=points.dtype)
+    V[:, 0] = SQRT_4PI
+    if spheres.shape[0] == 0:
+        return V
+    b = projected_blocker(points, spheres, n_bands, eps)
+    for i in range(spheres.shape[0]):
+        V = sh.triple_product(V, b[:, i], C)
+    return V
+
+
 # ---------------------------------------------------------------- step 6
 
 def transfer(normals: torch.Tensor, n_bands: int) -> torch.Tensor:
@@ -162,11 +199,15 @@ def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 
     """Whole forward path on one chunk of receivers (FP64 tensors; FP32
     tensors give the oracle's FP32 twin, used only to measure how much error
     FP32 arithmetic alone introduces).  ``exp_mode`` "quadrature" takes the
-    exponential by sh_exponential_quadrature instead."""
+    exponential by sh_exponential_quadrature instead; "product" forms V by the
+    direct product chain of Eq. 12 (sh_direct_product) instead of the
+    log-space scheme."""
     C = sh.gaunt_tensor(n_bands).to(points.dtype)
     F = log_visibility(points, spheres, n_bands, eps)
     if exp_mode == "quadrature":
         V, c, Es = sh_exponential_quadrature(F, n_bands), F[..., 0] / SQRT_4PI, []
+    elif exp_mode == "product":
+        V, c, Es = sh_direct_product(points, spheres, n_bands, eps, C), F[..., 0] / SQRT_4PI, []
     else:
         V, c, Es = sh_exponential(F, C, n_squarings)
     H = transfer(normals, n_bands)

@@ -48,6 +48,7 @@ SHV_MAX_ENVMAP_COLS = 1048576
 SHV_FLAG_EXP_ONE_WAVE = 1
 SHV_FLAG_EXP_FOUR_WAVES = 2
 SHV_FLAG_EXP_QUADRATURE = 4
+SHV_FLAG_EXP_PRODUCT = 8
 
 
 class shv_params(ctypes.Structure):

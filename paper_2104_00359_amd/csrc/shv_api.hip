@@ -100,22 +100,25 @@ shv_status check_params(const shv_params* prm) {
   if (!(prm->eps == prm->eps) || prm->eps < 0.0f)
     return set_error(SHV_ERR_INVALID_ARG, "eps must be a non-negative number");
   const uint32_t layouts = SHV_FLAG_EXP_ONE_WAVE | SHV_FLAG_EXP_FOUR_WAVES;
-  const uint32_t known = layouts | SHV_FLAG_EXP_QUADRATURE;
+  const uint32_t known = layouts | SHV_FLAG_EXP_QUADRATURE | SHV_FLAG_EXP_PRODUCT;
   if (prm->flags & ~known) return set_error(SHV_ERR_INVALID_ARG, "unknown flags 0x%x", prm->flags);
   if ((prm->flags & layouts) == layouts)
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_ONE_WAVE and SHV_FLAG_EXP_FOUR_WAVES are exclusive");
   if ((prm->flags & SHV_FLAG_EXP_QUADRATURE) && (prm->flags & layouts))
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_QUADRATURE takes no layout flag");
+  if ((prm->flags & SHV_FLAG_EXP_PRODUCT) && (prm->flags & ~SHV_FLAG_EXP_PRODUCT))
+    return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_PRODUCT takes no other flag");
   return SHV_OK;
 }
 
 bool quadrature(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_QUADRATURE) != 0; }
+bool product(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_PRODUCT) != 0; }
 
 // Entry points built on the squaring exponential only.
 shv_status no_quadrature(const shv_params* prm) {
-  if (quadrature(prm))
-    return set_error(SHV_ERR_UNSUPPORTED,
-                     "SHV_FLAG_EXP_QUADRATURE is supported by sh_visibility_forward / sh_visibility_backward only");
+  if (quadrature(prm) || product(prm))
+    return set_error(SHV_ERR_UNSUPPORTED, "%s is supported by sh_visibility_forward / sh_visibility_backward only",
+                     quadrature(prm) ? "SHV_FLAG_EXP_QUADRATURE" : "SHV_FLAG_EXP_PRODUCT");
   return SHV_OK;
 }
 
@@ -165,6 +168,28 @@ size_t fwd_bytes(int64_t P, int64_t S, int nb, FwdWs* o = nullptr) {
 size_t quad_table_bytes(int nb) { return align_up((size_t)shv::quad_table_floats(nb) * 4); }
 size_t quad_bytes(int nb, int64_t P) {
   return quad_table_bytes(nb) + align_up((size_t)shv::quad_part_floats(nb, P) * 4);
+}
+
+// The direct product chain's adjoint: every step's input [S][N][P] and the
+// sphere-gradient partials, one row per (block, wave).
+struct ProdWs {
+  size_t states, gs;
+};
+size_t prod_bytes(int64_t P, int64_t S, int nb, ProdWs* o = nullptr) {
+  const size_t st = align_up((size_t)S * nb * nb * (size_t)P * 4);
+  const size_t gs = align_up((size_t)4 * shv::pair_blocks(P) * (size_t)S * 16);
+  if (o) {
+    o->states = 0;
+    o->gs = st;
+  }
+  return st + gs;
+}
+// The chain's saved states must stay addressable (below 2^50 bytes).
+shv_status check_product_size(int64_t P, int64_t S, int nb) {
+  if ((double)P * (double)S * nb * nb * 4.0 > 1125899906842624.0)
+    return set_error(SHV_ERR_INVALID_ARG, "P * S too large for SHV_FLAG_EXP_PRODUCT (P=%lld, S=%lld)", (long long)P,
+                     (long long)S);
+  return SHV_OK;
 }
 
 size_t shade_bytes(int64_t P, int nb, ShadeWs* o = nullptr) {
@@ -325,6 +350,7 @@ int64_t shv_saved_floats(int64_t P, const shv_params* prm) {
   if (!prm || prm->n_bands < 1 || prm->n_bands > SHV_MAX_BANDS_API || prm->n_squarings < 0 || P < 0) return 0;
   const int64_t N = (int64_t)prm->n_bands * prm->n_bands;
   const int64_t squaring = (1 + (int64_t)prm->n_squarings * N) * P;
+  if (prm->flags & SHV_FLAG_EXP_PRODUCT) return 0;
   return (prm->flags & SHV_FLAG_EXP_QUADRATURE) ? std::max(squaring, N * P) : squaring;
 }
 
@@ -340,6 +366,7 @@ size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm) {
     b = std::max(b, fwd_bytes(P, S, nb) + quad_bytes(nb, P));
     b = std::max(b, visbwd_bytes(P, S, nb) + quad_bytes(nb, P));
   }
+  if (prm->flags & SHV_FLAG_EXP_PRODUCT) b = std::max(b, prod_bytes(P, S, nb));
   return b;
 }
 
@@ -453,6 +480,13 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
     SHV_TRY(aligned16(spheres, "spheres"));
   }
   const int nb = prm->n_bands;
+  if (product(prm)) {
+    SHV_TRY(check_product_size(P, S, nb));
+    SHV_TRY(launch("prod_fwd", stream, [&] {
+      return shv::launch_prod_fwd(nb, points, P, spheres, (int)S, prm->eps, vis, nullptr, stream);
+    }));
+    return SHV_OK;
+  }
   const size_t base = fwd_bytes(P, S, nb);
   SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
   float* Fpart = (float*)ws;
@@ -733,12 +767,35 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   SHV_TRY(need(grad_vis, "grad_vis"));
   SHV_TRY(need(vis, "vis"));
   SHV_TRY(need(points, "points"));
-  SHV_TRY(need(saved, "saved"));
+  if (!product(prm)) SHV_TRY(need(saved, "saved"));
   if (S > 0) {
     SHV_TRY(need(spheres, "spheres"));
     SHV_TRY(aligned16(spheres, "spheres"));
   }
   const int nb = prm->n_bands;
+  if (product(prm)) {
+    // The chain is run again, recording each step's input, then reversed.
+    SHV_TRY(check_product_size(P, S, nb));
+    ProdWs L;
+    SHV_TRY(check_ws(ws, ws_bytes, prod_bytes(P, S, nb, &L)));
+    float* states = (float*)((char*)ws + L.states);
+    float* gs = (float*)((char*)ws + L.gs);
+    if (S > 0) {
+      SHV_TRY(launch("prod_fwd_states", stream, [&] {
+        return shv::launch_prod_fwd(nb, points, P, spheres, (int)S, prm->eps, nullptr, states, stream);
+      }));
+    }
+    SHV_TRY(launch("prod_bwd", stream, [&] {
+      return shv::launch_prod_bwd(nb, grad_vis, states, points, P, spheres, (int)S, prm->eps, grad_points, gs,
+                                  stream);
+    }));
+    if (grad_spheres && S > 0) {
+      SHV_TRY(launch("reduce_spheres", stream, [&] {
+        return shv::launch_reduce_rows(gs, (int)(4 * shv::pair_blocks(P)), (int)(4 * S), grad_spheres, stream);
+      }));
+    }
+    return SHV_OK;
+  }
   VisBwdWs L;
   const size_t base = visbwd_bytes(P, S, nb, &L);
   SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));

@@ -267,6 +267,20 @@ hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const 
 #undef C
 }
 
+hipError_t launch_prod_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, float eps, float* vis,
+                           float* states, hipStream_t st) {
+#define C(N) prod_fwd_nb<N>(pts, P, sph, S, eps, vis, states, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_prod_bwd(int nb, const float* gvis, const float* states, const float* pts, int64_t P,
+                           const float* sph, int S, float eps, float* gpts, float* gs_part, hipStream_t st) {
+#define C(N) prod_bwd_nb<N>(gvis, states, pts, P, sph, S, eps, gpts, gs_part, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
 hipError_t launch_shade_ch_fwd(int nb, const float* vis, const float* nrm, const float* alb, const float* M,
                                int channels, int64_t P, float* rad, hipStream_t st) {
 #define C(N) shade_ch_fwd_nb<N>(vis, nrm, alb, M, channels, P, rad, st)

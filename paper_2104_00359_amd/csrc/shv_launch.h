@@ -59,6 +59,12 @@ hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t 
                                float* saved, float* table, float* part, hipStream_t st);
 hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
                                float* W, float* table, float* part, hipStream_t st);
+// The direct product chain (SHV_FLAG_EXP_PRODUCT).  states, when not NULL, receives each step's
+// input [S][N][P] (the adjoint's input); vis may be NULL.  gs_part is [4 pair_blocks(P)][S] float4.
+hipError_t launch_prod_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, float eps, float* vis,
+                           float* states, hipStream_t st);
+hipError_t launch_prod_bwd(int nb, const float* gvis, const float* states, const float* pts, int64_t P,
+                           const float* sph, int S, float eps, float* gpts, float* gs_part, hipStream_t st);
 hipError_t launch_pair_bwd(int nb, const float* W, const float* pts, int64_t P, const float* sph, int S,
                            Split sp, float* gp_part, float* gs_part, hipStream_t st);
 // Zero n floats with a plain kernel (safe inside captured graphs).
@@ -114,6 +120,12 @@ hipError_t exp_quad_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps
 template <int NB>
 hipError_t exp_quad_bwd_nb(const float* gV, const float* vis, const float* saved, int64_t P, float eps, float* W,
                            float* table, float* part, hipStream_t st);
+template <int NB>
+hipError_t prod_fwd_nb(const float* pts, int64_t P, const float* sph, int S, float eps, float* vis, float* states,
+                       hipStream_t st);
+template <int NB>
+hipError_t prod_bwd_nb(const float* gvis, const float* states, const float* pts, int64_t P, const float* sph, int S,
+                       float eps, float* gpts, float* gs_part, hipStream_t st);
 template <int NB>
 hipError_t batch_pair_fwd_nb(const void* table, int64_t blocks, hipStream_t st);
 template <int NB>

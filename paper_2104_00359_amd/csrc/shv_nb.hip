@@ -5,11 +5,12 @@
 
 #include "shv_exp_impl.h"
 #include "shv_pair_impl.h"
+#include "shv_prod_impl.h"
 #include "shv_quad_impl.h"
 #include "shv_shade_impl.h"
 
 #if !defined(SHV_NB) || !defined(SHV_PART)
-#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..6>"
+#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..7>"
 #endif
 
 namespace shv {
@@ -49,6 +50,10 @@ template hipError_t exp_quad_fwd_nb<SHV_NB>(const float*, int, int64_t, float, f
                                             hipStream_t);
 template hipError_t exp_quad_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, float, float*, float*,
                                             float*, hipStream_t);
+#elif SHV_PART == 7
+template hipError_t prod_fwd_nb<SHV_NB>(const float*, int64_t, const float*, int, float, float*, float*, hipStream_t);
+template hipError_t prod_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, const float*, int, float,
+                                        float*, float*, hipStream_t);
 #endif
 
 }  // namespace shv

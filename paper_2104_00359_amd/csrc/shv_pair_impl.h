@@ -155,6 +155,66 @@ struct PairBwdShared {
   float gpx_w[SHV_WAVES_PER_BLOCK - 1][3][64];
 };
 
+// Adjoint of one pair's term for the weights W_lm = dLoss/dF'_lm (and
+// Wz_lm = RHO[l][|m|] W_lm): the cotangent of v = c - x (gvx, gvy, gvz) and
+// of the radius (gr).
+template <int NB>
+__device__ __forceinline__ void pair_adjoint(const PairGeom& G, const float (&W)[NB * NB], const float (&Wz)[NB * NB],
+                                             float& gvx, float& gvy, float& gvz, float& gr) {
+  float R[NB + 1], g[NB], C[NB], Sn[NB];
+  legendre_resid<NB>(G.t, G.u, R);
+  cap_zonal<NB>(G.u, R, g);
+  cs_powers<NB>(G.x, G.y, C, Sn);
+  float Gx = 0.0f, Gy = 0.0f, Gz = 0.0f, Gt = 0.0f;
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    float Xc = 0.0f, Xs = 0.0f, Tc = 0.0f, Ts = 0.0f, Zc = 0.0f, Zs = 0.0f;
+    float r2 = 0.0f, r1 = 1.0f;
+#pragma unroll
+    for (int l = m; l < NB; ++l) {
+      float r;
+      if (l == m) r = 1.0f;
+      else if (l == m + 1) r = G.z;
+      else r = fmaf(G.z, r1, SHV_GAMMA[l][m] * r2);
+      if (l > m) { r2 = r1; r1 = r; }
+      const float v = g[l] * r;   // value weight of r_l^m
+      const float w = fmaf(-R[l], r, r);  // P_l(t) r: t-derivative weight (times 1 / 2 pi)
+      if (m == 0) {
+        Tc = fmaf(W[idx(l, 0)], w, Tc);
+      } else {
+        Xc = fmaf(W[idx(l, m)], v, Xc);
+        Xs = fmaf(W[idx(l, -m)], v, Xs);
+        Tc = fmaf(W[idx(l, m)], w, Tc);
+        Ts = fmaf(W[idx(l, -m)], w, Ts);
+        Zc = fmaf(Wz[idx(l, m - 1)], v, Zc);
+        if (m - 1 >= 1) Zs = fmaf(Wz[idx(l, -(m - 1))], v, Zs);
+      }
+    }
+    Gt = fmaf(Tc, C[m], fmaf(Ts, Sn[m], Gt));
+    if (m >= 1) {
+      const float fm = (float)m;
+      Gz = fmaf(Zc, C[m - 1], fmaf(Zs, Sn[m - 1], Gz));
+      Gx = fmaf(fm, fmaf(Xc, C[m - 1], Xs * Sn[m - 1]), Gx);
+      Gy = fmaf(fm, fmaf(Xs, C[m - 1], -Xc * Sn[m - 1]), Gy);
+    }
+  }
+  Gt *= SHV_TWO_PI;
+  // chain rule: s = v/|v| (tangential part / |v|), t(|v|, r)
+  const float sd = fmaf(Gx, G.x, fmaf(Gy, G.y, Gz * G.z));
+  gvx = (Gx - sd * G.x) * G.inv;
+  gvy = (Gy - sd * G.y) * G.inv;
+  gvz = (Gz - sd * G.z) * G.inv;
+  gr = 0.0f;
+  if (G.t > 0.0f) {
+    const float k = Gt * G.rs / G.t * G.inv;  // dLoss/dt * (-dt/dr)
+    const float kd = k * G.rs;                // dLoss/dt * dt/d|v|
+    gvx = fmaf(kd, G.x, gvx);
+    gvy = fmaf(kd, G.y, gvy);
+    gvz = fmaf(kd, G.z, gvz);
+    gr = -k;
+  }
+}
+
 template <int NB>
 __device__ __forceinline__ void pair_bwd_item(const float* __restrict__ Wg, const float* __restrict__ pts, int64_t P,
                                               const float4* __restrict__ sph, int S, int chunk,
@@ -189,58 +249,8 @@ __device__ __forceinline__ void pair_bwd_item(const float* __restrict__ Wg, cons
   float gpx = 0.0f, gpy = 0.0f, gpz = 0.0f;
   for (int s = s0 + wave; s < s1; s += SHV_WAVES_PER_BLOCK) {
     const PairGeom G = pair_geom(px, py, pz, sph[s]);
-    float R[NB + 1], g[NB], C[NB], Sn[NB];
-    legendre_resid<NB>(G.t, G.u, R);
-    cap_zonal<NB>(G.u, R, g);
-    cs_powers<NB>(G.x, G.y, C, Sn);
-    float Gx = 0.0f, Gy = 0.0f, Gz = 0.0f, Gt = 0.0f;
-#pragma unroll
-    for (int m = 0; m < NB; ++m) {
-      float Xc = 0.0f, Xs = 0.0f, Tc = 0.0f, Ts = 0.0f, Zc = 0.0f, Zs = 0.0f;
-      float r2 = 0.0f, r1 = 1.0f;
-#pragma unroll
-      for (int l = m; l < NB; ++l) {
-        float r;
-        if (l == m) r = 1.0f;
-        else if (l == m + 1) r = G.z;
-        else r = fmaf(G.z, r1, SHV_GAMMA[l][m] * r2);
-        if (l > m) { r2 = r1; r1 = r; }
-        const float v = g[l] * r;   // value weight of r_l^m
-        const float w = fmaf(-R[l], r, r);  // P_l(t) r: t-derivative weight (times 1 / 2 pi)
-        if (m == 0) {
-          Tc = fmaf(W[idx(l, 0)], w, Tc);
-        } else {
-          Xc = fmaf(W[idx(l, m)], v, Xc);
-          Xs = fmaf(W[idx(l, -m)], v, Xs);
-          Tc = fmaf(W[idx(l, m)], w, Tc);
-          Ts = fmaf(W[idx(l, -m)], w, Ts);
-          Zc = fmaf(Wz[idx(l, m - 1)], v, Zc);
-          if (m - 1 >= 1) Zs = fmaf(Wz[idx(l, -(m - 1))], v, Zs);
-        }
-      }
-      Gt = fmaf(Tc, C[m], fmaf(Ts, Sn[m], Gt));
-      if (m >= 1) {
-        const float fm = (float)m;
-        Gz = fmaf(Zc, C[m - 1], fmaf(Zs, Sn[m - 1], Gz));
-        Gx = fmaf(fm, fmaf(Xc, C[m - 1], Xs * Sn[m - 1]), Gx);
-        Gy = fmaf(fm, fmaf(Xs, C[m - 1], -Xc * Sn[m - 1]), Gy);
-      }
-    }
-    Gt *= SHV_TWO_PI;
-    // chain rule: s = v/|v| (tangential part / |v|), t(|v|, r)
-    const float sd = fmaf(Gx, G.x, fmaf(Gy, G.y, Gz * G.z));
-    float gvx = (Gx - sd * G.x) * G.inv;
-    float gvy = (Gy - sd * G.y) * G.inv;
-    float gvz = (Gz - sd * G.z) * G.inv;
-    float gr = 0.0f;
-    if (G.t > 0.0f) {
-      const float k = Gt * G.rs / G.t * G.inv;  // dLoss/dt * (-dt/dr)
-      const float kd = k * G.rs;                // dLoss/dt * dt/d|v|
-      gvx = fmaf(kd, G.x, gvx);
-      gvy = fmaf(kd, G.y, gvy);
-      gvz = fmaf(kd, G.z, gvz);
-      gr = -k;
-    }
+    float gvx, gvy, gvz, gr;
+    pair_adjoint<NB>(G, W, Wz, gvx, gvy, gvz, gr);
     gpx -= gvx;
     gpy -= gvy;
     gpz -= gvz;

@@ -137,6 +137,23 @@ def exp_quad_bwd_flops(n: int) -> int:
     return 3 * (2 * N * Q) + 3 * Q
 
 
+def prod_fwd_flops(n: int) -> int:
+    """Per (receiver, sphere) step of the direct product chain: the pair's
+    blocker vector (the pair forward's basis work plus one LAMBDA multiply per
+    coefficient), one sparse product V * h (the generated product, which
+    returns 2 V * h) and the update V + beta/2 (2 V * h)."""
+    N = n * n
+    return pair_fwd_flops(n) + N + square_adj_flops(n) + 2 * N
+
+
+def prod_bwd_flops(n: int) -> int:
+    """Per step of the chain's adjoint: the blocker vector again, the two
+    sparse products Vbar * V_in and Vbar * h with their scale and update, the
+    pair weights W and RHO W, and the pair adjoint."""
+    N = n * n
+    return (pair_fwd_flops(n) + N) + 2 * square_adj_flops(n) + 3 * N + 2 * N + pair_bwd_flops(n)
+
+
 def envmap_pixel_flops(n: int) -> int:
     """One map pixel: sin and cos of its azimuth, the direction (3), the
     polynomial SH basis (powers of x + i y, three-term recurrences in z, one
@@ -170,6 +187,10 @@ def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pi
         return exp_quad_fwd_flops(n) * P, P
     if name == "exp_quad_bwd":
         return exp_quad_bwd_flops(n) * P, P
+    if name in ("prod_fwd", "prod_fwd_states"):
+        return prod_fwd_flops(n) * P * S, P * S
+    if name == "prod_bwd":
+        return prod_bwd_flops(n) * P * S, P * S
     if name == "pair_fwd":
         return pair_fwd_flops(n) * P * S, P * S
     if name == "pair_bwd":

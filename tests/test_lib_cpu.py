@@ -70,7 +70,7 @@ def test_invalid_parameters_rejected_before_any_device_call(L):
     assert f(None, -5, None, 0, ctypes.byref(neg), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
     bad_eps = L.params(4, -1.0)
     assert f(None, 10, None, 0, ctypes.byref(bad_eps), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
-    for bad_flags in (8, 3, 5, 6):  # unknown bit; both layouts; quadrature with a layout flag
+    for bad_flags in (16, 3, 5, 6, 9, 12):  # unknown bit; both layouts; quadrature or product with another flag
         flags = L.shv_params(4, 4, 3.0, bad_flags)
         assert f(None, 10, None, 0, ctypes.byref(flags), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
     g = L.raw("sh_shade")
