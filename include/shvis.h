@@ -58,6 +58,7 @@ typedef int32_t shv_status;
 
 #define SHV_MAX_BANDS_API 8
 #define SHV_MAX_SQUARINGS 12
+#define SHV_MAX_TAYLOR_ORDER 8   /* K of SHV_FLAG_EXP_TAYLOR */
 #define SHV_RANGE_ALIGN 256   /* receiver-range granularity of batched calls */
 #define SHV_MAX_CHANNELS 4    /* colour channels of one multi-channel shading call */
 #define SHV_MAX_ENVMAP_ROWS 65536     /* environment-map rows (polar samples) */
@@ -89,6 +90,16 @@ typedef int32_t shv_status;
                                       S * N * P floats).  n_squarings is unused; no other flag may
                                       be set.  Only sh_visibility_forward / sh_visibility_backward
                                       accept it; nothing is saved and saved may be NULL. */
+#define SHV_FLAG_EXP_TAYLOR 16u    /* a different exponential (this flag changes the result): the
+                                      scaling-and-squaring scheme with the linear approximation
+                                      replaced by the Taylor series of exp truncated after the
+                                      term of degree K, E_0 = sum_{j <= K} G^{*j} / j! with
+                                      truncated products, then the k squarings.  K (1 ..
+                                      SHV_MAX_TAYLOR_ORDER) goes into the flags with
+                                      SHV_FLAG_EXP_TAYLOR_ORDER(K); no other flag may be set.  Only
+                                      sh_visibility_forward / sh_visibility_backward accept it;
+                                      saved then holds (1 + (k + K) N) * P values. */
+#define SHV_FLAG_EXP_TAYLOR_ORDER(K) (((uint32_t)(K) & 15u) << 8)
 typedef struct shv_params {
   int32_t n_bands;
   int32_t n_squarings;
@@ -109,7 +120,7 @@ const char* shv_last_error(void);
 /* Number of FP32 values the forward saves for the backward, per call:
  * (1 + k * N) * P  (the DC value c and E_0 .. E_{k-1} of the exponential);
  * with SHV_FLAG_EXP_QUADRATURE the larger of that and N * P (F itself); with
- * SHV_FLAG_EXP_PRODUCT 0. */
+ * SHV_FLAG_EXP_PRODUCT 0; with SHV_FLAG_EXP_TAYLOR (1 + (k + K) N) * P. */
 int64_t shv_saved_floats(int64_t P, const shv_params* prm);
 
 /* Workspace bytes that every entry point below needs for P receivers and S

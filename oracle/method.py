@@ -114,6 +114,29 @@ def sh_exponential(F: torch.Tensor, C: torch.Tensor, n_squarings: int):
     return V, c, Es
 
 
+def sh_exponential_taylor(F: torch.Tensor, C: torch.Tensor, order: int, n_squarings: int):
+    """The scaling-and-squaring exponential with the linear approximation
+    replaced by the Taylor series of exp truncated after the term of degree
+    ``order`` (K): E_0 = sum_{j <= K} G^{*j} / j!, each power the truncated
+    product of the previous one with G (G^{*0} the constant 1), then the same
+    k truncated squarings.  The DC term is split off exactly and the rest is
+    scaled by 2^-k, as in sh_exponential; K = 1 is the linear approximation
+    with a = b = 1."""
+    N = F.shape[-1]
+    c = F[..., 0] / SQRT_4PI
+    G = torch.cat([torch.zeros_like(F[..., :1]), F[..., 1:]], dim=-1) * (2.0 ** -n_squarings)
+    one = torch.zeros(N, dtype=F.dtype)
+    one[0] = SQRT_4PI
+    E = one.expand_as(F).clone()
+    power = None
+    for j in range(1, order + 1):
+        power = G if j == 1 else sh.triple_product(power, G, C)
+        E = E + power / math.factorial(j)
+    for _ in range(n_squarings):
+        E = sh.triple_product(E, E, C)
+    return torch.exp(c)[..., None] * E
+
+
 def sh_exponential_quadrature(F: torch.Tensor, n_bands: int, degree: int | None = None):
     """The exponential as the projection Proj_n[exp(F~)] of the pointwise
     exponential (the function-space quantity the scaling and squaring scheme
@@ -199,15 +222,17 @@ def forward(points, normals, albedo, spheres, light, n_bands: int, eps: float = 
     """Whole forward path on one chunk of receivers (FP64 tensors; FP32
     tensors give the oracle's FP32 twin, used only to measure how much error
     FP32 arithmetic alone introduces).  ``exp_mode`` "quadrature" takes the
-    exponential by sh_exponential_quadrature instead; "product" forms V by the
-    direct product chain of Eq. 12 (sh_direct_product) instead of the
-    log-space scheme."""
+    exponential by sh_exponential_quadrature instead; "taylorK" (K = 1..8) by
+    sh_exponential_taylor of order K; "product" forms V by the direct product
+    chain of Eq. 12 (sh_direct_product) instead of the log-space scheme."""
     C = sh.gaunt_tensor(n_bands).to(points.dtype)
     F = log_visibility(points, spheres, n_bands, eps)
     if exp_mode == "quadrature":
         V, c, Es = sh_exponential_quadrature(F, n_bands), F[..., 0] / SQRT_4PI, []
     elif exp_mode == "product":
         V, c, Es = sh_direct_product(points, spheres, n_bands, eps, C), F[..., 0] / SQRT_4PI, []
+    elif exp_mode.startswith("taylor"):
+        V, c, Es = sh_exponential_taylor(F, C, int(exp_mode[6:]), n_squarings), F[..., 0] / SQRT_4PI, []
     else:
         V, c, Es = sh_exponential(F, C, n_squarings)
     H = transfer(normals, n_bands)

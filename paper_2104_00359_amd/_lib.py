@@ -49,6 +49,13 @@ SHV_FLAG_EXP_ONE_WAVE = 1
 SHV_FLAG_EXP_FOUR_WAVES = 2
 SHV_FLAG_EXP_QUADRATURE = 4
 SHV_FLAG_EXP_PRODUCT = 8
+SHV_FLAG_EXP_TAYLOR = 16
+SHV_MAX_TAYLOR_ORDER = 8
+
+
+def SHV_FLAG_EXP_TAYLOR_ORDER(K):
+    """Bits that carry the Taylor order K of SHV_FLAG_EXP_TAYLOR."""
+    return (int(K) & 15) << 8
 
 
 class shv_params(ctypes.Structure):

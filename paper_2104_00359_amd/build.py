@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libshvis.so")
 # (source, extra flags, object name): the band-count-dependent kernels are
 # compiled once per band count.
 SOURCES = [("shv_nb.hip", [f"-DSHV_NB={n}", f"-DSHV_PART={part}"], f"shv_nb{n}_p{part}.o")
-           for n in range(8, 0, -1) for part in (3, 7, 2, 5, 4, 6, 1, 0)] + [
+           for n in range(8, 0, -1) for part in (3, 7, 8, 2, 5, 4, 6, 1, 0)] + [
     ("shv_api.hip", [], "shv_api.o"), ("shv_common.hip", [], "shv_common.o"), ("shv_deform.hip", [], "shv_deform.o")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -100,7 +100,8 @@ shv_status check_params(const shv_params* prm) {
   if (!(prm->eps == prm->eps) || prm->eps < 0.0f)
     return set_error(SHV_ERR_INVALID_ARG, "eps must be a non-negative number");
   const uint32_t layouts = SHV_FLAG_EXP_ONE_WAVE | SHV_FLAG_EXP_FOUR_WAVES;
-  const uint32_t known = layouts | SHV_FLAG_EXP_QUADRATURE | SHV_FLAG_EXP_PRODUCT;
+  const uint32_t known = layouts | SHV_FLAG_EXP_QUADRATURE | SHV_FLAG_EXP_PRODUCT | SHV_FLAG_EXP_TAYLOR |
+                         SHV_FLAG_EXP_TAYLOR_ORDER(15);
   if (prm->flags & ~known) return set_error(SHV_ERR_INVALID_ARG, "unknown flags 0x%x", prm->flags);
   if ((prm->flags & layouts) == layouts)
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_ONE_WAVE and SHV_FLAG_EXP_FOUR_WAVES are exclusive");
@@ -108,17 +109,30 @@ shv_status check_params(const shv_params* prm) {
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_QUADRATURE takes no layout flag");
   if ((prm->flags & SHV_FLAG_EXP_PRODUCT) && (prm->flags & ~SHV_FLAG_EXP_PRODUCT))
     return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_PRODUCT takes no other flag");
+  const uint32_t order = (prm->flags >> 8) & 15u;
+  if (prm->flags & SHV_FLAG_EXP_TAYLOR) {
+    if (prm->flags & ~(SHV_FLAG_EXP_TAYLOR | SHV_FLAG_EXP_TAYLOR_ORDER(15)))
+      return set_error(SHV_ERR_INVALID_ARG, "SHV_FLAG_EXP_TAYLOR takes no other flag");
+    if (order < 1 || order > SHV_MAX_TAYLOR_ORDER)
+      return set_error(SHV_ERR_INVALID_ARG, "Taylor order %u outside [1, %d]", order, SHV_MAX_TAYLOR_ORDER);
+  } else if (order) {
+    return set_error(SHV_ERR_INVALID_ARG, "a Taylor order is set without SHV_FLAG_EXP_TAYLOR");
+  }
   return SHV_OK;
 }
 
 bool quadrature(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_QUADRATURE) != 0; }
 bool product(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_PRODUCT) != 0; }
+bool taylor(const shv_params* prm) { return (prm->flags & SHV_FLAG_EXP_TAYLOR) != 0; }
+int taylor_order(const shv_params* prm) { return (int)((prm->flags >> 8) & 15u); }
 
-// Entry points built on the squaring exponential only.
+// Entry points built on the squaring exponential with its linear
+// approximation only.
 shv_status no_quadrature(const shv_params* prm) {
-  if (quadrature(prm) || product(prm))
+  if (quadrature(prm) || product(prm) || taylor(prm))
     return set_error(SHV_ERR_UNSUPPORTED, "%s is supported by sh_visibility_forward / sh_visibility_backward only",
-                     quadrature(prm) ? "SHV_FLAG_EXP_QUADRATURE" : "SHV_FLAG_EXP_PRODUCT");
+                     quadrature(prm) ? "SHV_FLAG_EXP_QUADRATURE"
+                                     : (product(prm) ? "SHV_FLAG_EXP_PRODUCT" : "SHV_FLAG_EXP_TAYLOR"));
   return SHV_OK;
 }
 
@@ -351,6 +365,7 @@ int64_t shv_saved_floats(int64_t P, const shv_params* prm) {
   const int64_t N = (int64_t)prm->n_bands * prm->n_bands;
   const int64_t squaring = (1 + (int64_t)prm->n_squarings * N) * P;
   if (prm->flags & SHV_FLAG_EXP_PRODUCT) return 0;
+  if (prm->flags & SHV_FLAG_EXP_TAYLOR) return (1 + ((int64_t)prm->n_squarings + ((prm->flags >> 8) & 15u)) * N) * P;
   return (prm->flags & SHV_FLAG_EXP_QUADRATURE) ? std::max(squaring, N * P) : squaring;
 }
 
@@ -498,6 +513,13 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
     SHV_TRY(launch("exp_quad_fwd", stream, [&] {
       return shv::launch_exp_quad_fwd(nb, Fpart, sp.nchunks, P, prm->eps, vis, saved, (float*)((char*)ws + base),
                                       (float*)((char*)ws + base + quad_table_bytes(nb)), stream);
+    }));
+    return SHV_OK;
+  }
+  if (taylor(prm)) {
+    SHV_TRY(launch("exp_taylor_fwd", stream, [&] {
+      return shv::launch_exp_taylor_fwd(nb, Fpart, sp.nchunks, P, prm->eps, prm->n_squarings, taylor_order(prm), vis,
+                                        saved, stream);
     }));
     return SHV_OK;
   }
@@ -807,6 +829,11 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
     SHV_TRY(launch("exp_quad_bwd", stream, [&] {
       return shv::launch_exp_quad_bwd(nb, grad_vis, vis, saved, P, prm->eps, W, (float*)((char*)ws + base),
                                       (float*)((char*)ws + base + quad_table_bytes(nb)), stream);
+    }));
+  } else if (taylor(prm)) {
+    SHV_TRY(launch("exp_taylor_bwd", stream, [&] {
+      return shv::launch_exp_taylor_bwd(nb, grad_vis, vis, saved, P, prm->eps, prm->n_squarings, taylor_order(prm), W,
+                                        stream);
     }));
   } else {
     SHV_TRY(launch("exp_bwd", stream, [&] {

@@ -267,6 +267,20 @@ hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const 
 #undef C
 }
 
+hipError_t launch_exp_taylor_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k, int K,
+                                 float* vis, float* saved, hipStream_t st) {
+#define C(N) exp_taylor_fwd_nb<N>(Fpart, nchunks, P, eps, k, K, vis, saved, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
+hipError_t launch_exp_taylor_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
+                                 int k, int K, float* W, hipStream_t st) {
+#define C(N) exp_taylor_bwd_nb<N>(gV, vis, saved, P, eps, k, K, W, st)
+  SHV_NB_SWITCH(nb, C)
+#undef C
+}
+
 hipError_t launch_prod_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, float eps, float* vis,
                            float* states, hipStream_t st) {
 #define C(N) prod_fwd_nb<N>(pts, P, sph, S, eps, vis, states, st)

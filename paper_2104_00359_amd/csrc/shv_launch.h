@@ -59,6 +59,12 @@ hipError_t launch_exp_quad_fwd(int nb, const float* Fpart, int nchunks, int64_t 
                                float* saved, float* table, float* part, hipStream_t st);
 hipError_t launch_exp_quad_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
                                float* W, float* table, float* part, hipStream_t st);
+// The exponential with a Taylor series of order K in place of the linear approximation
+// (SHV_FLAG_EXP_TAYLOR); saved holds (1 + (k + K) N) rows of P.
+hipError_t launch_exp_taylor_fwd(int nb, const float* Fpart, int nchunks, int64_t P, float eps, int k, int K,
+                                 float* vis, float* saved, hipStream_t st);
+hipError_t launch_exp_taylor_bwd(int nb, const float* gV, const float* vis, const float* saved, int64_t P, float eps,
+                                 int k, int K, float* W, hipStream_t st);
 // The direct product chain (SHV_FLAG_EXP_PRODUCT).  states, when not NULL, receives each step's
 // input [S][N][P] (the adjoint's input); vis may be NULL.  gs_part is [4 pair_blocks(P)][S] float4.
 hipError_t launch_prod_fwd(int nb, const float* pts, int64_t P, const float* sph, int S, float eps, float* vis,
@@ -120,6 +126,12 @@ hipError_t exp_quad_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps
 template <int NB>
 hipError_t exp_quad_bwd_nb(const float* gV, const float* vis, const float* saved, int64_t P, float eps, float* W,
                            float* table, float* part, hipStream_t st);
+template <int NB>
+hipError_t exp_taylor_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, int k, int K, float* vis,
+                             float* saved, hipStream_t st);
+template <int NB>
+hipError_t exp_taylor_bwd_nb(const float* gIn, const float* vis, const float* saved, int64_t P, float eps, int k,
+                             int K, float* W, hipStream_t st);
 template <int NB>
 hipError_t prod_fwd_nb(const float* pts, int64_t P, const float* sph, int S, float eps, float* vis, float* states,
                        hipStream_t st);

@@ -8,9 +8,10 @@
 #include "shv_prod_impl.h"
 #include "shv_quad_impl.h"
 #include "shv_shade_impl.h"
+#include "shv_taylor_impl.h"
 
 #if !defined(SHV_NB) || !defined(SHV_PART)
-#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..7>"
+#error "compile with -DSHV_NB=<1..8> -DSHV_PART=<0..8>"
 #endif
 
 namespace shv {
@@ -54,6 +55,11 @@ template hipError_t exp_quad_bwd_nb<SHV_NB>(const float*, const float*, const fl
 template hipError_t prod_fwd_nb<SHV_NB>(const float*, int64_t, const float*, int, float, float*, float*, hipStream_t);
 template hipError_t prod_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, const float*, int, float,
                                         float*, float*, hipStream_t);
+#elif SHV_PART == 8
+template hipError_t exp_taylor_fwd_nb<SHV_NB>(const float*, int, int64_t, float, int, int, float*, float*,
+                                              hipStream_t);
+template hipError_t exp_taylor_bwd_nb<SHV_NB>(const float*, const float*, const float*, int64_t, float, int, int,
+                                              float*, hipStream_t);
 #endif
 
 }  // namespace shv

@@ -1,0 +1,94 @@
+"""The Taylor-series variant of the exponential (SHV_FLAG_EXP_TAYLOR with order
+K) against the FP64 oracle's, and its accuracy against the projected
+pointwise exponential next to the linear approximation's.
+
+Tolerances: V ||dV|| / ||V|| <= 1e-5 and B max |dB| / max |B| <= 1e-5 per
+scene; gradients ||d grad|| / ||grad|| <= 1e-4 per parameter group, as for the
+main exponential."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from gpu_helpers import lib, rel_l2, rel_max, run_hip
+from oracle import brute, method
+
+pytestmark = pytest.mark.gpu
+
+
+def _flags(K):
+    L = lib()
+    return L.SHV_FLAG_EXP_TAYLOR | L.SHV_FLAG_EXP_TAYLOR_ORDER(K)
+
+
+def _oracle(sc, K, k, grad_B=None, idx=None):
+    if grad_B is None:
+        o = method.run_forward(sc, n_squarings=k, idx=idx, exp_mode=f"taylor{K}")
+        return {"V": o["V"].numpy(), "B": o["B"].numpy()}
+    o = method.run_forward_backward(sc, grad_B, n_squarings=k, idx=idx, exp_mode=f"taylor{K}")
+    return {key: v.detach().numpy() for key, v in o.items()}
+
+
+@pytest.mark.parametrize("n,K,k", [(1, 2, 4), (2, 1, 4), (3, 3, 2), (4, 2, 4), (5, 8, 4), (6, 4, 3), (8, 1, 4),
+                                   (8, 3, 4), (8, 4, 2), (8, 2, 0)])
+def test_taylor_forward_and_gradients(n, K, k):
+    """777 receivers (12 blocks of 64 and a ragged tail) and 37 spheres."""
+    sc = scenegen.scene_random_shell(90 + n, 777, 37, n)
+    w = sc["grad_radiance"]
+    h = run_hip(sc, w, k=k, flags=_flags(K))
+    o = _oracle(sc, K, k, w)
+    ev, eb = rel_l2(h["V"], o["V"]), rel_max(h["B"], o["B"])
+    print(f"V {ev:.2e}  B {eb:.2e}")
+    assert ev <= 1e-5 and eb <= 1e-5
+    for key in ("grad_points", "grad_normals", "grad_albedo", "grad_light", "grad_spheres"):
+        e = rel_l2(h[key], o[key])
+        print(f"{key} {e:.2e}")
+        assert e <= 1e-4, key
+
+
+def test_taylor_body_scene_sampled():
+    """The body-like scene at full size: outputs on 256 sampled receivers,
+    sphere gradients from a cotangent nonzero only there (K = 2, k = 4)."""
+    sc = scenegen.scene_body()
+    P = sc["points"].shape[0]
+    idx = np.sort(np.random.default_rng(3).choice(P, 256, replace=False))
+    w = np.zeros(P, np.float32)
+    w[idx] = sc["grad_radiance"][idx]
+    h = run_hip(sc, w, k=4, flags=_flags(2))
+    o = _oracle(sc, 2, 4, w[idx], idx=idx)
+    ev, eb = rel_l2(h["V"][idx], o["V"]), rel_max(h["B"][idx], o["B"])
+    print(f"V {ev:.2e}  B {eb:.2e}")
+    assert ev <= 1e-5 and eb <= 1e-5
+    for key in ("grad_points", "grad_normals"):
+        assert rel_l2(h[key][idx], o[key]) <= 1e-4, key
+    for key in ("grad_light", "grad_spheres"):
+        assert rel_l2(h[key], o[key]) <= 1e-4, key
+
+
+def test_taylor_order_study_against_the_projected_exponential():
+    """Shell scene, k = 4: against Proj_n[exp(F~)] (dense quadrature), raising
+    the order K beyond 2 changes nothing (the k truncated squarings set the
+    error floor), and the linear approximation with its fitted coefficient is
+    at least as close as any order."""
+    sc = scenegen.scene_random_shell(81, 100, 37, 8)
+    T = method.scene_tensors(sc)
+    F = method.log_visibility(T["points"], T["spheres"], 8, 3.0)
+    ref = brute.exact_exponential(F, 8, degree=160).numpy()
+    errs = {K: rel_l2(run_hip(sc, flags=_flags(K))["V"], ref) for K in (1, 2, 3, 4)}
+    ol = rel_l2(run_hip(sc)["V"], ref)
+    print("OL %.3e  " % ol + "  ".join(f"K{K} {e:.3e}" for K, e in errs.items()))
+    assert errs[2] < errs[1]
+    assert abs(errs[4] - errs[3]) < 0.02 * errs[3]
+    assert ol <= min(errs.values())
+
+
+def test_taylor_flag_is_rejected_by_the_fused_path():
+    L = lib()
+    from paper_2104_00359_amd import ops
+    ops.ensure_init(torch.device("cuda", 0))
+    prm = L.params(4, 3.0, 4, _flags(3))
+    f = L.raw("sh_render_forward")
+    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, None, 0, None) == \
+        L.SHV_ERR_UNSUPPORTED

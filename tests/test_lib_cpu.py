@@ -70,7 +70,9 @@ def test_invalid_parameters_rejected_before_any_device_call(L):
     assert f(None, -5, None, 0, ctypes.byref(neg), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
     bad_eps = L.params(4, -1.0)
     assert f(None, 10, None, 0, ctypes.byref(bad_eps), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
-    for bad_flags in (16, 3, 5, 6, 9, 12):  # unknown bit; both layouts; quadrature or product with another flag
+    # unknown bit; both layouts; quadrature or product with another flag; Taylor without an order, with
+    # order 9, with a layout flag; an order without the Taylor flag
+    for bad_flags in (32, 3, 5, 6, 9, 12, 16, 16 | (9 << 8), 16 | (2 << 8) | 1, 2 << 8):
         flags = L.shv_params(4, 4, 3.0, bad_flags)
         assert f(None, 10, None, 0, ctypes.byref(flags), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
     g = L.raw("sh_shade")
@@ -241,3 +243,11 @@ def test_deform_arguments_rejected_before_any_device_call(L):
     assert L.raw("sh_sgd_step")(None, None, -1, ctypes.c_float(0.1), st) == L.SHV_ERR_INVALID_ARG
     assert L.shv_deform_workspace_bytes(0, 5) == 0 and L.shv_deform_workspace_bytes(100, 5) > 0
     assert L.shv_l2_workspace_bytes(0) == 0 and L.shv_l2_workspace_bytes(1000) >= 4 * 4
+
+
+def test_taylor_flags_and_saved_sizes(L):
+    for K in (1, 3, 8):
+        prm = L.params(4, 3.0, 2, L.SHV_FLAG_EXP_TAYLOR | L.SHV_FLAG_EXP_TAYLOR_ORDER(K))
+        assert L.shv_saved_floats(100, prm) == (1 + (2 + K) * 16) * 100
+        assert L.shv_workspace_bytes(100, 7, prm) == L.shv_workspace_bytes(100, 7, L.params(4, 3.0, 2))
+    assert L.shv_saved_floats(100, L.params(4, 3.0, 2, L.SHV_FLAG_EXP_PRODUCT)) == 0

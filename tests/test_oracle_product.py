@@ -143,3 +143,43 @@ def test_forward_product_mode_runs_through_the_pipeline():
     T = method.scene_tensors(sc)
     V = method.sh_direct_product(T["points"], T["spheres"], 4, 3.0, sh.gaunt_tensor(4))
     assert torch.allclose(o["V"], V, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- taylor-K
+
+def _band1_F(seed, n, P=5, scale=1.0):
+    """Log-visibility vectors with a DC term and band-1 terms only, so every
+    truncated power G^{*j} of band <= j stays exact while j < n."""
+    g = torch.Generator().manual_seed(seed)
+    F = torch.zeros(P, n * n, dtype=DT)
+    F[:, 0] = torch.randn(P, generator=g, dtype=DT)
+    F[:, 1:4] = torch.randn(P, 3, generator=g, dtype=DT) * scale
+    return F
+
+
+@pytest.mark.parametrize("K,k", [(1, 0), (1, 2), (2, 1), (3, 1), (4, 0), (7, 0), (2, 0)])
+def test_taylor_is_exact_when_no_product_truncates(K, k):
+    """n = 8 and F in bands <= 1: E_0 has band <= K and E_k band <= K 2^k <= 7,
+    so no truncation happens and V is the projection of the pointwise
+    exp(c) (sum_{j <= K} (g / 2^k)^j / j!)^(2^k), g the band-1 function."""
+    n = 8
+    F = _band1_F(K * 10 + k, n)
+    V = method.sh_exponential_taylor(F, sh.gaunt_tensor(n), K, k)
+    d, w = sh.sphere_quadrature(3 * n)
+    Y = sh.real_sh(d, n)
+    g = (F[:, 1:4] @ Y[:, 1:4].T) * 2.0 ** -k                  # [P, Q]
+    poly = sum(g ** j / math.factorial(j) for j in range(K + 1)) ** (2 ** k)
+    ref = torch.exp(F[:, 0] / math.sqrt(4 * math.pi))[:, None] * ((poly * w) @ Y)
+    assert torch.abs(V - ref).max() < 1e-12 * max(1.0, float(torch.abs(ref).max()))
+
+
+def test_taylor_converges_to_the_quadrature_exponential_without_truncation():
+    """Still exact band-1 input, high order: sum_j g^j/j! -> exp(g), so V
+    approaches Proj_n[exp(F~)] at the rate of the series' remainder."""
+    n = 8
+    F = _band1_F(3, n, scale=0.3)
+    V = method.sh_exponential_taylor(F, sh.gaunt_tensor(n), 7, 0)
+    ref = brute.exact_exponential(F, n, degree=80)
+    rem = max(float(torch.linalg.norm(F[j, 1:4])) * math.sqrt(3 / (4 * math.pi)) for j in range(F.shape[0]))
+    bound = rem ** 8 / math.factorial(8) * math.exp(rem) * 4 * math.pi
+    assert float(torch.abs(V - ref).max() / torch.abs(ref).max()) < bound
