@@ -71,8 +71,8 @@ def parse():
     ap.add_argument("--path", default="render", choices=["render", "separate"])
     ap.add_argument("--flags", type=int, default=0,
                     help="shv_params.flags: 1 / 2 select the exponential's kernel layout; 4 selects the "
-                         "quadrature exponential, 8 the direct product chain of Eq. 12 (different "
-                         "approximations; separate entry points only)")
+                         "quadrature exponential, 8 the direct product chain of Eq. 12, 16 | (K << 8) the "
+                         "Taylor series of order K (different approximations; separate entry points only)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched64: time eager batched calls instead of graph replays")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
@@ -307,17 +307,19 @@ def bench_single(args):
     ms, prof = timed(step, stream, args.warmup, args.steps, True)
     copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
-    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
+    order = (args.flags >> 8) & 15 if args.flags & _lib.SHV_FLAG_EXP_TAYLOR else 0
+    roof = roofline(kernels, sampled_steps(args.steps),
+                    lambda name: workmodel.kernel_work(name, n, k, P, S, order=order))
     if roof is not None:
         roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
-    mode = {4: "quadrature", 8: "product"}.get(args.flags, "squaring")
+    mode = {4: "quadrature", 8: "product"}.get(args.flags, f"taylor{order}" if order else "squaring")
     cpu = cpu_baseline([sc], k, args.cpu_seconds, mode) if args.cpu_seconds > 0 else None
     return {
         "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0,
-                   "entry_points": args.path},
+                   "entry_points": args.path, "visibility": mode},
         "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
     }
 

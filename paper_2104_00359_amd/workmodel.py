@@ -137,6 +137,22 @@ def exp_quad_bwd_flops(n: int) -> int:
     return 3 * (2 * N * Q) + 3 * Q
 
 
+def exp_taylor_fwd_flops(n: int, k: int, K: int) -> int:
+    """Per receiver: the DC split and scaling (2 N), K Horner steps (one
+    sparse product each, returned doubled, and its scale), k squarings and
+    the final exp(c) scale."""
+    N = n * n
+    return 2 * N + K * (square_adj_flops(n) + N) + k * square_flops(n) + N + 1
+
+
+def exp_taylor_bwd_flops(n: int, k: int, K: int) -> int:
+    """Per receiver: cbar and exp(c) Vbar (3 N), k adjoint squarings, the
+    Horner adjoint (two sparse products per step but one in the last, each
+    with its scale / accumulation) and the weights W (2 N)."""
+    N = n * n
+    return 3 * N + k * square_adj_flops(n) + (2 * K - 1) * (square_adj_flops(n) + 2 * N) + 2 * N
+
+
 def prod_fwd_flops(n: int) -> int:
     """Per (receiver, sphere) step of the direct product chain: the pair's
     blocker vector (the pair forward's basis work plus one LAMBDA multiply per
@@ -173,10 +189,14 @@ def pair_fwd_bytes_per_receiver(n: int, nchunks: int) -> int:
     return 4 * (3 * nchunks + n * n * nchunks)
 
 
-def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pixels: int = 0):
+def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pixels: int = 0, order: int = 0):
     """(flops, unit count) of one launch of kernel ``name`` (``channels``
     for the multi-channel shading kernels, ``pixels`` = C H W for the
-    environment-map projection)."""
+    environment-map projection, ``order`` = K of the Taylor exponential)."""
+    if name == "exp_taylor_fwd":
+        return exp_taylor_fwd_flops(n, k, order) * P, P
+    if name == "exp_taylor_bwd":
+        return exp_taylor_bwd_flops(n, k, order) * P, P
     if name == "shade_ch_fwd":
         return shade_ch_fwd_flops(n, channels) * P, P
     if name == "shade_ch_bwd":
