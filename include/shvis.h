@@ -237,6 +237,53 @@ shv_status shv_deform_graph_build(const float* vertices, int64_t P, const float*
                                   int32_t* vert_ptr, int32_t* vert_sph, float* vert_w, int32_t* sph_vert,
                                   float* sph_w);
 
+/* ------------------------------------------------------------------ rasteriser
+ * Rendering the shaded mesh into an image (Sec. 3.4, Eq. 14):
+ * I_R = R(B(x_0), ..., B(x_n), P).  The camera matrix P (3 x 4, row-major)
+ * maps a homogeneous world point X to (u, v, w): pixel coordinates
+ * (u / w, v / w), depth w.  Pixel (i, j) (column i, row j; image row-major
+ * [height][width]) has its centre at (i + 0.5, j + 0.5).  Each centre takes
+ * the nearest triangle covering it (edges inclusive, no culling; depth
+ * 1 / sum_k lambda_k / w_k, ties to the lower face index) and the
+ * perspective-correct interpolation of its vertices' radiance; uncovered
+ * pixels are 0.  Triangles with a vertex at w <= 1e-6, zero area, or an index
+ * outside [0, V) are not drawn (no clipping).  The coverage and depth
+ * decisions use FP32 with one rounding per operation in a fixed order (see
+ * the implementation), so they are reproducible.  Gradients flow through the
+ * winning triangle's weights to the vertices' radiance and positions (a hard
+ * rasteriser: occlusion and silhouette changes contribute nothing). */
+#define SHV_MAX_IMAGE_SIDE 16384
+typedef struct shv_camera {
+  float P[12];   /* row-major 3 x 4 projection (intrinsics times extrinsics) */
+  int32_t width; /* 1 .. SHV_MAX_IMAGE_SIDE */
+  int32_t height;
+} shv_camera;
+
+/* Vertex-to-corner incidence of a triangle mesh, built on the host (a
+ * one-time preprocessing of the mesh): faces [T][3] host int32; outputs ptr
+ * [V + 1] and idx [3 T] (host), idx[ptr[v] .. ptr[v + 1]) = 3 f + k for every
+ * corner k of face f at vertex v, in increasing f.  Fails if an index is
+ * outside [0, V). */
+shv_status shv_raster_incidence_build(const int32_t* faces, int64_t T, int64_t V, int32_t* ptr, int32_t* idx);
+
+/* Workspace bytes of sh_raster_forward / sh_raster_backward (0 if invalid). */
+size_t shv_raster_workspace_bytes(int64_t V, int64_t T);
+
+/* vertices [3][V], faces [T][3], radiance [V] (device) -> image [height][width]
+ * and face_id [height][width] (device; -1 where nothing is drawn). */
+shv_status sh_raster_forward(const float* vertices, int64_t V, const int32_t* faces, int64_t T,
+                             const float* radiance, const shv_camera* camera, float* image, int32_t* face_id,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of sh_raster_forward for the cotangent grad_image [height][width]:
+ * face_id is the forward's output for the same inputs, inc_ptr / inc_idx the
+ * incidence (device copies).  grad_radiance [V] and grad_vertices [3][V]
+ * (either may be NULL).  Deterministic (fixed-order sums, no atomics). */
+shv_status sh_raster_backward(const float* grad_image, const float* vertices, int64_t V, const int32_t* faces,
+                              int64_t T, const float* radiance, const shv_camera* camera, const int32_t* face_id,
+                              const int32_t* inc_ptr, const int32_t* inc_idx, float* grad_radiance,
+                              float* grad_vertices, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Workspace bytes of sh_deform_forward / sh_deform_backward (0 if invalid). */
 size_t shv_deform_workspace_bytes(int64_t P, int64_t S);
 

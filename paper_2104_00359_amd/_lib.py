@@ -34,6 +34,7 @@ EXPORTED = [
     "shv_channels_workspace_bytes", "sh_shade_channels", "sh_shade_channels_backward",
     "shv_envmap_workspace_bytes", "sh_envmap_project",
     "shv_deform_graph_build", "shv_deform_workspace_bytes", "sh_deform_forward", "sh_deform_backward",
+    "shv_raster_incidence_build", "shv_raster_workspace_bytes", "sh_raster_forward", "sh_raster_backward",
     "shv_l2_workspace_bytes", "sh_l2_loss", "sh_sgd_step",
     "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
     "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
@@ -79,6 +80,21 @@ class shv_deform_graph(ctypes.Structure):
         ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("K", ctypes.c_int32)]
 
 
+class shv_camera(ctypes.Structure):
+    """Row-major 3 x 4 projection and the image size (as in the C struct)."""
+    _fields_ = [("P", ctypes.c_float * 12), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+def camera(P, width, height):
+    c = shv_camera()
+    flat = [float(x) for row in P for x in row]
+    if len(flat) != 12:
+        raise ValueError("camera matrix must be 3 x 4")
+    c.P[:] = flat
+    c.width, c.height = int(width), int(height)
+    return c
+
+
 class shv_batch_grid(ctypes.Structure):
     """Block counts of the batched launches (see the C header)."""
     _fields_ = [("pair", ctypes.c_int64 * 9), ("exp", (ctypes.c_int64 * 9) * 2), ("finalize", ctypes.c_int64)]
@@ -107,6 +123,11 @@ _sig = {
     "sh_envmap_project": (ctypes.c_int32, [_P, ctypes.c_int, _I64, _I64, _PRM, _P, _P, _SZ, _P]),
     "shv_deform_graph_build": (ctypes.c_int32, [_P, _I64, _P, _I64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "shv_deform_workspace_bytes": (_SZ, [_I64, _I64]),
+    "shv_raster_incidence_build": (ctypes.c_int32, [_P, _I64, _I64, _P, _P]),
+    "shv_raster_workspace_bytes": (_SZ, [_I64, _I64]),
+    "sh_raster_forward": (ctypes.c_int32, [_P, _I64, _P, _I64, _P, ctypes.POINTER(shv_camera), _P, _P, _P, _SZ, _P]),
+    "sh_raster_backward": (ctypes.c_int32, [_P, _P, _I64, _P, _I64, _P, ctypes.POINTER(shv_camera), _P, _P, _P, _P,
+                                            _P, _P, _SZ, _P]),
     "sh_deform_forward": (ctypes.c_int32, [ctypes.POINTER(shv_deform_graph), _P, _P, _P, _P, _P, _SZ, _P]),
     "sh_deform_backward": (ctypes.c_int32, [ctypes.POINTER(shv_deform_graph), _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "shv_l2_workspace_bytes": (_SZ, [_I64]),
@@ -226,6 +247,31 @@ def shv_deform_graph_build(vertices, P, spheres, S, K, vert_ptr, vert_sph, vert_
         return ctypes.c_void_p(a.ctypes.data)
     _check(_lib.shv_deform_graph_build(hp(vertices), int(P), hp(spheres), int(S), int(K), hp(vert_ptr),
                                        hp(vert_sph), hp(vert_w), hp(sph_vert), hp(sph_w)), "shv_deform_graph_build")
+
+
+def shv_raster_incidence_build(faces, T, V, inc_ptr, inc_idx):
+    """Host arrays (numpy, C-contiguous): faces int32 [T][3]; outputs int32
+    inc_ptr [V + 1] and inc_idx [3 T]."""
+    def hp(a):
+        return ctypes.c_void_p(a.ctypes.data)
+    _check(_lib.shv_raster_incidence_build(hp(faces), int(T), int(V), hp(inc_ptr), hp(inc_idx)),
+           "shv_raster_incidence_build")
+
+
+def shv_raster_workspace_bytes(V: int, T: int) -> int:
+    return int(_lib.shv_raster_workspace_bytes(int(V), int(T)))
+
+
+def sh_raster_forward(vertices, V, faces, T, radiance, cam, image, face_id, ws, ws_bytes, stream):
+    _check(_lib.sh_raster_forward(ptr(vertices), int(V), ptr(faces), int(T), ptr(radiance), ctypes.byref(cam),
+                                  ptr(image), ptr(face_id), ptr(ws), int(ws_bytes), stream), "sh_raster_forward")
+
+
+def sh_raster_backward(grad_image, vertices, V, faces, T, radiance, cam, face_id, inc_ptr, inc_idx, grad_radiance,
+                       grad_vertices, ws, ws_bytes, stream):
+    _check(_lib.sh_raster_backward(ptr(grad_image), ptr(vertices), int(V), ptr(faces), int(T), ptr(radiance),
+                                   ctypes.byref(cam), ptr(face_id), ptr(inc_ptr), ptr(inc_idx), ptr(grad_radiance),
+                                   ptr(grad_vertices), ptr(ws), int(ws_bytes), stream), "sh_raster_backward")
 
 
 def shv_deform_workspace_bytes(P: int, S: int) -> int:

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libshvis.so")
 # compiled once per band count.
 SOURCES = [("shv_nb.hip", [f"-DSHV_NB={n}", f"-DSHV_PART={part}"], f"shv_nb{n}_p{part}.o")
            for n in range(8, 0, -1) for part in (3, 7, 8, 2, 5, 4, 6, 1, 0)] + [
-    ("shv_api.hip", [], "shv_api.o"), ("shv_common.hip", [], "shv_common.o"), ("shv_deform.hip", [], "shv_deform.o")]
+    ("shv_api.hip", [], "shv_api.o"), ("shv_common.hip", [], "shv_common.o"), ("shv_deform.hip", [], "shv_deform.o"),
+    ("shv_raster.hip", [], "shv_raster.o")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled on purpose (see the design notes).

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -325,6 +326,26 @@ shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
   if (!ws) return set_error(SHV_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", needed);
   if (((uintptr_t)ws) % kAlign) return set_error(SHV_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
   if (ws_bytes < needed) return set_error(SHV_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, needed);
+  return SHV_OK;
+}
+
+shv_status check_camera(const shv_camera* cam, shv::RasterCam& rc) {
+  if (!cam) return set_error(SHV_ERR_INVALID_ARG, "camera is NULL");
+  if (cam->width < 1 || cam->height < 1 || cam->width > SHV_MAX_IMAGE_SIDE || cam->height > SHV_MAX_IMAGE_SIDE)
+    return set_error(SHV_ERR_INVALID_ARG, "image size %d x %d outside [1, %d]", cam->width, cam->height,
+                     SHV_MAX_IMAGE_SIDE);
+  for (int i = 0; i < 12; ++i) {
+    if (!std::isfinite(cam->P[i])) return set_error(SHV_ERR_INVALID_ARG, "camera matrix has a non-finite entry");
+    rc.P[i] = cam->P[i];
+  }
+  rc.width = cam->width;
+  rc.height = cam->height;
+  return SHV_OK;
+}
+
+shv_status check_mesh(int64_t V, int64_t T) {
+  if (V < 0 || T < 0 || V >= ((int64_t)1 << 31) || 3 * T >= ((int64_t)1 << 31))
+    return set_error(SHV_ERR_INVALID_ARG, "mesh size out of range (V=%lld, T=%lld)", (long long)V, (long long)T);
   return SHV_OK;
 }
 
@@ -687,6 +708,79 @@ shv_status sh_envmap_project(const float* image, int channels, int64_t H, int64_
                  [&] { return shv::launch_envmap_rows(nb, image, channels, H, W, part, stream); }));
   SHV_TRY(launch("reduce_envmap", stream, [&] {
     return shv::launch_reduce_rows(part, (int)shv::envmap_row_blocks(H, W), N, light, stream, channels);
+  }));
+  return SHV_OK;
+}
+
+// ------------------------------------------------------------------ rasteriser
+
+shv_status shv_raster_incidence_build(const int32_t* faces, int64_t T, int64_t V, int32_t* ptr, int32_t* idx) {
+  if (T < 0 || V < 0 || 3 * T >= ((int64_t)1 << 31) || V >= ((int64_t)1 << 31))
+    return set_error(SHV_ERR_INVALID_ARG, "mesh size out of range (T=%lld, V=%lld)", (long long)T, (long long)V);
+  if ((T > 0 && (!faces || !idx)) || !ptr) return set_error(SHV_ERR_INVALID_ARG, "NULL array");
+  std::vector<int32_t> count(V + 1, 0);
+  for (int64_t c = 0; c < 3 * T; ++c) {
+    const int32_t v = faces[c];
+    if (v < 0 || v >= V)
+      return set_error(SHV_ERR_INVALID_ARG, "face %lld has vertex index %d outside [0, %lld)", (long long)(c / 3), v,
+                       (long long)V);
+    ++count[v + 1];
+  }
+  for (int64_t v = 0; v < V; ++v) count[v + 1] += count[v];
+  for (int64_t v = 0; v <= V; ++v) ptr[v] = count[v];
+  for (int64_t c = 0; c < 3 * T; ++c) idx[count[faces[c]]++] = (int32_t)c;
+  return SHV_OK;
+}
+
+size_t shv_raster_workspace_bytes(int64_t V, int64_t T) {
+  if (V < 0 || T < 0 || 3 * T >= ((int64_t)1 << 31)) return 0;
+  return align_up(shv::raster_record_bytes(T)) + align_up((size_t)T * 12 * 4);
+}
+
+shv_status sh_raster_forward(const float* vertices, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
+                             const shv_camera* camera, float* image, int32_t* face_id, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  shv::RasterCam rc;
+  SHV_TRY(check_camera(camera, rc));
+  SHV_TRY(check_mesh(V, T));
+  SHV_TRY(check_device());
+  SHV_TRY(need(image, "image"));
+  SHV_TRY(need(face_id, "face_id"));
+  if (T > 0) {
+    SHV_TRY(need(vertices, "vertices"));
+    SHV_TRY(need(faces, "faces"));
+    SHV_TRY(need(radiance, "radiance"));
+  }
+  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T)));
+  SHV_TRY(launch("raster_fwd", stream, [&] {
+    return shv::launch_raster_forward(vertices, V, faces, T, radiance, rc, image, face_id, ws, stream);
+  }));
+  return SHV_OK;
+}
+
+shv_status sh_raster_backward(const float* grad_image, const float* vertices, int64_t V, const int32_t* faces,
+                              int64_t T, const float* radiance, const shv_camera* camera, const int32_t* face_id,
+                              const int32_t* inc_ptr, const int32_t* inc_idx, float* grad_radiance,
+                              float* grad_vertices, void* ws, size_t ws_bytes, hipStream_t stream) {
+  shv::RasterCam rc;
+  SHV_TRY(check_camera(camera, rc));
+  SHV_TRY(check_mesh(V, T));
+  SHV_TRY(check_device());
+  if (V == 0 || (!grad_radiance && !grad_vertices)) return SHV_OK;
+  SHV_TRY(need(vertices, "vertices"));
+  SHV_TRY(need(inc_ptr, "inc_ptr"));
+  if (T > 0) {
+    SHV_TRY(need(grad_image, "grad_image"));
+    SHV_TRY(need(faces, "faces"));
+    SHV_TRY(need(radiance, "radiance"));
+    SHV_TRY(need(face_id, "face_id"));
+    SHV_TRY(need(inc_idx, "inc_idx"));
+  }
+  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T)));
+  float* part = (float*)((char*)ws + align_up(shv::raster_record_bytes(T)));
+  SHV_TRY(launch("raster_bwd", stream, [&] {
+    return shv::launch_raster_backward(grad_image, vertices, V, faces, T, radiance, rc, face_id, inc_ptr, inc_idx,
+                                       grad_radiance, grad_vertices, ws, part, stream);
   }));
   return SHV_OK;
 }

@@ -1,0 +1,342 @@
+// Rasterisation of the shaded mesh (Sec. 3.4, Eq. 14) and its adjoint.
+//
+// I_R = R(B(x_0), ..., B(x_n), P): the vertices are projected by the 3 x 4
+// camera matrix P ((u, v, w) = P [x; 1], pixel coordinates (u / w, v / w),
+// depth w); each pixel centre (i + 0.5, j + 0.5) takes the nearest triangle
+// covering it (edge functions over the doubled signed area all >= 0, depth
+// 1 / sum_k lambda_k / w_k, ties to the lower face index) and interpolates
+// the vertices' radiance with the perspective-correct weights
+// b_k = (lambda_k / w_k) / sum_j (lambda_j / w_j).  Uncovered pixels are 0.
+//
+// The coverage and depth decisions pick integers from floating-point values,
+// so they are taken with one rounding per operation (no contraction into
+// FMAs, correctly rounded division) in a fixed order; the same decisions can
+// then be reproduced exactly in FP32 elsewhere.
+//
+// Forward: a setup pass writes one record per face (projected corners,
+// depths, area, pixel bounding box; faces behind the camera, degenerate or
+// with an index outside [0, V) get an empty box).  Then one block per 16 x 16
+// pixel tile walks the faces in index order in chunks of 256: the chunk's
+// records are staged in LDS, the ones whose box meets the tile are compacted
+// (in order) and every thread tests its pixel against them.
+//
+// Adjoint (through the winning triangle's weights; which triangle wins is
+// piecewise constant): one wave per face walks the face's bounding box, takes
+// the pixels that face won, and sums their contributions to the face's three
+// corners (radiance, pixel x, pixel y, depth) in a fixed order; a per-vertex
+// pass then sums the corners of its incident faces in the incidence list's
+// order and chains through the projection.  No atomics: every sum has a
+// fixed order.
+
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "shv_config.h"
+#include "shv_launch.h"
+
+namespace shv {
+
+constexpr float kRasterMinW = 1e-6f;
+constexpr int kTile = 16;
+
+struct alignas(16) FaceRec {
+  float x[3], y[3], w[3], area;
+  int32_t i0, i1, j0, j1;
+  int32_t pad[2];
+};
+static_assert(sizeof(FaceRec) == 64, "face record is one 64-byte line");
+
+// (u, v, w) of one vertex, each ((P_r0 x + P_r1 y) + P_r2 z) + P_r3.
+__device__ __forceinline__ void project_vertex(const float* __restrict__ P, float x, float y, float z, float& u,
+                                               float& v, float& w) {
+  u = ((P[0] * x + P[1] * y) + P[2] * z) + P[3];
+  v = ((P[4] * x + P[5] * y) + P[6] * z) + P[7];
+  w = ((P[8] * x + P[9] * y) + P[10] * z) + P[11];
+}
+
+__device__ __forceinline__ float edge_fn(float ax, float ay, float bx, float by, float px, float py) {
+  return (ax - px) * (by - py) - (bx - px) * (ay - py);
+}
+
+__device__ __forceinline__ int clamp_floor(float v, int lo, int hi) {
+  if (!(v > (float)lo)) return lo;  // also NaN
+  if (v >= (float)hi) return hi;
+  return (int)floorf(v);
+}
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restrict__ verts, int64_t V,
+                                                            const int32_t* __restrict__ faces, int64_t T,
+                                                            RasterCam cam, FaceRec* __restrict__ rec) {
+  const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (f >= T) return;
+  FaceRec r;
+  r.i0 = 0;
+  r.i1 = -1;
+  r.j0 = 0;
+  r.j1 = -1;
+  r.pad[0] = r.pad[1] = 0;
+  bool ok = true;
+  for (int k = 0; k < 3; ++k) {
+    const int32_t vi = faces[3 * f + k];
+    if (vi < 0 || vi >= V) {
+      ok = false;
+      r.x[k] = r.y[k] = r.w[k] = 0.0f;
+      continue;
+    }
+    float u, v, w;
+    project_vertex(cam.P, verts[vi], verts[V + vi], verts[2 * V + vi], u, v, w);
+    r.x[k] = u / w;
+    r.y[k] = v / w;
+    r.w[k] = w;
+    ok = ok && (w > kRasterMinW);
+  }
+  r.area = (r.x[1] - r.x[0]) * (r.y[2] - r.y[0]) - (r.x[2] - r.x[0]) * (r.y[1] - r.y[0]);
+  ok = ok && (r.area != 0.0f) && isfinite(r.area);
+  if (ok) {
+    const float xmin = fminf(fminf(r.x[0], r.x[1]), r.x[2]), xmax = fmaxf(fmaxf(r.x[0], r.x[1]), r.x[2]);
+    const float ymin = fminf(fminf(r.y[0], r.y[1]), r.y[2]), ymax = fmaxf(fmaxf(r.y[0], r.y[1]), r.y[2]);
+    // pixel i is a candidate when xmin - 1 <= i <= xmax (a superset of the
+    // centres i + 0.5 inside [xmin, xmax]); the coverage test decides.
+    r.i0 = clamp_floor(xmin - 1.0f, 0, cam.width - 1);
+    r.i1 = clamp_floor(xmax, -1, cam.width - 1);
+    r.j0 = clamp_floor(ymin - 1.0f, 0, cam.height - 1);
+    r.j1 = clamp_floor(ymax, -1, cam.height - 1);
+    if (xmax < -1.0f || ymax < -1.0f) r.i1 = -1;
+  }
+  rec[f] = r;
+}
+
+struct RasterShared {
+  FaceRec recs[SHV_BLOCK];
+  int32_t list[SHV_BLOCK];
+  int32_t wave_count[SHV_WAVES_PER_BLOCK];
+};
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_tiles(const FaceRec* __restrict__ rec, int64_t T,
+                                                            const int32_t* __restrict__ faces,
+                                                            const float* __restrict__ radiance, int width,
+                                                            int height, int tiles_x, float* __restrict__ image,
+                                                            int32_t* __restrict__ face_id) {
+  __shared__ RasterShared sh;
+  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int ti0 = tx * kTile, tj0 = ty * kTile;
+  const int ti1 = min(ti0 + kTile, width) - 1, tj1 = min(tj0 + kTile, height) - 1;
+  const int i = ti0 + (threadIdx.x % kTile), j = tj0 + (threadIdx.x / kTile);
+  const float px = (float)i + 0.5f, py = (float)j + 0.5f;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float best_z = INFINITY;
+  int32_t best_f = -1;
+  float bl0 = 0.0f, bl1 = 0.0f, bl2 = 0.0f;
+  for (int64_t c0 = 0; c0 < T; c0 += SHV_BLOCK) {
+    const int64_t f = c0 + threadIdx.x;
+    bool hit = false;
+    if (f < T) {
+      const FaceRec r = rec[f];
+      sh.recs[threadIdx.x] = r;
+      hit = r.i0 <= r.i1 && r.j0 <= r.j1 && r.i0 <= ti1 && r.i1 >= ti0 && r.j0 <= tj1 && r.j1 >= tj0;
+    }
+    // compact the chunk's faces that meet the tile, keeping index order
+    const uint64_t m = __ballot(hit);
+    if (lane == 0) sh.wave_count[wave] = __popcll(m);
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < SHV_WAVES_PER_BLOCK; ++w) {
+      if (w < wave) base += sh.wave_count[w];
+      total += sh.wave_count[w];
+    }
+    if (hit) sh.list[base + __popcll(m & ((1ull << lane) - 1ull))] = threadIdx.x;
+    __syncthreads();
+    for (int n = 0; n < total; ++n) {
+      const FaceRec& r = sh.recs[sh.list[n]];
+      if (i < r.i0 || i > r.i1 || j < r.j0 || j > r.j1) continue;
+      const float l0 = edge_fn(r.x[1], r.y[1], r.x[2], r.y[2], px, py) / r.area;
+      const float l1 = edge_fn(r.x[2], r.y[2], r.x[0], r.y[0], px, py) / r.area;
+      const float l2 = edge_fn(r.x[0], r.y[0], r.x[1], r.y[1], px, py) / r.area;
+      if (!(l0 >= 0.0f && l1 >= 0.0f && l2 >= 0.0f)) continue;
+      const float z = 1.0f / ((l0 / r.w[0] + l1 / r.w[1]) + l2 / r.w[2]);
+      if (z < best_z) {
+        best_z = z;
+        best_f = (int32_t)(c0 + sh.list[n]);
+        bl0 = l0;
+        bl1 = l1;
+        bl2 = l2;
+      }
+    }
+    __syncthreads();  // the chunk's records are no longer read
+  }
+  if (i > ti1 || j > tj1) return;
+  const int64_t pix = (int64_t)j * width + i;
+  face_id[pix] = best_f;
+  float val = 0.0f;
+  if (best_f >= 0) {
+    const FaceRec r = rec[best_f];
+    const float q0 = bl0 / r.w[0], q1 = bl1 / r.w[1], q2 = bl2 / r.w[2];
+    const float Q = (q0 + q1) + q2;
+    const int32_t* fv = faces + 3 * (int64_t)best_f;
+    val = ((q0 * radiance[fv[0]] + q1 * radiance[fv[1]]) + q2 * radiance[fv[2]]) / Q;
+  }
+  image[pix] = val;
+}
+
+// Contributions of one pixel won by face r to its corners: radiance
+// cotangent, pixel-coordinate and depth cotangents (see the header).
+__device__ __forceinline__ void pixel_adjoint(const FaceRec& r, float px, float py, float gI, const float (&B)[3],
+                                              float (&gB)[3], float (&gx)[3], float (&gy)[3], float (&gw)[3]) {
+  const float dx[3] = {r.x[0] - px, r.x[1] - px, r.x[2] - px};
+  const float dy[3] = {r.y[0] - py, r.y[1] - py, r.y[2] - py};
+  const float E[3] = {dx[1] * dy[2] - dx[2] * dy[1], dx[2] * dy[0] - dx[0] * dy[2], dx[0] * dy[1] - dx[1] * dy[0]};
+  const float inv_a = 1.0f / r.area;
+  float lam[3], q[3];
+  for (int k = 0; k < 3; ++k) {
+    lam[k] = E[k] * inv_a;
+    q[k] = lam[k] / r.w[k];
+  }
+  const float Q = (q[0] + q[1]) + q[2];
+  const float invQ = 1.0f / Q;
+  const float I = ((q[0] * B[0] + q[1] * B[1]) + q[2] * B[2]) * invQ;
+  float gl[3], gA = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    gB[k] = gI * (q[k] * invQ);
+    const float gq = gI * (B[k] - I) * invQ;
+    gw[k] = -gq * q[k] / r.w[k];
+    gl[k] = gq / r.w[k];
+    gA -= gl[k] * lam[k];
+  }
+  const float gE0 = gl[0] * inv_a, gE1 = gl[1] * inv_a, gE2 = gl[2] * inv_a;
+  gA *= inv_a;
+  gx[0] = -gE1 * dy[2] + gE2 * dy[1] + gA * (r.y[1] - r.y[2]);
+  gx[1] = gE0 * dy[2] - gE2 * dy[0] + gA * (r.y[2] - r.y[0]);
+  gx[2] = -gE0 * dy[1] + gE1 * dy[0] + gA * (r.y[0] - r.y[1]);
+  gy[0] = gE1 * dx[2] - gE2 * dx[1] + gA * (r.x[2] - r.x[1]);
+  gy[1] = -gE0 * dx[2] + gE2 * dx[0] + gA * (r.x[0] - r.x[2]);
+  gy[2] = gE0 * dx[1] - gE1 * dx[0] + gA * (r.x[1] - r.x[0]);
+}
+
+__device__ __forceinline__ float wave_sum_fixed(float v) {
+  // butterfly over the 64 lanes: every lane ends with the same, fixed-order sum
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wave per face: part[f][k][c] for corner k and c = (radiance, x, y, w).
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_face_grads(const FaceRec* __restrict__ rec, int64_t T,
+                                                                 const int32_t* __restrict__ faces,
+                                                                 const float* __restrict__ radiance,
+                                                                 const float* __restrict__ grad_image,
+                                                                 const int32_t* __restrict__ face_id, int width,
+                                                                 float* __restrict__ part) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t f = (int64_t)blockIdx.x * SHV_WAVES_PER_BLOCK + wave;
+  if (f >= T) return;
+  const FaceRec r = rec[f];
+  float acc[12];
+  for (int c = 0; c < 12; ++c) acc[c] = 0.0f;
+  if (r.i0 <= r.i1 && r.j0 <= r.j1) {
+    const int32_t* fv = faces + 3 * f;
+    const float B[3] = {radiance[fv[0]], radiance[fv[1]], radiance[fv[2]]};
+    const int bw = r.i1 - r.i0 + 1;
+    const int64_t n = (int64_t)bw * (r.j1 - r.j0 + 1);
+    for (int64_t t = lane; t < n; t += 64) {
+      const int i = r.i0 + (int)(t % bw), j = r.j0 + (int)(t / bw);
+      const int64_t pix = (int64_t)j * width + i;
+      if (face_id[pix] != (int32_t)f) continue;
+      float gB[3], gx[3], gy[3], gw[3];
+      pixel_adjoint(r, (float)i + 0.5f, (float)j + 0.5f, grad_image[pix], B, gB, gx, gy, gw);
+      for (int k = 0; k < 3; ++k) {
+        acc[4 * k + 0] += gB[k];
+        acc[4 * k + 1] += gx[k];
+        acc[4 * k + 2] += gy[k];
+        acc[4 * k + 3] += gw[k];
+      }
+    }
+  }
+  for (int c = 0; c < 12; ++c) acc[c] = wave_sum_fixed(acc[c]);
+  if (lane < 12) {
+    float v = acc[0];
+    for (int c = 1; c < 12; ++c)
+      if (lane == c) v = acc[c];
+    part[12 * f + lane] = v;
+  }
+}
+
+// Per vertex: the corners of its incident faces in incidence order, then the
+// projection's adjoint.  inc holds 3 f + k for corner k of face f.
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_vertex_grads(const float* __restrict__ verts, int64_t V,
+                                                                   int64_t T, RasterCam cam,
+                                                                   const int32_t* __restrict__ inc_ptr,
+                                                                   const int32_t* __restrict__ inc,
+                                                                   const float* __restrict__ part,
+                                                                   float* __restrict__ grad_radiance,
+                                                                   float* __restrict__ grad_verts) {
+  const int64_t v = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (v >= V) return;
+  const int64_t lim = 3 * T;
+  int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
+  b = b < 0 ? 0 : (b > lim ? lim : b);
+  e = e < b ? b : (e > lim ? lim : e);
+  float gB = 0.0f, gx = 0.0f, gy = 0.0f, gw = 0.0f;
+  for (int64_t t = b; t < e; ++t) {
+    const int64_t c = inc[t];
+    if (c < 0 || c >= lim) continue;
+    const float* p = part + 4 * c;
+    gB += p[0];
+    gx += p[1];
+    gy += p[2];
+    gw += p[3];
+  }
+  if (grad_radiance) grad_radiance[v] = gB;
+  if (grad_verts) {
+    const float x = verts[v], y = verts[V + v], z = verts[2 * V + v];
+    float u, vv, w;
+    project_vertex(cam.P, x, y, z, u, vv, w);
+    const float gu = gx / w, gv = gy / w;
+    const float gww = gw - (gu * u + gv * vv) / w;
+    const float* P = cam.P;
+    grad_verts[v] = (P[0] * gu + P[4] * gv) + P[8] * gww;
+    grad_verts[V + v] = (P[1] * gu + P[5] * gv) + P[9] * gww;
+    grad_verts[2 * V + v] = (P[2] * gu + P[6] * gv) + P[10] * gww;
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+int64_t raster_tiles(int width, int height) {
+  return (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+}
+
+hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
+                                 const RasterCam& cam, float* image, int32_t* face_id, void* rec, hipStream_t st) {
+  if (T > 0) {
+    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(verts, V, faces, T, cam,
+                                                                                      (FaceRec*)rec);
+  }
+  const int tiles_x = (cam.width + kTile - 1) / kTile;
+  k_raster_tiles<<<(unsigned)raster_tiles(cam.width, cam.height), SHV_BLOCK, 0, st>>>(
+      (const FaceRec*)rec, T, faces, radiance, cam.width, cam.height, tiles_x, image, face_id);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_backward(const float* grad_image, const float* verts, int64_t V, const int32_t* faces,
+                                  int64_t T, const float* radiance, const RasterCam& cam, const int32_t* face_id,
+                                  const int32_t* inc_ptr, const int32_t* inc, float* grad_radiance,
+                                  float* grad_verts, void* rec, float* part, hipStream_t st) {
+  if (T > 0) {
+    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(verts, V, faces, T, cam,
+                                                                                      (FaceRec*)rec);
+    k_raster_face_grads<<<(unsigned)((T + SHV_WAVES_PER_BLOCK - 1) / SHV_WAVES_PER_BLOCK), SHV_BLOCK, 0, st>>>(
+        (const FaceRec*)rec, T, faces, radiance, grad_image, face_id, cam.width, part);
+  }
+  if (V > 0) {
+    k_raster_vertex_grads<<<(unsigned)((V + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
+        verts, V, T, cam, inc_ptr, inc, part, grad_radiance, grad_verts);
+  }
+  return hipGetLastError();
+}
+
+size_t raster_record_bytes(int64_t T) { return (size_t)T * sizeof(FaceRec); }
+
+}  // namespace shv

@@ -408,3 +408,97 @@ def envmap_image(seed=0, C=3, H=256, W=512, suns=3):
         for c in range(C):
             img[c] += power[c] * np.exp(-ang2 / (2.0 * width * width))
     return _f32(img)
+
+
+def capsule_mesh(a, b, R, segments, spacing):
+    """Triangulated capsule around the segment a-b: two hemispherical caps
+    and a cylinder, rings of ``segments`` vertices about every ``spacing`` of
+    arc length, a vertex at each pole.  Returns (vertices, outward normals,
+    faces), faces wound counter-clockwise seen from outside."""
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    axis = b - a
+    ln = np.linalg.norm(axis)
+    ez = axis / ln
+    tmp = np.array([1.0, 0, 0]) if abs(ez[0]) < 0.9 else np.array([0, 1.0, 0])
+    ex = np.cross(ez, tmp)
+    ex /= np.linalg.norm(ex)
+    ey = np.cross(ez, ex)
+    n_cap = max(2, int(round(0.5 * np.pi * R / spacing)))
+    n_cyl = max(1, int(round(ln / spacing)))
+    # rings from the pole at a to the pole at b: (centre, polar angle from -ez)
+    rings = []
+    for k in range(1, n_cap + 1):
+        th = 0.5 * np.pi * k / n_cap                      # 0 at the pole of a, pi/2 at the equator
+        rings.append((a, th))
+    for k in range(1, n_cyl):
+        rings.append((a + axis * k / n_cyl, 0.5 * np.pi))
+    for k in range(n_cap, 0, -1):
+        rings.append((b, np.pi - 0.5 * np.pi * k / n_cap))
+    phi = 2 * np.pi * np.arange(segments) / segments
+    ring_dir = np.cos(phi)[:, None] * ex + np.sin(phi)[:, None] * ey
+    verts, nrms = [a - R * ez], [-ez]
+    for c, th in rings:
+        n = -np.cos(th) * ez + np.sin(th) * ring_dir
+        verts.extend(c + R * n)
+        nrms.extend(n)
+    verts.append(b + R * ez)
+    nrms.append(ez)
+    faces = []
+    first = 1
+    for s in range(segments):
+        faces.append((0, first + (s + 1) % segments, first + s))
+    for r in range(len(rings) - 1):
+        o0, o1 = 1 + r * segments, 1 + (r + 1) * segments
+        for s in range(segments):
+            s1 = (s + 1) % segments
+            faces.append((o0 + s, o0 + s1, o1 + s1))
+            faces.append((o0 + s, o1 + s1, o1 + s))
+    top, last = len(verts) - 1, 1 + (len(rings) - 1) * segments
+    for s in range(segments):
+        faces.append((last + s, last + (s + 1) % segments, top))
+    return np.array(verts), np.array(nrms), np.array(faces, np.int64)
+
+
+def look_at_camera(eye, target, up, f, width, height):
+    """3 x 4 pinhole projection: pixel x to the right, y down, depth along
+    the view direction; principal point at the image centre."""
+    eye, target, up = (np.asarray(v, float) for v in (eye, target, up))
+    fwd = target - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, up)
+    right /= np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    Rm = np.stack([right, down, fwd])
+    K = np.array([[f, 0, width / 2.0], [0, f, height / 2.0], [0, 0, 1.0]])
+    return K @ np.concatenate([Rm, (-Rm @ eye)[:, None]], 1)
+
+
+def scene_mesh_body(seed=0, segments=24, spacing=None, n_bands=8, width=512, height=512):
+    """The body scene as a triangle mesh: every capsule tessellated
+    (capsule_mesh, 24 azimuths, rings about 1 cm of arc apart: 21,288
+    vertices and 42,480 triangles), the same 128 spheres; the vertices are the
+    receivers (lifted by the shadow bias).  A camera 4 m in front of the body
+    looking at its middle frames it in a width x height image.  Draw order
+    (one rng): light, albedo, image cotangent."""
+    caps = body_capsules()
+    spacing = 0.0102 if spacing is None else spacing
+    V, N, F = [], [], []
+    for _, a, b, R in caps:
+        v, n, f = capsule_mesh(a, b, R, segments, spacing)
+        F.append(f + sum(len(x) for x in V))
+        V.append(v)
+        N.append(n)
+    verts, nrm, faces = np.concatenate(V), np.concatenate(N), np.concatenate(F)
+    verts = verts + SHADOW_BIAS * nrm
+    spheres = scene_body(seed, P=1, n_bands=n_bands)["spheres"]
+    rng = np.random.default_rng(seed)
+    light = draw_light(rng, n_bands)
+    albedo = draw_albedo(rng, len(verts))
+    lo, hi = verts.min(0), verts.max(0)
+    mid = (lo + hi) / 2
+    f = 0.9 * height * 4.0 / (hi[2] - lo[2])
+    P = look_at_camera(mid + np.array([0.0, 4.0, 0.0]), mid, (0, 0, 1), f, width, height)
+    gI = rng.standard_normal((height, width))
+    return dict(points=_f32(verts), normals=_f32(nrm), albedo=_f32(albedo), spheres=_f32(spheres),
+                light=_f32(light), n_bands=n_bands, faces=faces.astype(np.int32), camera=_f32(P),
+                width=width, height=height, grad_image=_f32(gI))

@@ -251,3 +251,29 @@ def test_taylor_flags_and_saved_sizes(L):
         assert L.shv_saved_floats(100, prm) == (1 + (2 + K) * 16) * 100
         assert L.shv_workspace_bytes(100, 7, prm) == L.shv_workspace_bytes(100, 7, L.params(4, 3.0, 2))
     assert L.shv_saved_floats(100, L.params(4, 3.0, 2, L.SHV_FLAG_EXP_PRODUCT)) == 0
+
+
+def test_raster_incidence_and_argument_checks(L):
+    import ctypes
+    import numpy as np
+    rng = np.random.default_rng(0)
+    V, T = 50, 80
+    faces = rng.integers(0, V, size=(T, 3)).astype(np.int32)
+    ptr = np.zeros(V + 1, np.int32)
+    idx = np.zeros(3 * T, np.int32)
+    L.shv_raster_incidence_build(faces, T, V, ptr, idx)
+    flat = faces.reshape(-1)
+    order = np.argsort(flat, kind="stable")                 # corners grouped by vertex, in corner order
+    assert np.array_equal(idx, order.astype(np.int32))
+    assert np.array_equal(ptr, np.concatenate([[0], np.cumsum(np.bincount(flat, minlength=V))]).astype(np.int32))
+    bad = faces.copy()
+    bad[7, 1] = V
+    with pytest.raises(RuntimeError):
+        L.shv_raster_incidence_build(bad, T, V, ptr, idx)
+    assert L.shv_raster_workspace_bytes(V, T) >= T * (64 + 48)
+    assert L.shv_raster_workspace_bytes(-1, T) == 0
+    f = L.raw("sh_raster_forward")
+    cam = L.camera(np.zeros((3, 4)), 0, 10)
+    assert f(None, 3, None, 1, None, ctypes.byref(cam), None, None, None, 0, None) == L.SHV_ERR_INVALID_ARG
+    cam = L.camera(np.full((3, 4), np.nan), 8, 8)
+    assert f(None, 3, None, 1, None, ctypes.byref(cam), None, None, None, 0, None) == L.SHV_ERR_INVALID_ARG
