@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="body",
-                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap", "inverse"])
+                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap", "inverse",
+                             "image"])
     ap.add_argument("--channels", type=int, default=3, help="rgb / envmap: colour channels")
     ap.add_argument("--map", default="512x1024", help="envmap: H x W of the equirectangular map")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -604,6 +605,56 @@ def bench_inverse(args):
     }
 
 
+def bench_image(args):
+    """One gradient-descent iteration of the image-space inverse problem
+    (Eqs. 14-16): the mesh body scene rendered and rasterised at 512 x 512."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import inverse, ops, workmodel
+
+    sc = scenegen.scene_mesh_body()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    n, k = int(sc["n_bands"]), args.k
+    P, S = sc["points"].shape[0], sc["spheres"].shape[0]
+    W, H, T = sc["width"], sc["height"], len(sc["faces"])
+    K = int(np.ceil(4 * P / S))
+    cam = (sc["camera"], W, H)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        graph = inverse.DeformGraph(sc["points"], sc["normals"], sc["spheres"], K, dev)
+        rng = np.random.default_rng(0)
+        true = np.zeros((S + 1, 6), np.float32)
+        true[:S, :3] = rng.standard_normal((S, 3)) * 0.1
+        true[:S, 3:] = rng.standard_normal((S, 3)) * 0.01
+        make = inverse.InverseProblem(graph, sc["albedo"], sc["light"], np.zeros((H, W), np.float32), n, lr=0.0,
+                                      init=true, n_squarings=k, faces=sc["faces"], camera=cam)
+        make.step()
+        target = make.raster["image"].clone()
+        ip = inverse.InverseProblem(graph, sc["albedo"], sc["light"], target, n, lr=1e-2, n_squarings=k,
+                                    faces=sc["faces"], camera=cam)
+    torch.cuda.synchronize()
+    ms, prof = timed(ip.step, stream, args.warmup, args.steps, True)
+    kernels = kernel_table(prof)
+    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
+    if roof is not None:
+        roof["traffic"] = measured_traffic("image", roof["kernel"])
+    return {
+        "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"image-space inverse problem on the mesh body scene: {P} vertices ({T} triangles) x "
+                               f"{S} spheres, 8 bands, k={k}, {W} x {H} image; one gradient-descent iteration "
+                               f"(deformation with K={K}, render, rasterise, image loss, adjoints, update)",
+                   "receivers": P, "spheres": S, "triangles": T, "image": [H, W], "n_bands": n, "n_squarings": k,
+                   "K": K, "iterations_per_s": 1e3 / ms, "lr": 1e-2},
+        "roofline": roof, "cpu_baseline": None, "kernels": finish_kernels(kernels),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -620,6 +671,8 @@ def main():
         out = bench_envmap(args)
     elif args.workload == "inverse":
         out = bench_inverse(args)
+    elif args.workload == "image":
+        out = bench_image(args)
     else:
         out = bench_single(args)
     print(json.dumps(out))

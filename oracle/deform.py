@@ -131,3 +131,31 @@ def render_loss(params, scene, idx, w, target, n_bands: int, eps: float = 3.0, n
     r = out["B"] - torch.as_tensor(target).to(DT)
     loss = (r * r).mean()
     return loss.detach(), torch.autograd.grad(loss, p)[0]
+
+
+def image_loss(params, scene, idx, w, target_image, n_bands: int, eps: float = 3.0, n_squarings: int = 4,
+               raster_positions: bool = True):
+    """The inverse problem of Sec. 3.5 on the image (Eqs. 14-16): the
+    deformed mesh's vertex radiance (method.forward) is rasterised
+    (raster.render's rules; ``scene`` holds faces, camera, width, height) and
+    L(theta) = mean over pixels of (I_R - target)^2.  The face of each pixel
+    is decided from the deformed vertices rounded to FP32.  With
+    ``raster_positions`` False the rasteriser's dependence on the vertex
+    positions is cut (gradients through the radiance only).  Returns (loss,
+    d loss / d params, face ids) in FP64."""
+    import numpy as np
+
+    from . import method, raster
+    v, m, s = (torch.as_tensor(scene[k]).to(DT) for k in ("points", "normals", "spheres"))
+    p = torch.as_tensor(params).to(DT).clone().requires_grad_(True)
+    x, n, c = deform(p, v, m, s, torch.as_tensor(idx), torch.as_tensor(w).to(DT))
+    B = method.forward(x, n, torch.as_tensor(scene["albedo"]).to(DT), c, torch.as_tensor(scene["light"]).to(DT),
+                       n_bands, eps, n_squarings)["B"]
+    cam = np.asarray(scene["camera"], np.float32)
+    fid = raster.rasterize_ids(x.detach().numpy().astype(np.float32), scene["faces"], cam, scene["width"],
+                               scene["height"])
+    xr = x if raster_positions else x.detach()
+    img = raster.shade_pixels(xr, scene["faces"], B, torch.as_tensor(cam).to(DT), fid)
+    r = img - torch.as_tensor(target_image).to(DT)
+    loss = (r * r).mean()
+    return loss.detach(), torch.autograd.grad(loss, p)[0], fid

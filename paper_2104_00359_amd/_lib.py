@@ -124,7 +124,7 @@ _sig = {
     "shv_deform_graph_build": (ctypes.c_int32, [_P, _I64, _P, _I64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "shv_deform_workspace_bytes": (_SZ, [_I64, _I64]),
     "shv_raster_incidence_build": (ctypes.c_int32, [_P, _I64, _I64, _P, _P]),
-    "shv_raster_workspace_bytes": (_SZ, [_I64, _I64]),
+    "shv_raster_workspace_bytes": (_SZ, [_I64, _I64, ctypes.c_int32, ctypes.c_int32]),
     "sh_raster_forward": (ctypes.c_int32, [_P, _I64, _P, _I64, _P, ctypes.POINTER(shv_camera), _P, _P, _P, _SZ, _P]),
     "sh_raster_backward": (ctypes.c_int32, [_P, _P, _I64, _P, _I64, _P, ctypes.POINTER(shv_camera), _P, _P, _P, _P,
                                             _P, _P, _SZ, _P]),
@@ -258,8 +258,8 @@ def shv_raster_incidence_build(faces, T, V, inc_ptr, inc_idx):
            "shv_raster_incidence_build")
 
 
-def shv_raster_workspace_bytes(V: int, T: int) -> int:
-    return int(_lib.shv_raster_workspace_bytes(int(V), int(T)))
+def shv_raster_workspace_bytes(V: int, T: int, width: int, height: int) -> int:
+    return int(_lib.shv_raster_workspace_bytes(int(V), int(T), int(width), int(height)))
 
 
 def sh_raster_forward(vertices, V, faces, T, radiance, cam, image, face_id, ws, ws_bytes, stream):

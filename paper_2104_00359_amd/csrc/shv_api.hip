@@ -732,9 +732,12 @@ shv_status shv_raster_incidence_build(const int32_t* faces, int64_t T, int64_t V
   return SHV_OK;
 }
 
-size_t shv_raster_workspace_bytes(int64_t V, int64_t T) {
-  if (V < 0 || T < 0 || 3 * T >= ((int64_t)1 << 31)) return 0;
-  return align_up(shv::raster_record_bytes(T)) + align_up((size_t)T * 12 * 4);
+size_t shv_raster_workspace_bytes(int64_t V, int64_t T, int32_t width, int32_t height) {
+  if (V < 0 || T < 0 || 3 * T >= ((int64_t)1 << 31) || width < 1 || height < 1 || width > SHV_MAX_IMAGE_SIDE ||
+      height > SHV_MAX_IMAGE_SIDE)
+    return 0;
+  return align_up(shv::raster_record_bytes(T)) +
+         std::max(align_up((size_t)T * 12 * 4), align_up(shv::raster_bin_bytes(T, width, height)));
 }
 
 shv_status sh_raster_forward(const float* vertices, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
@@ -751,9 +754,10 @@ shv_status sh_raster_forward(const float* vertices, int64_t V, const int32_t* fa
     SHV_TRY(need(faces, "faces"));
     SHV_TRY(need(radiance, "radiance"));
   }
-  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T)));
+  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T, rc.width, rc.height)));
+  void* bins = (char*)ws + align_up(shv::raster_record_bytes(T));
   SHV_TRY(launch("raster_fwd", stream, [&] {
-    return shv::launch_raster_forward(vertices, V, faces, T, radiance, rc, image, face_id, ws, stream);
+    return shv::launch_raster_forward(vertices, V, faces, T, radiance, rc, image, face_id, ws, bins, stream);
   }));
   return SHV_OK;
 }
@@ -776,7 +780,7 @@ shv_status sh_raster_backward(const float* grad_image, const float* vertices, in
     SHV_TRY(need(face_id, "face_id"));
     SHV_TRY(need(inc_idx, "inc_idx"));
   }
-  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T)));
+  SHV_TRY(check_ws(ws, ws_bytes, shv_raster_workspace_bytes(V, T, rc.width, rc.height)));
   float* part = (float*)((char*)ws + align_up(shv::raster_record_bytes(T)));
   SHV_TRY(launch("raster_bwd", stream, [&] {
     return shv::launch_raster_backward(grad_image, vertices, V, faces, T, radiance, rc, face_id, inc_ptr, inc_idx,

@@ -149,16 +149,18 @@ hipError_t batch_exp_bwd_nb(const void* table, bool four, int64_t blocks, hipStr
 
 bool exp_four_waves(int64_t P, uint32_t flags);
 
-// Rasteriser (the camera as in shv_camera).  rec is scratch of raster_record_bytes(T); part of
-// 12 T floats (per-face corner cotangents).
+// Rasteriser (the camera as in shv_camera).  rec is scratch of raster_record_bytes(T); bins of
+// raster_bin_bytes (forward); part of 12 T floats (per-face corner cotangents, backward).
 struct RasterCam {
   float P[12];
   int width, height;
 };
 size_t raster_record_bytes(int64_t T);
+size_t raster_bin_bytes(int64_t T, int width, int height);  // forward scratch after the records
 int64_t raster_tiles(int width, int height);
 hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
-                                 const RasterCam& cam, float* image, int32_t* face_id, void* rec, hipStream_t st);
+                                 const RasterCam& cam, float* image, int32_t* face_id, void* rec, void* bins,
+                                 hipStream_t st);
 hipError_t launch_raster_backward(const float* grad_image, const float* verts, int64_t V, const int32_t* faces,
                                   int64_t T, const float* radiance, const RasterCam& cam, const int32_t* face_id,
                                   const int32_t* inc_ptr, const int32_t* inc, float* grad_radiance,

@@ -15,10 +15,17 @@
 //
 // Forward: a setup pass writes one record per face (projected corners,
 // depths, area, pixel bounding box; faces behind the camera, degenerate or
-// with an index outside [0, V) get an empty box).  Then one block per 16 x 16
-// pixel tile walks the faces in index order in chunks of 256: the chunk's
-// records are staged in LDS, the ones whose box meets the tile are compacted
-// (in order) and every thread tests its pixel against them.
+// with an index outside [0, V) get an empty box) and counts, per 8 x 8
+// pixel tile, the faces whose box meets it; faces meeting more than
+// kMaxBinTiles tiles go to one shared list instead.  A scan turns the counts
+// into offsets and a binning pass writes each tile's face list (integer
+// atomics: the order within a list varies from run to run).  Then one wave
+// per (tile, chunk of 64 entries of its list and the shared list) tests its
+// 8 x 8 pixels against the chunk's faces, staged in LDS, and merges each
+// pixel's smallest (depth, face index) pair into a 64-bit depth buffer with
+// an atomic; the result does not depend on the order of the lists or of the
+// merges.  A per-pixel pass then writes the face and the interpolated
+// radiance.
 //
 // Adjoint (through the winning triangle's weights; which triangle wins is
 // piecewise constant): one wave per face walks the face's bounding box, takes
@@ -41,7 +48,9 @@
 namespace shv {
 
 constexpr float kRasterMinW = 1e-6f;
-constexpr int kTile = 16;
+constexpr int kTile = 8;                 // one wave per 8 x 8 tile
+constexpr int kTileThreads = kTile * kTile;
+constexpr int kMaxBinTiles = 16;
 
 struct alignas(16) FaceRec {
   float x[3], y[3], w[3], area;
@@ -68,9 +77,24 @@ __device__ __forceinline__ int clamp_floor(float v, int lo, int hi) {
   return (int)floorf(v);
 }
 
+// Tile range of a record's box; false for an empty box.
+__device__ __forceinline__ bool tile_range(const FaceRec& r, int& tx0, int& tx1, int& ty0, int& ty1) {
+  if (r.i0 > r.i1 || r.j0 > r.j1) return false;
+  tx0 = r.i0 / kTile;
+  tx1 = r.i1 / kTile;
+  ty0 = r.j0 / kTile;
+  ty1 = r.j1 / kTile;
+  return true;
+}
+
+// With counts != NULL also bins: counts[tile] += 1 for each tile a binned
+// face meets; a face meeting more tiles is appended to big_list.
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restrict__ verts, int64_t V,
                                                             const int32_t* __restrict__ faces, int64_t T,
-                                                            RasterCam cam, FaceRec* __restrict__ rec) {
+                                                            RasterCam cam, FaceRec* __restrict__ rec,
+                                                            int tiles_x, int32_t* __restrict__ counts,
+                                                            int32_t* __restrict__ big_count,
+                                                            int32_t* __restrict__ big_list) {
   const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   if (f >= T) return;
   FaceRec r;
@@ -108,77 +132,161 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
     if (xmax < -1.0f || ymax < -1.0f) r.i1 = -1;
   }
   rec[f] = r;
+  int tx0, tx1, ty0, ty1;
+  if (counts && tile_range(r, tx0, tx1, ty0, ty1)) {
+    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) {
+      big_list[atomicAdd(big_count, 1)] = (int32_t)f;
+    } else {
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&counts[ty * tiles_x + tx], 1);
+    }
+  }
+}
+
+// Exclusive scan of the tile counts into offsets[0 .. n] (one block), and the
+// binning cursors.
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __restrict__ counts, int n,
+                                                           int32_t* __restrict__ offsets,
+                                                           int32_t* __restrict__ cursor) {
+  __shared__ int32_t part[SHV_BLOCK];
+  const int per = (n + SHV_BLOCK - 1) / SHV_BLOCK;
+  const int b = threadIdx.x * per, e = min(n, b + per);
+  int32_t sum = 0;
+  for (int t = b; t < e; ++t) sum += counts[t];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < SHV_BLOCK; ++w) {
+      const int32_t c = part[w];
+      part[w] = run;
+      run += c;
+    }
+    offsets[n] = run;
+  }
+  __syncthreads();
+  int32_t run = part[threadIdx.x];
+  for (int t = b; t < e; ++t) {
+    offsets[t] = run;
+    cursor[t] = run;
+    run += counts[t];
+  }
+}
+
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_bin(const FaceRec* __restrict__ rec, int64_t T, int tiles_x,
+                                                          int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+  const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (f >= T) return;
+  const FaceRec r = rec[f];
+  int tx0, tx1, ty0, ty1;
+  if (!tile_range(r, tx0, tx1, ty0, ty1) || (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) return;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) list[atomicAdd(&cursor[ty * tiles_x + tx], 1)] = (int32_t)f;
 }
 
 struct RasterShared {
-  FaceRec recs[SHV_BLOCK];
-  int32_t list[SHV_BLOCK];
-  int32_t wave_count[SHV_WAVES_PER_BLOCK];
+  FaceRec recs[kTileThreads];
+  int32_t ids[kTileThreads];
 };
 
-__global__ __launch_bounds__(SHV_BLOCK) void k_raster_tiles(const FaceRec* __restrict__ rec, int64_t T,
-                                                            const int32_t* __restrict__ faces,
-                                                            const float* __restrict__ radiance, int width,
-                                                            int height, int tiles_x, float* __restrict__ image,
-                                                            int32_t* __restrict__ face_id) {
+// Coverage and depth of one pixel centre for one face: false if the face does
+// not cover it; else its weights' numerators l0, l1, l2 and the depth z.
+__device__ __forceinline__ bool cover(const FaceRec& r, int i, int j, float px, float py, float& l0, float& l1,
+                                      float& l2, float& z) {
+  if (i < r.i0 || i > r.i1 || j < r.j0 || j > r.j1) return false;
+  const float e0 = edge_fn(r.x[1], r.y[1], r.x[2], r.y[2], px, py);
+  const float e1 = edge_fn(r.x[2], r.y[2], r.x[0], r.y[0], px, py);
+  const float e2 = edge_fn(r.x[0], r.y[0], r.x[1], r.y[1], px, py);
+  // Exact early rejection: an edge value of the opposite sign to the area and
+  // above 2^-100 |area| in magnitude has a quotient by the area below
+  // -2^-101, strictly negative (no underflow to -0), so the coverage test
+  // below fails for it too.
+  const float sg = r.area > 0.0f ? 1.0f : -1.0f;
+  const float thr = -(fabsf(r.area) * 0x1p-100f);
+  if (sg * e0 < thr || sg * e1 < thr || sg * e2 < thr) return false;
+  l0 = e0 / r.area;
+  l1 = e1 / r.area;
+  l2 = e2 / r.area;
+  if (!(l0 >= 0.0f && l1 >= 0.0f && l2 >= 0.0f)) return false;
+  z = 1.0f / ((l0 / r.w[0] + l1 / r.w[1]) + l2 / r.w[2]);
+  return true;
+}
+
+// One wave per (tile, chunk of 64 list entries), chunks y, y + gridDim.y, ...
+// of the tile's list followed by the shared list.  Each lane keeps its
+// pixel's smallest (depth, face) and merges it into zbuf with one atomic
+// max of the bit-inverted key (depth bits above the face index: positive
+// floats order like their bits), which is the lexicographic minimum whatever
+// the order of the merges.
+__global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __restrict__ rec,
+                                                              const int32_t* __restrict__ offsets,
+                                                              const int32_t* __restrict__ list,
+                                                              const int32_t* __restrict__ big_count,
+                                                              const int32_t* __restrict__ big_list, int width,
+                                                              int height, int tiles_x,
+                                                              unsigned long long* __restrict__ zbuf) {
   __shared__ RasterShared sh;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tile = blockIdx.x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int ti0 = tx * kTile, tj0 = ty * kTile;
   const int ti1 = min(ti0 + kTile, width) - 1, tj1 = min(tj0 + kTile, height) - 1;
   const int i = ti0 + (threadIdx.x % kTile), j = tj0 + (threadIdx.x / kTile);
   const float px = (float)i + 0.5f, py = (float)j + 0.5f;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float best_z = INFINITY;
-  int32_t best_f = -1;
-  float bl0 = 0.0f, bl1 = 0.0f, bl2 = 0.0f;
-  for (int64_t c0 = 0; c0 < T; c0 += SHV_BLOCK) {
-    const int64_t f = c0 + threadIdx.x;
-    bool hit = false;
-    if (f < T) {
+  const int lane = threadIdx.x;
+  const int b0 = offsets[tile], nb = offsets[tile + 1] - b0;
+  const int n = nb + *big_count;
+  unsigned long long best = 0ull;  // inverted key: 0 = nothing
+  for (int c0 = (int)blockIdx.y * kTileThreads; c0 < n; c0 += (int)gridDim.y * kTileThreads) {
+    const int e = c0 + lane;
+    bool meets = false;
+    if (e < n) {
+      const int32_t f = e < nb ? list[b0 + e] : big_list[e - nb];
       const FaceRec r = rec[f];
-      sh.recs[threadIdx.x] = r;
-      hit = r.i0 <= r.i1 && r.j0 <= r.j1 && r.i0 <= ti1 && r.i1 >= ti0 && r.j0 <= tj1 && r.j1 >= tj0;
+      sh.ids[lane] = f;
+      sh.recs[lane] = r;
+      meets = r.i0 <= ti1 && r.i1 >= ti0 && r.j0 <= tj1 && r.j1 >= tj0;
     }
-    // compact the chunk's faces that meet the tile, keeping index order
-    const uint64_t m = __ballot(hit);
-    if (lane == 0) sh.wave_count[wave] = __popcll(m);
+    uint64_t mask = __ballot(meets);
     __syncthreads();
-    int base = 0, total = 0;
-    for (int w = 0; w < SHV_WAVES_PER_BLOCK; ++w) {
-      if (w < wave) base += sh.wave_count[w];
-      total += sh.wave_count[w];
-    }
-    if (hit) sh.list[base + __popcll(m & ((1ull << lane) - 1ull))] = threadIdx.x;
-    __syncthreads();
-    for (int n = 0; n < total; ++n) {
-      const FaceRec& r = sh.recs[sh.list[n]];
-      if (i < r.i0 || i > r.i1 || j < r.j0 || j > r.j1) continue;
-      const float l0 = edge_fn(r.x[1], r.y[1], r.x[2], r.y[2], px, py) / r.area;
-      const float l1 = edge_fn(r.x[2], r.y[2], r.x[0], r.y[0], px, py) / r.area;
-      const float l2 = edge_fn(r.x[0], r.y[0], r.x[1], r.y[1], px, py) / r.area;
-      if (!(l0 >= 0.0f && l1 >= 0.0f && l2 >= 0.0f)) continue;
-      const float z = 1.0f / ((l0 / r.w[0] + l1 / r.w[1]) + l2 / r.w[2]);
-      if (z < best_z) {
-        best_z = z;
-        best_f = (int32_t)(c0 + sh.list[n]);
-        bl0 = l0;
-        bl1 = l1;
-        bl2 = l2;
-      }
+    while (mask) {
+      const int k = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      float l0, l1, l2, z;
+      if (!cover(sh.recs[k], i, j, px, py, l0, l1, l2, z)) continue;
+      const unsigned long long key =
+          ~(((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)(uint32_t)sh.ids[k]);
+      best = key > best ? key : best;
     }
     __syncthreads();  // the chunk's records are no longer read
   }
-  if (i > ti1 || j > tj1) return;
-  const int64_t pix = (int64_t)j * width + i;
-  face_id[pix] = best_f;
+  if (best != 0ull && i <= ti1 && j <= tj1) atomicMax(&zbuf[(int64_t)j * width + i], best);
+}
+
+// Per pixel: the winning face from the depth buffer, its weights again (the
+// same operations as the coverage test) and the interpolated radiance.
+__global__ __launch_bounds__(SHV_BLOCK) void k_raster_resolve(const FaceRec* __restrict__ rec,
+                                                              const unsigned long long* __restrict__ zbuf,
+                                                              const int32_t* __restrict__ faces,
+                                                              const float* __restrict__ radiance, int width,
+                                                              int64_t npix, float* __restrict__ image,
+                                                              int32_t* __restrict__ face_id) {
+  const int64_t pix = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  if (pix >= npix) return;
+  const unsigned long long key = zbuf[pix];
+  int32_t f = -1;
   float val = 0.0f;
-  if (best_f >= 0) {
-    const FaceRec r = rec[best_f];
-    const float q0 = bl0 / r.w[0], q1 = bl1 / r.w[1], q2 = bl2 / r.w[2];
+  if (key != 0ull) {
+    f = (int32_t)(uint32_t)(~key & 0xffffffffull);
+    const int i = (int)(pix % width), j = (int)(pix / width);
+    const FaceRec r = rec[f];
+    float l0 = 0.0f, l1 = 0.0f, l2 = 0.0f, z;
+    cover(r, i, j, (float)i + 0.5f, (float)j + 0.5f, l0, l1, l2, z);
+    const float q0 = l0 / r.w[0], q1 = l1 / r.w[1], q2 = l2 / r.w[2];
     const float Q = (q0 + q1) + q2;
-    const int32_t* fv = faces + 3 * (int64_t)best_f;
+    const int32_t* fv = faces + 3 * (int64_t)f;
     val = ((q0 * radiance[fv[0]] + q1 * radiance[fv[1]]) + q2 * radiance[fv[2]]) / Q;
   }
+  face_id[pix] = f;
   image[pix] = val;
 }
 
@@ -308,15 +416,47 @@ int64_t raster_tiles(int width, int height) {
   return (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
 }
 
+// Forward scratch after the face records: the depth buffer (one 64-bit key
+// per pixel), counts, offsets and cursors ([tiles + 1] each), the shared-list
+// count, the tile lists (kMaxBinTiles entries per face at most) and the
+// shared list (one per face at most).
+size_t raster_bin_bytes(int64_t T, int width, int height) {
+  const int64_t tiles = raster_tiles(width, height);
+  return (size_t)width * height * 8 + (size_t)(3 * (tiles + 1) + 1 + (kMaxBinTiles + 1) * T) * 4;
+}
+
+constexpr int kZbufSplit = 8;  // waves per tile (chunks of 64 list entries each)
+
 hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
-                                 const RasterCam& cam, float* image, int32_t* face_id, void* rec, hipStream_t st) {
-  if (T > 0) {
-    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(verts, V, faces, T, cam,
-                                                                                      (FaceRec*)rec);
-  }
+                                 const RasterCam& cam, float* image, int32_t* face_id, void* rec, void* bins,
+                                 hipStream_t st) {
   const int tiles_x = (cam.width + kTile - 1) / kTile;
-  k_raster_tiles<<<(unsigned)raster_tiles(cam.width, cam.height), SHV_BLOCK, 0, st>>>(
-      (const FaceRec*)rec, T, faces, radiance, cam.width, cam.height, tiles_x, image, face_id);
+  const int64_t tiles = raster_tiles(cam.width, cam.height);
+  const int64_t npix = (int64_t)cam.width * cam.height;
+  unsigned long long* zbuf = (unsigned long long*)bins;
+  int32_t* counts = (int32_t*)(zbuf + npix);
+  int32_t* offsets = counts + (tiles + 1);
+  int32_t* cursor = offsets + (tiles + 1);
+  int32_t* big_count = cursor + (tiles + 1);
+  int32_t* list = big_count + 1;
+  int32_t* big_list = list + kMaxBinTiles * T;
+  // zero the depth buffer, the counts and the shared-list count (a fill
+  // kernel, also under stream capture)
+  hipError_t e = launch_fill_zero((float*)zbuf, 2 * npix + (tiles + 1), st);
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero((float*)big_count, 1, st);
+  if (e != hipSuccess) return e;
+  if (T > 0) {
+    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
+        verts, V, faces, T, cam, (FaceRec*)rec, tiles_x, counts, big_count, big_list);
+    k_raster_scan<<<1, SHV_BLOCK, 0, st>>>(counts, (int)tiles, offsets, cursor);
+    k_raster_bin<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>((const FaceRec*)rec, T, tiles_x,
+                                                                                    cursor, list);
+    k_raster_zbuf<<<dim3((unsigned)tiles, kZbufSplit), kTileThreads, 0, st>>>(
+        (const FaceRec*)rec, offsets, list, big_count, big_list, cam.width, cam.height, tiles_x, zbuf);
+  }
+  k_raster_resolve<<<(unsigned)((npix + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
+      (const FaceRec*)rec, zbuf, faces, radiance, cam.width, npix, image, face_id);
   return hipGetLastError();
 }
 
@@ -325,8 +465,8 @@ hipError_t launch_raster_backward(const float* grad_image, const float* verts, i
                                   const int32_t* inc_ptr, const int32_t* inc, float* grad_radiance,
                                   float* grad_verts, void* rec, float* part, hipStream_t st) {
   if (T > 0) {
-    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(verts, V, faces, T, cam,
-                                                                                      (FaceRec*)rec);
+    k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
+        verts, V, faces, T, cam, (FaceRec*)rec, 0, nullptr, nullptr, nullptr);
     k_raster_face_grads<<<(unsigned)((T + SHV_WAVES_PER_BLOCK - 1) / SHV_WAVES_PER_BLOCK), SHV_BLOCK, 0, st>>>(
         (const FaceRec*)rec, T, faces, radiance, grad_image, face_id, cam.width, part);
   }

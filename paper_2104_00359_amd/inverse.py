@@ -97,10 +97,16 @@ class InverseProblem:
     """Gradient descent on L(theta) = mean_j (B_j(theta) - target_j)^2 with B
     the rendered radiance of the deformed scene (Sec. 3.5; the paper's step is
     1e-2).  ``albedo`` [P], ``light`` [n_bands^2] and ``target`` [P] are fixed;
-    ``params`` [S + 1, 6] starts at ``init`` (zeros: the template)."""
+    ``params`` [S + 1, 6] starts at ``init`` (zeros: the template).
+
+    With ``faces`` [T, 3] (the template's triangles over its P vertices) and
+    ``camera`` = (P 3 x 4, width, height), the loss is taken on the image
+    instead (Eqs. 14-16): the vertices' radiance is rasterised and L is the
+    mean over pixels of (I_R - target)^2, ``target`` then being the
+    [height, width] reference image."""
 
     def __init__(self, graph: DeformGraph, albedo, light, target, n_bands: int, lr: float = 1e-2, init=None,
-                 eps: float = 3.0, n_squarings: int = 4):
+                 eps: float = 3.0, n_squarings: int = 4, faces=None, camera=None):
         dev = graph.device
         P, S = graph.P, graph.S
         self.graph, self.lr, self.P, self.S = graph, float(lr), P, S
@@ -120,7 +126,24 @@ class InverseProblem:
                                                                                                                device=dev)
         self.loss = torch.zeros(1, device=dev)
         self.ws_r = torch.empty(_lib.shv_workspace_bytes(P, S, self.prm), dtype=torch.uint8, device=dev)
-        self.ws_l = torch.empty(max(_lib.shv_l2_workspace_bytes(P), 256), dtype=torch.uint8, device=dev)
+        self.raster = None
+        n_loss = P
+        if faces is not None:
+            faces = np.ascontiguousarray(np.asarray(faces, np.int32))
+            Pm, width, height = camera
+            T = len(faces)
+            inc_ptr, inc_idx = np.zeros(P + 1, np.int32), np.zeros(max(3 * T, 1), np.int32)
+            _lib.shv_raster_incidence_build(faces, T, P, inc_ptr, inc_idx)
+            nb = _lib.shv_raster_workspace_bytes(P, T, width, height)
+            self.raster = dict(
+                T=T, cam=_lib.camera(np.asarray(Pm, np.float32), width, height),
+                faces=torch.as_tensor(faces).to(dev), inc_ptr=torch.as_tensor(inc_ptr).to(dev),
+                inc_idx=torch.as_tensor(inc_idx).to(dev), image=torch.empty(height, width, device=dev),
+                face_id=torch.empty(height, width, dtype=torch.int32, device=dev),
+                gI=torch.empty(height, width, device=dev), gPr=torch.empty(3, P, device=dev),
+                ws=torch.empty(max(nb, 256), dtype=torch.uint8, device=dev))
+            n_loss = width * height
+        self.ws_l = torch.empty(max(_lib.shv_l2_workspace_bytes(n_loss), 256), dtype=torch.uint8, device=dev)
 
     def step(self):
         """One iteration: loss at the current parameters, then the update.
@@ -129,9 +152,22 @@ class InverseProblem:
         _lib.sh_deform_forward(g.c, self.params, self.pts, self.nrm, self.sph, g.ws, g.ws.numel(), st)
         _lib.sh_render_forward(self.pts, self.nrm, self.albedo, self.sph, self.light, P, S, self.prm, self.vis,
                                self.rad, self.saved, self.ws_r, self.ws_r.numel(), st)
-        _lib.sh_l2_loss(self.rad, self.target, P, self.gB, self.loss, self.ws_l, self.ws_l.numel(), st)
+        r = self.raster
+        if r is None:
+            _lib.sh_l2_loss(self.rad, self.target, P, self.gB, self.loss, self.ws_l, self.ws_l.numel(), st)
+        else:
+            _lib.sh_raster_forward(self.pts, P, r["faces"], r["T"], self.rad, r["cam"], r["image"], r["face_id"],
+                                   r["ws"], r["ws"].numel(), st)
+            _lib.sh_l2_loss(r["image"], self.target, r["image"].numel(), r["gI"], self.loss, self.ws_l,
+                            self.ws_l.numel(), st)
+            _lib.sh_raster_backward(r["gI"], self.pts, P, r["faces"], r["T"], self.rad, r["cam"], r["face_id"],
+                                    r["inc_ptr"], r["inc_idx"], self.gB, r["gPr"], r["ws"], r["ws"].numel(), st)
         _lib.sh_render_backward(self.gB, self.pts, self.nrm, self.albedo, self.sph, P, S, self.prm, self.vis,
                                 self.saved, self.gP, self.gN, None, self.gS, None, self.ws_r, self.ws_r.numel(), st)
+        if r is not None:
+            # the vertices' positions reach the loss through the shading and
+            # through the rasteriser: gP <- gP - (-1) gPr
+            _lib.sh_sgd_step(self.gP, r["gPr"], 3 * P, -1.0, st)
         _lib.sh_deform_backward(g.c, self.params, self.gP, self.gN, self.gS, self.grad, g.ws, g.ws.numel(), st)
         _lib.sh_sgd_step(self.params, self.grad, self.params.numel(), self.lr, st)
 

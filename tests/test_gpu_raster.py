@@ -35,7 +35,7 @@ def run_raster(verts, faces, B, P, width, height, gI, inc_faces=None):
     bt = to_dev(B)
     img = torch.empty(height, width, device=dev)
     fid = torch.empty(height, width, dtype=torch.int32, device=dev)
-    nb = L.shv_raster_workspace_bytes(V, T)
+    nb = L.shv_raster_workspace_bytes(V, T, width, height)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     st = torch.cuda.current_stream().cuda_stream
     L.sh_raster_forward(vt, V, ft, T, bt, cam, img, fid, ws, nb, st)
