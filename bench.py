@@ -106,6 +106,13 @@ def make_scene(name):
     return sc, desc
 
 
+def saved_buffer_floats(lib, P, prm):
+    """Floats of a state buffer that serves both the fused render entry points
+    and the separate visibility ones (whose state grows with the Taylor
+    order), so either path of bench_single can use it."""
+    return max(lib.shv_render_saved_floats(P, prm), lib.shv_saved_floats(P, prm), 1)
+
+
 def cpu_baseline(scenes, k, seconds, exp_mode="squaring"):
     """The FP64 oracle (autograd for the backward) on seeded samples of
     receivers (chunks of 256, all spheres), cycling over ``scenes`` until
@@ -281,7 +288,7 @@ def bench_single(args):
     alb, sph, lig = t(sc["albedo"]), t(sc["spheres"]), t(sc["light"])
     gB = t(sc["grad_radiance"])
     vis = torch.empty(N, P, device=dev)
-    saved = torch.empty(_lib.shv_render_saved_floats(P, prm), device=dev)
+    saved = torch.empty(saved_buffer_floats(_lib, P, prm), device=dev)
     rad = torch.empty(P, device=dev)
     gV = torch.empty(N, P, device=dev)
     gN = torch.empty(3, P, device=dev)

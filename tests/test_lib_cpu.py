@@ -278,3 +278,15 @@ def test_raster_incidence_and_argument_checks(L):
     assert f(None, 3, None, 1, None, ctypes.byref(cam), None, None, None, 0, None) == L.SHV_ERR_INVALID_ARG
     cam = L.camera(np.full((3, 4), np.nan), 8, 8)
     assert f(None, 3, None, 1, None, ctypes.byref(cam), None, None, None, 0, None) == L.SHV_ERR_INVALID_ARG
+
+
+def test_bench_state_buffer_covers_every_mode(L):
+    """The benchmark's state buffer must hold what either path writes, for
+    every flag combination it is run with (the Taylor state grows with K)."""
+    import bench
+    for P in (1, 777, 20000):
+        for flags in (0, 1, 2, 4, 8, 16 | (1 << 8), 16 | (2 << 8), 16 | (8 << 8)):
+            for k in (0, 4, 12):
+                prm = L.params(8, 3.0, k, flags)
+                n = bench.saved_buffer_floats(L, P, prm)
+                assert n >= L.shv_saved_floats(P, prm) and n >= L.shv_render_saved_floats(P, prm)
