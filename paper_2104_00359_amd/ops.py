@@ -106,16 +106,67 @@ def shade_sh(points, normals, albedo, spheres, light, n_bands: int, eps: float =
     return ShadeSH.apply(points, normals, albedo, spheres, light, n_bands, eps, n_squarings)
 
 
-def visibility_sh(points, spheres, n_bands: int, eps: float = 3.0, n_squarings: int = 4):
-    """Visibility SH vectors [P, n_bands^2] (forward only)."""
-    dev = points.device
-    ensure_init(dev)
-    prm = _lib.params(n_bands, eps, n_squarings)
-    P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
-    vis = torch.empty(N, P, dtype=torch.float32, device=dev)
-    ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
-    _lib.sh_visibility_forward(_soa(points), P, _f32(spheres), S, prm, vis, None, ws, ws.numel(), _stream())
-    return vis.t()
+def mode_flags(mode) -> int:
+    """shv_params flags of a way of forming V: "squaring" (the default:
+    scaling, squaring and the linear approximation), "quadrature" (the
+    projected pointwise exponential), "product" (the direct product chain of
+    Eq. 12) or "taylorK" for K = 1..8 (a Taylor series of order K in place of
+    the linear approximation)."""
+    if mode in (None, "squaring"):
+        return 0
+    if mode == "quadrature":
+        return _lib.SHV_FLAG_EXP_QUADRATURE
+    if mode == "product":
+        return _lib.SHV_FLAG_EXP_PRODUCT
+    if isinstance(mode, str) and mode.startswith("taylor") and mode[6:].isdigit():
+        K = int(mode[6:])
+        if 1 <= K <= _lib.SHV_MAX_TAYLOR_ORDER:
+            return _lib.SHV_FLAG_EXP_TAYLOR | _lib.SHV_FLAG_EXP_TAYLOR_ORDER(K)
+    raise ValueError(f"unknown visibility mode {mode!r}")
+
+
+class VisibilitySH(torch.autograd.Function):
+    """Visibility SH vectors through sh_visibility_forward; backward through
+    sh_visibility_backward (gradients for receiver positions and spheres)."""
+
+    @staticmethod
+    def forward(ctx, points, spheres, n_bands, eps, n_squarings, flags):
+        dev = points.device
+        if dev.type != "cuda":
+            raise RuntimeError("visibility_sh runs on the GPU only; move the inputs to a HIP device")
+        ensure_init(dev)
+        prm = _lib.params(n_bands, eps, n_squarings, flags)
+        P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
+        pts, sph = _soa(points), _f32(spheres)
+        vis = torch.empty(N, P, dtype=torch.float32, device=dev)
+        saved = torch.empty(max(_lib.shv_saved_floats(P, prm), 1), dtype=torch.float32, device=dev)
+        ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), _stream())
+        ctx.save_for_backward(pts, sph, vis, saved)
+        ctx.cfg = (n_bands, eps, n_squarings, flags)
+        return vis.t()
+
+    @staticmethod
+    def backward(ctx, grad_vis):
+        pts, sph, vis, saved = ctx.saved_tensors
+        prm = _lib.params(*ctx.cfg)
+        dev = pts.device
+        P, S = pts.shape[1], sph.shape[0]
+        need_p, need_s = ctx.needs_input_grad[:2]
+        if not (need_p or need_s):
+            return None, None, None, None, None, None
+        gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
+        gS = torch.empty(max(S, 1), 4, dtype=torch.float32, device=dev) if need_s else None
+        ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
+        _lib.sh_visibility_backward(_soa(grad_vis), vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), _stream())
+        return (gP.t() if gP is not None else None, gS[:S] if gS is not None else None, None, None, None, None)
+
+
+def visibility_sh(points, spheres, n_bands: int, eps: float = 3.0, n_squarings: int = 4, mode: str = "squaring"):
+    """Visibility SH vectors [P, n_bands^2] of receivers ``points`` [P, 3]
+    occluded by ``spheres`` [S, 4], differentiable with respect to both;
+    ``mode`` selects how V is formed (see mode_flags)."""
+    return VisibilitySH.apply(points, spheres, n_bands, eps, n_squarings, mode_flags(mode))
 
 
 class ShadeSHChannels(torch.autograd.Function):
@@ -124,12 +175,12 @@ class ShadeSHChannels(torch.autograd.Function):
     sh_shade_channels_backward and sh_visibility_backward)."""
 
     @staticmethod
-    def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings):
+    def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings, flags=0):
         dev = points.device
         if dev.type != "cuda":
             raise RuntimeError("shade_sh_channels runs on the GPU only; move the inputs to a HIP device")
         ensure_init(dev)
-        prm = _lib.params(n_bands, eps, n_squarings)
+        prm = _lib.params(n_bands, eps, n_squarings, flags)
         P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
         if light.dim() != 2 or light.shape[1] != N:
             raise ValueError(f"light must be [channels, {N}] for {n_bands} bands, got {tuple(light.shape)}")
@@ -139,20 +190,20 @@ class ShadeSHChannels(torch.autograd.Function):
         pts, nrm = _soa(points), _soa(normals)
         alb, sph, L = _soa(albedo), _f32(spheres), _f32(light)
         vis = torch.empty(N, P, dtype=torch.float32, device=dev)
-        saved = torch.empty(_lib.shv_saved_floats(P, prm), dtype=torch.float32, device=dev)
+        saved = torch.empty(max(_lib.shv_saved_floats(P, prm), 1), dtype=torch.float32, device=dev)
         rad = torch.empty(C, P, dtype=torch.float32, device=dev)
         ws = workspace(dev, max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm)))
         _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), _stream())
         _lib.sh_shade_channels(vis, nrm, alb, L, C, P, prm, rad, ws, ws.numel(), _stream())
         ctx.save_for_backward(pts, nrm, alb, sph, L, vis, saved)
-        ctx.cfg = (n_bands, eps, n_squarings)
+        ctx.cfg = (n_bands, eps, n_squarings, flags)
         return rad.t()
 
     @staticmethod
     def backward(ctx, grad_rad):
         pts, nrm, alb, sph, L, vis, saved = ctx.saved_tensors
-        n_bands, eps, n_squarings = ctx.cfg
-        prm = _lib.params(n_bands, eps, n_squarings)
+        n_bands, eps, n_squarings, flags = ctx.cfg
+        prm = _lib.params(n_bands, eps, n_squarings, flags)
         dev = pts.device
         P, S, N, C = pts.shape[1], sph.shape[0], n_bands * n_bands, L.shape[0]
         gB = _soa(grad_rad)
@@ -169,17 +220,18 @@ class ShadeSHChannels(torch.autograd.Function):
         if need_v:
             _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), _stream())
         return (gP.t() if gP is not None else None, gN.t() if gN is not None else None,
-                gA.t() if gA is not None else None, gS, gL, None, None, None)
+                gA.t() if gA is not None else None, gS, gL, None, None, None, None)
 
 
 def shade_sh_channels(points, normals, albedo, spheres, light, n_bands: int, eps: float = 3.0,
-                      n_squarings: int = 4):
+                      n_squarings: int = 4, mode: str = "squaring"):
     """Radiance [P, C] of C colour channels (e.g. RGB) at receivers ``points``
     [P, 3] with ``normals`` [P, 3] and ``albedo`` [P, C], under one shared
     visibility from ``spheres`` [S, 4], lit by ``light`` [C, n_bands^2] (one
     SH vector per channel; Eq. 8 per channel).  Differentiable with respect to
-    every tensor input."""
-    return ShadeSHChannels.apply(points, normals, albedo, spheres, light, n_bands, eps, n_squarings)
+    every tensor input; ``mode`` selects how V is formed (see mode_flags)."""
+    return ShadeSHChannels.apply(points, normals, albedo, spheres, light, n_bands, eps, n_squarings,
+                                 mode_flags(mode))
 
 
 def envmap_to_sh(image, n_bands: int):
