@@ -17,9 +17,10 @@
 // depths, area, pixel bounding box; faces behind the camera, degenerate or
 // with an index outside [0, V) get an empty box) and counts, per 8 x 8
 // pixel tile, the faces whose box meets it; faces meeting more than
-// kMaxBinTiles tiles go to one shared list instead.  A scan turns the counts
-// into offsets and a binning pass writes each tile's face list (integer
-// atomics: the order within a list varies from run to run).  Then one wave
+// kMaxBinTiles tiles go to one shared list instead.  The counting atomics
+// also give each face its slot in each tile's list; a scan turns the counts
+// into offsets and a binning pass scatters the faces to their slots (the
+// order within a list varies from run to run).  Then one wave
 // per (tile, chunk of 64 entries of its list and the shared list) tests its
 // 8 x 8 pixels against the chunk's faces, staged in LDS, and merges each
 // pixel's smallest (depth, face index) pair into a 64-bit depth buffer with
@@ -88,11 +89,14 @@ __device__ __forceinline__ bool tile_range(const FaceRec& r, int& tx0, int& tx1,
 }
 
 // With counts != NULL also bins: counts[tile] += 1 for each tile a binned
-// face meets; a face meeting more tiles is appended to big_list.
+// face meets, the count before the increment kept as the face's slot in that
+// tile's list (slots[kMaxBinTiles f + k] for its k-th tile, row by row); a
+// face meeting more tiles is appended to big_list.
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restrict__ verts, int64_t V,
                                                             const int32_t* __restrict__ faces, int64_t T,
                                                             RasterCam cam, FaceRec* __restrict__ rec,
                                                             int tiles_x, int32_t* __restrict__ counts,
+                                                            int32_t* __restrict__ slots,
                                                             int32_t* __restrict__ big_count,
                                                             int32_t* __restrict__ big_list) {
   const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
@@ -137,51 +141,52 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
     if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) {
       big_list[atomicAdd(big_count, 1)] = (int32_t)f;
     } else {
+      int k = 0;
       for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&counts[ty * tiles_x + tx], 1);
+        for (int tx = tx0; tx <= tx1; ++tx) slots[kMaxBinTiles * f + k++] = atomicAdd(&counts[ty * tiles_x + tx], 1);
     }
   }
 }
 
-// Exclusive scan of the tile counts into offsets[0 .. n] (one block), and the
-// binning cursors.
+// Exclusive scan of the tile counts into offsets[0 .. n] (one block: each
+// thread sums a contiguous run, the run totals are scanned in LDS in log2
+// steps, then each thread writes its run's offsets).
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __restrict__ counts, int n,
-                                                           int32_t* __restrict__ offsets,
-                                                           int32_t* __restrict__ cursor) {
-  __shared__ int32_t part[SHV_BLOCK];
+                                                           int32_t* __restrict__ offsets) {
+  __shared__ int32_t part[2][SHV_BLOCK];
   const int per = (n + SHV_BLOCK - 1) / SHV_BLOCK;
-  const int b = threadIdx.x * per, e = min(n, b + per);
+  const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
   int32_t sum = 0;
   for (int t = b; t < e; ++t) sum += counts[t];
-  part[threadIdx.x] = sum;
+  int cur = 0;
+  part[0][threadIdx.x] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int w = 0; w < SHV_BLOCK; ++w) {
-      const int32_t c = part[w];
-      part[w] = run;
-      run += c;
-    }
-    offsets[n] = run;
+  for (int d = 1; d < SHV_BLOCK; d <<= 1) {
+    const int32_t v = part[cur][threadIdx.x] + (threadIdx.x >= (unsigned)d ? part[cur][threadIdx.x - d] : 0);
+    part[cur ^ 1][threadIdx.x] = v;
+    cur ^= 1;
+    __syncthreads();
   }
-  __syncthreads();
-  int32_t run = part[threadIdx.x];
+  int32_t run = part[cur][threadIdx.x] - sum;  // exclusive prefix of this thread's run
   for (int t = b; t < e; ++t) {
     offsets[t] = run;
-    cursor[t] = run;
     run += counts[t];
   }
+  if (threadIdx.x == SHV_BLOCK - 1) offsets[n] = part[cur][threadIdx.x];
 }
 
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_bin(const FaceRec* __restrict__ rec, int64_t T, int tiles_x,
-                                                          int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+                                                          const int32_t* __restrict__ offsets,
+                                                          const int32_t* __restrict__ slots,
+                                                          int32_t* __restrict__ list) {
   const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
   if (f >= T) return;
   const FaceRec r = rec[f];
   int tx0, tx1, ty0, ty1;
   if (!tile_range(r, tx0, tx1, ty0, ty1) || (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) return;
+  int k = 0;
   for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) list[atomicAdd(&cursor[ty * tiles_x + tx], 1)] = (int32_t)f;
+    for (int tx = tx0; tx <= tx1; ++tx) list[offsets[ty * tiles_x + tx] + slots[kMaxBinTiles * f + k++]] = (int32_t)f;
 }
 
 struct RasterShared {
@@ -417,12 +422,12 @@ int64_t raster_tiles(int width, int height) {
 }
 
 // Forward scratch after the face records: the depth buffer (one 64-bit key
-// per pixel), counts, offsets and cursors ([tiles + 1] each), the shared-list
-// count, the tile lists (kMaxBinTiles entries per face at most) and the
-// shared list (one per face at most).
+// per pixel), counts and offsets ([tiles + 1] each), the shared-list count,
+// the faces' slots (kMaxBinTiles per face), the tile lists (kMaxBinTiles
+// entries per face at most) and the shared list (one per face at most).
 size_t raster_bin_bytes(int64_t T, int width, int height) {
   const int64_t tiles = raster_tiles(width, height);
-  return (size_t)width * height * 8 + (size_t)(3 * (tiles + 1) + 1 + (kMaxBinTiles + 1) * T) * 4;
+  return (size_t)width * height * 8 + (size_t)(2 * (tiles + 1) + 1 + (2 * kMaxBinTiles + 1) * T) * 4;
 }
 
 constexpr int kZbufSplit = 8;  // waves per tile (chunks of 64 list entries each)
@@ -436,9 +441,9 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
   unsigned long long* zbuf = (unsigned long long*)bins;
   int32_t* counts = (int32_t*)(zbuf + npix);
   int32_t* offsets = counts + (tiles + 1);
-  int32_t* cursor = offsets + (tiles + 1);
-  int32_t* big_count = cursor + (tiles + 1);
-  int32_t* list = big_count + 1;
+  int32_t* big_count = offsets + (tiles + 1);
+  int32_t* slots = big_count + 1;
+  int32_t* list = slots + kMaxBinTiles * T;
   int32_t* big_list = list + kMaxBinTiles * T;
   // zero the depth buffer, the counts and the shared-list count (a fill
   // kernel, also under stream capture)
@@ -448,10 +453,10 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
   if (e != hipSuccess) return e;
   if (T > 0) {
     k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
-        verts, V, faces, T, cam, (FaceRec*)rec, tiles_x, counts, big_count, big_list);
-    k_raster_scan<<<1, SHV_BLOCK, 0, st>>>(counts, (int)tiles, offsets, cursor);
+        verts, V, faces, T, cam, (FaceRec*)rec, tiles_x, counts, slots, big_count, big_list);
+    k_raster_scan<<<1, SHV_BLOCK, 0, st>>>(counts, (int)tiles, offsets);
     k_raster_bin<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>((const FaceRec*)rec, T, tiles_x,
-                                                                                    cursor, list);
+                                                                                    offsets, slots, list);
     k_raster_zbuf<<<dim3((unsigned)tiles, kZbufSplit), kTileThreads, 0, st>>>(
         (const FaceRec*)rec, offsets, list, big_count, big_list, cam.width, cam.height, tiles_x, zbuf);
   }
@@ -466,7 +471,7 @@ hipError_t launch_raster_backward(const float* grad_image, const float* verts, i
                                   float* grad_verts, void* rec, float* part, hipStream_t st) {
   if (T > 0) {
     k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
-        verts, V, faces, T, cam, (FaceRec*)rec, 0, nullptr, nullptr, nullptr);
+        verts, V, faces, T, cam, (FaceRec*)rec, 0, nullptr, nullptr, nullptr, nullptr);
     k_raster_face_grads<<<(unsigned)((T + SHV_WAVES_PER_BLOCK - 1) / SHV_WAVES_PER_BLOCK), SHV_BLOCK, 0, st>>>(
         (const FaceRec*)rec, T, faces, radiance, grad_image, face_id, cam.width, part);
   }
