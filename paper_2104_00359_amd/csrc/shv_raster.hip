@@ -29,7 +29,7 @@
 // radiance.
 //
 // Adjoint (through the winning triangle's weights; which triangle wins is
-// piecewise constant): one wave per face walks the face's bounding box, takes
+// piecewise constant): sixteen lanes per face walk the face's bounding box, takes
 // the pixels that face won, and sums their contributions to the face's three
 // corners (radiance, pixel x, pixel y, depth) in a fixed order; a per-vertex
 // pass then sums the corners of its incident faces in the incidence list's
@@ -329,31 +329,37 @@ __device__ __forceinline__ void pixel_adjoint(const FaceRec& r, float px, float 
   gy[2] = gE0 * dx[1] - gE1 * dx[0] + gA * (r.x[1] - r.x[0]);
 }
 
-__device__ __forceinline__ float wave_sum_fixed(float v) {
-  // butterfly over the 64 lanes: every lane ends with the same, fixed-order sum
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over a group of 16 lanes by a butterfly: every lane of the group ends
+// with the same, fixed-order sum.
+__device__ __forceinline__ float group16_sum(float v) {
+  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// One wave per face: part[f][k][c] for corner k and c = (radiance, x, y, w).
+constexpr int kFaceLanes = 16;                 // lanes per face in the adjoint
+constexpr int kFacesPerBlock = SHV_BLOCK / kFaceLanes;
+
+// Sixteen lanes per face: part[f][k][c] for corner k and c = (radiance, x, y,
+// w).  The lanes stride over the face's box; each lane sums its pixels in
+// order, then the group's butterfly adds the lanes in a fixed order.
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_face_grads(const FaceRec* __restrict__ rec, int64_t T,
                                                                  const int32_t* __restrict__ faces,
                                                                  const float* __restrict__ radiance,
                                                                  const float* __restrict__ grad_image,
                                                                  const int32_t* __restrict__ face_id, int width,
                                                                  float* __restrict__ part) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t f = (int64_t)blockIdx.x * SHV_WAVES_PER_BLOCK + wave;
-  if (f >= T) return;
-  const FaceRec r = rec[f];
+  const int sub = threadIdx.x % kFaceLanes;
+  const int64_t f = (int64_t)blockIdx.x * kFacesPerBlock + threadIdx.x / kFaceLanes;
+  const bool live = f < T;  // whole groups of 16 lanes are live or not
+  const FaceRec r = rec[live ? f : 0];
   float acc[12];
   for (int c = 0; c < 12; ++c) acc[c] = 0.0f;
-  if (r.i0 <= r.i1 && r.j0 <= r.j1) {
+  if (live && r.i0 <= r.i1 && r.j0 <= r.j1) {
     const int32_t* fv = faces + 3 * f;
     const float B[3] = {radiance[fv[0]], radiance[fv[1]], radiance[fv[2]]};
     const int bw = r.i1 - r.i0 + 1;
     const int64_t n = (int64_t)bw * (r.j1 - r.j0 + 1);
-    for (int64_t t = lane; t < n; t += 64) {
+    for (int64_t t = sub; t < n; t += kFaceLanes) {
       const int i = r.i0 + (int)(t % bw), j = r.j0 + (int)(t / bw);
       const int64_t pix = (int64_t)j * width + i;
       if (face_id[pix] != (int32_t)f) continue;
@@ -367,12 +373,12 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_face_grads(const FaceRec* 
       }
     }
   }
-  for (int c = 0; c < 12; ++c) acc[c] = wave_sum_fixed(acc[c]);
-  if (lane < 12) {
+  for (int c = 0; c < 12; ++c) acc[c] = group16_sum(acc[c]);
+  if (live && sub < 12) {
     float v = acc[0];
     for (int c = 1; c < 12; ++c)
-      if (lane == c) v = acc[c];
-    part[12 * f + lane] = v;
+      if (sub == c) v = acc[c];
+    part[12 * f + sub] = v;
   }
 }
 
@@ -472,7 +478,7 @@ hipError_t launch_raster_backward(const float* grad_image, const float* verts, i
   if (T > 0) {
     k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
         verts, V, faces, T, cam, (FaceRec*)rec, 0, nullptr, nullptr, nullptr, nullptr);
-    k_raster_face_grads<<<(unsigned)((T + SHV_WAVES_PER_BLOCK - 1) / SHV_WAVES_PER_BLOCK), SHV_BLOCK, 0, st>>>(
+    k_raster_face_grads<<<(unsigned)((T + kFacesPerBlock - 1) / kFacesPerBlock), SHV_BLOCK, 0, st>>>(
         (const FaceRec*)rec, T, faces, radiance, grad_image, face_id, cam.width, part);
   }
   if (V > 0) {
