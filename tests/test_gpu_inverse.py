@@ -154,15 +154,17 @@ def test_gradient_descent_follows_the_oracle_and_reduces_the_loss():
     assert hist[-1] < 0.3 * hist[0]
 
 
-def test_image_space_inverse_problem_gradient_parity():
+@pytest.mark.parametrize("n,spacing", [(4, None), (8, 0.03)])
+def test_image_space_inverse_problem_gradient_parity(n, spacing):
     """Eqs. 14-16: d/d theta of the mean squared image error through the
     deformation, visibility, shading and the rasteriser (the mesh body
-    scene, 4 bands, a 96 x 96 image), against the oracle's autograd.  The
-    GPU's face map agrees with the oracle's on all but a few edge pixels (the
-    deformed vertices differ by FP32 rounding), so the gradient bar is 2e-3;
-    dropping the rasteriser's position term would miss it by far."""
+    scene, a 96 x 96 image; 8 bands on a coarser tessellation), against the
+    oracle's autograd.  The GPU's face map agrees with the oracle's on all
+    but a few edge pixels (the deformed vertices differ by FP32 rounding), so
+    the gradient bar is 2e-3; dropping the rasteriser's position term would
+    miss it by far."""
     from paper_2104_00359_amd import inverse
-    sc = scenegen.scene_mesh_body(n_bands=4, width=96, height=96)
+    sc = scenegen.scene_mesh_body(n_bands=n, width=96, height=96, spacing=spacing)
     P, S = sc["points"].shape[0], sc["spheres"].shape[0]
     K = int(np.ceil(4 * P / S))
     g = inverse.DeformGraph(sc["points"], sc["normals"], sc["spheres"], K)
@@ -172,12 +174,12 @@ def test_image_space_inverse_problem_gradient_parity():
     tgt = rng.uniform(0.0, 1.0, (96, 96)).astype(np.float32)
     p0 = _params(S, 7, rot=0.05, trans=0.01)
     cam = (sc["camera"], 96, 96)
-    ip = inverse.InverseProblem(g, sc["albedo"], sc["light"], tgt, 4, lr=0.0, init=p0, faces=sc["faces"],
+    ip = inverse.InverseProblem(g, sc["albedo"], sc["light"], tgt, n, lr=0.0, init=p0, faces=sc["faces"],
                                 camera=cam)
     ip.step()
     torch.cuda.synchronize()
-    loss, ref, fid = deform.image_loss(p0, sc, idx, w, tgt, 4)
-    _, ref_nopos, _ = deform.image_loss(p0, sc, idx, w, tgt, 4, raster_positions=False)
+    loss, ref, fid = deform.image_loss(p0, sc, idx, w, tgt, n)
+    _, ref_nopos, _ = deform.image_loss(p0, sc, idx, w, tgt, n, raster_positions=False)
     same = float((ip.raster["face_id"].cpu().numpy() == fid).mean())
     e = rel_l2(ip.grad.cpu().numpy(), ref.numpy())
     e_nopos = rel_l2(ref_nopos.numpy(), ref.numpy())
