@@ -266,8 +266,9 @@ typedef struct shv_camera {
  * outside [0, V). */
 shv_status shv_raster_incidence_build(const int32_t* faces, int64_t T, int64_t V, int32_t* ptr, int32_t* idx);
 
-/* Workspace bytes of sh_raster_forward / sh_raster_backward for V vertices,
- * T triangles and a width x height image (0 if invalid). */
+/* Workspace bytes of sh_raster_forward / sh_raster_backward for V vertices
+ * (V < 2^31), T triangles (T < 2^26) and a width x height image (0 if
+ * invalid). */
 size_t shv_raster_workspace_bytes(int64_t V, int64_t T, int32_t width, int32_t height);
 
 /* vertices [3][V], faces [T][3], radiance [V] (device) -> image [height][width]

@@ -343,9 +343,15 @@ shv_status check_camera(const shv_camera* cam, shv::RasterCam& rc) {
   return SHV_OK;
 }
 
+// The tile lists hold up to 16 entries per face in 32-bit offsets.
+bool mesh_size_ok(int64_t V, int64_t T) {
+  return V >= 0 && T >= 0 && V < ((int64_t)1 << 31) && 32 * T < ((int64_t)1 << 31);
+}
+
 shv_status check_mesh(int64_t V, int64_t T) {
-  if (V < 0 || T < 0 || V >= ((int64_t)1 << 31) || 3 * T >= ((int64_t)1 << 31))
-    return set_error(SHV_ERR_INVALID_ARG, "mesh size out of range (V=%lld, T=%lld)", (long long)V, (long long)T);
+  if (!mesh_size_ok(V, T))
+    return set_error(SHV_ERR_INVALID_ARG, "mesh size out of range (V=%lld, T=%lld; T < 2^26)", (long long)V,
+                     (long long)T);
   return SHV_OK;
 }
 
@@ -733,8 +739,7 @@ shv_status shv_raster_incidence_build(const int32_t* faces, int64_t T, int64_t V
 }
 
 size_t shv_raster_workspace_bytes(int64_t V, int64_t T, int32_t width, int32_t height) {
-  if (V < 0 || T < 0 || 3 * T >= ((int64_t)1 << 31) || width < 1 || height < 1 || width > SHV_MAX_IMAGE_SIDE ||
-      height > SHV_MAX_IMAGE_SIDE)
+  if (!mesh_size_ok(V, T) || width < 1 || height < 1 || width > SHV_MAX_IMAGE_SIDE || height > SHV_MAX_IMAGE_SIDE)
     return 0;
   return align_up(shv::raster_record_bytes(T)) +
          std::max(align_up((size_t)T * 12 * 4), align_up(shv::raster_bin_bytes(T, width, height)));

@@ -273,6 +273,8 @@ def test_raster_incidence_and_argument_checks(L):
     assert L.shv_raster_workspace_bytes(V, T, 64, 48) >= T * (64 + 17 * 4)
     assert L.shv_raster_workspace_bytes(-1, T, 64, 48) == 0
     assert L.shv_raster_workspace_bytes(V, T, 0, 48) == 0
+    assert L.shv_raster_workspace_bytes(V, 1 << 26, 64, 48) == 0
+    assert L.shv_raster_workspace_bytes(V, (1 << 26) - 1, 64, 48) > 0
     f = L.raw("sh_raster_forward")
     cam = L.camera(np.zeros((3, 4)), 0, 10)
     assert f(None, 3, None, 1, None, ctypes.byref(cam), None, None, None, 0, None) == L.SHV_ERR_INVALID_ARG
