@@ -223,7 +223,7 @@ __device__ __forceinline__ bool cover(const FaceRec& r, int i, int j, float px, 
 // max of the bit-inverted key (depth bits above the face index: positive
 // floats order like their bits), which is the lexicographic minimum whatever
 // the order of the merges.
-__global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __restrict__ rec,
+__global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __restrict__ rec, int64_t T,
                                                               const int32_t* __restrict__ offsets,
                                                               const int32_t* __restrict__ list,
                                                               const int32_t* __restrict__ big_count,
@@ -246,10 +246,12 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
     bool meets = false;
     if (e < n) {
       const int32_t f = e < nb ? list[b0 + e] : big_list[e - nb];
-      const FaceRec r = rec[f];
-      sh.ids[lane] = f;
-      sh.recs[lane] = r;
-      meets = r.i0 <= ti1 && r.i1 >= ti0 && r.j0 <= tj1 && r.j1 >= tj0;
+      if (f >= 0 && (int64_t)f < T) {  // every list entry is a face index; checked all the same
+        const FaceRec r = rec[f];
+        sh.ids[lane] = f;
+        sh.recs[lane] = r;
+        meets = r.i0 <= ti1 && r.i1 >= ti0 && r.j0 <= tj1 && r.j1 >= tj0;
+      }
     }
     uint64_t mask = __ballot(meets);
     __syncthreads();
@@ -464,7 +466,7 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
     k_raster_bin<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>((const FaceRec*)rec, T, tiles_x,
                                                                                     offsets, slots, list);
     k_raster_zbuf<<<dim3((unsigned)tiles, kZbufSplit), kTileThreads, 0, st>>>(
-        (const FaceRec*)rec, offsets, list, big_count, big_list, cam.width, cam.height, tiles_x, zbuf);
+        (const FaceRec*)rec, T, offsets, list, big_count, big_list, cam.width, cam.height, tiles_x, zbuf);
   }
   k_raster_resolve<<<(unsigned)((npix + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
       (const FaceRec*)rec, zbuf, faces, radiance, cam.width, npix, image, face_id);
