@@ -162,6 +162,15 @@ def roofline(kernels, steps, work):
     time."""
     dom = max(kernels, key=lambda kname: kernels[kname]["total_ms"])
     flops_step, _ = work(dom)
+    unmodelled = None
+    if flops_step is None:
+        # the largest launch has no flop model (the rasteriser's, which is bound by latency and launches):
+        # report the largest modelled kernel and name the other
+        modelled = [kname for kname in kernels if work(kname)[0] is not None]
+        if modelled:
+            unmodelled = dom
+            dom = max(modelled, key=lambda kname: kernels[kname]["total_ms"])
+            flops_step, _ = work(dom)
     for name, kv in kernels.items():
         f, _ = work(name)
         if f is not None:
@@ -172,9 +181,12 @@ def roofline(kernels, steps, work):
     per_launch = flops_step * steps / kernels[dom]["launches"]
     ach = per_launch / (kernels[dom]["avg_us"] * 1e-6) / 1e12
     bound = "mfma" if dom.startswith("exp_quad") else "alu"   # FP32 MFMA and FP32 vector share the peak
-    return {"bound": bound, "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "flops_per_launch": int(per_launch), "avg_launch_us": kernels[dom]["avg_us"]}
+    out = {"bound": bound, "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+           "flops_per_launch": int(per_launch), "avg_launch_us": kernels[dom]["avg_us"]}
+    if unmodelled is not None:
+        out["largest_unmodelled"] = unmodelled
+    return out
 
 
 def kernel_source_hash():
