@@ -17,7 +17,7 @@ Split choose_split(int64_t P, int64_t S) {
   const int64_t waves = 4 * pair_blocks(P);  // 4 waves per 64-receiver tile
   const int64_t target_waves = 4096;  // 4 waves per SIMD on 256 CUs x 4 SIMDs
   int64_t n = waves > 0 ? (target_waves + waves - 1) / waves : 1;
-  const int64_t max_by_size = (S + 63) / 64;  // keep >= 16 spheres per wave
+  const int64_t max_by_size = (S + 31) / 32;  // keep >= 8 spheres per wave
   if (n > max_by_size) n = max_by_size;
   const int64_t min_by_lds = (S + SHV_MAX_CHUNK - 1) / SHV_MAX_CHUNK;
   if (n < min_by_lds) n = min_by_lds;
