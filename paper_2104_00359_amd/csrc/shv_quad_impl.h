@@ -156,14 +156,26 @@ __device__ __forceinline__ void quad_load_rows(const float* __restrict__ X, int 
   constexpr int N = NB * NB;
   const int half = (threadIdx.x & 63) >> 5;
   const int64_t q = ok ? p : 0;
+  // Chunk by chunk, each chunk's 32 loads issued together (the sum per row
+  // is still taken in chunk order).
 #pragma unroll
   for (int s = 0; s < 32; ++s) {
     const int coef = 2 * s + half;
-    const int cc = coef < N ? coef : N - 1;
-    float v = X[(int64_t)cc * P + q];
-    for (int c = 1; c < chunks; ++c) v += X[c * stride + (int64_t)cc * P + q];
-    a[s] = (ok && coef < N) ? v : 0.0f;
+    a[s] = X[(int64_t)(coef < N ? coef : N - 1) * P + q];
   }
+  for (int c = 1; c < chunks; ++c) {
+    const float* src = X + c * stride + q;
+    float t[32];
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const int coef = 2 * s + half;
+      t[s] = src[(int64_t)(coef < N ? coef : N - 1) * P];
+    }
+#pragma unroll
+    for (int s = 0; s < 32; ++s) a[s] += t[s];
+  }
+#pragma unroll
+  for (int s = 0; s < 32; ++s) a[s] = (ok && 2 * s + half < N) ? a[s] : 0.0f;
 }
 
 // Forward: Fpart [nchunks][N][P] -> vis [gridDim.y][N][P], the partial sums of
