@@ -89,9 +89,22 @@ __device__ __forceinline__ bool tile_range(const FaceRec& r, int& tx0, int& tx1,
 }
 
 // With counts != NULL also bins: counts[tile] += 1 for each tile a binned
-// face meets, the count before the increment kept as the face's slot in that
-// tile's list (slots[kMaxBinTiles f + k] for its k-th tile, row by row); a
-// face meeting more tiles is appended to big_list.
+// face meets, and the face gets a distinct slot in that tile's list
+// (slots[kMaxBinTiles f + k] for its k-th tile, row by row); a face meeting
+// more tiles is appended to big_list.  The block first counts its faces'
+// tiles in an LDS hash table (a block's faces are usually neighbours and meet
+// few tiles), then reserves each tile's run of slots with one global atomic;
+// when the table is full a face's tile takes its slot from the global counter
+// directly.
+constexpr int kBinHash = 1024;  // LDS hash slots per block
+
+__device__ __forceinline__ int bin_hash(int tile) { return (int)(((uint32_t)tile * 0x9E3779B1u) >> 22); }
+
+struct SetupShared {
+  int32_t key[kBinHash];  // tile + 1, 0 = empty
+  int32_t cnt[kBinHash];
+  int32_t base[kBinHash];
+};
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restrict__ verts, int64_t V,
                                                             const int32_t* __restrict__ faces, int64_t T,
                                                             RasterCam cam, FaceRec* __restrict__ rec,
@@ -99,80 +112,149 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
                                                             int32_t* __restrict__ slots,
                                                             int32_t* __restrict__ big_count,
                                                             int32_t* __restrict__ big_list) {
+  __shared__ SetupShared sh;
   const int64_t f = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
-  if (f >= T) return;
+  const bool live = f < T;
   FaceRec r;
   r.i0 = 0;
   r.i1 = -1;
   r.j0 = 0;
   r.j1 = -1;
   r.pad[0] = r.pad[1] = 0;
-  bool ok = true;
-  for (int k = 0; k < 3; ++k) {
-    const int32_t vi = faces[3 * f + k];
-    if (vi < 0 || vi >= V) {
-      ok = false;
-      r.x[k] = r.y[k] = r.w[k] = 0.0f;
-      continue;
+  r.area = 0.0f;
+  if (live) {
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      const int32_t vi = faces[3 * f + k];
+      if (vi < 0 || vi >= V) {
+        ok = false;
+        r.x[k] = r.y[k] = r.w[k] = 0.0f;
+        continue;
+      }
+      float u, v, w;
+      project_vertex(cam.P, verts[vi], verts[V + vi], verts[2 * V + vi], u, v, w);
+      r.x[k] = u / w;
+      r.y[k] = v / w;
+      r.w[k] = w;
+      ok = ok && (w > kRasterMinW);
     }
-    float u, v, w;
-    project_vertex(cam.P, verts[vi], verts[V + vi], verts[2 * V + vi], u, v, w);
-    r.x[k] = u / w;
-    r.y[k] = v / w;
-    r.w[k] = w;
-    ok = ok && (w > kRasterMinW);
+    r.area = (r.x[1] - r.x[0]) * (r.y[2] - r.y[0]) - (r.x[2] - r.x[0]) * (r.y[1] - r.y[0]);
+    ok = ok && (r.area != 0.0f) && isfinite(r.area);
+    if (ok) {
+      const float xmin = fminf(fminf(r.x[0], r.x[1]), r.x[2]), xmax = fmaxf(fmaxf(r.x[0], r.x[1]), r.x[2]);
+      const float ymin = fminf(fminf(r.y[0], r.y[1]), r.y[2]), ymax = fmaxf(fmaxf(r.y[0], r.y[1]), r.y[2]);
+      // pixel i is a candidate when xmin - 1 <= i <= xmax (a superset of the
+      // centres i + 0.5 inside [xmin, xmax]); the coverage test decides.
+      r.i0 = clamp_floor(xmin - 1.0f, 0, cam.width - 1);
+      r.i1 = clamp_floor(xmax, -1, cam.width - 1);
+      r.j0 = clamp_floor(ymin - 1.0f, 0, cam.height - 1);
+      r.j1 = clamp_floor(ymax, -1, cam.height - 1);
+      if (xmax < -1.0f || ymax < -1.0f) r.i1 = -1;
+    }
+    rec[f] = r;
   }
-  r.area = (r.x[1] - r.x[0]) * (r.y[2] - r.y[0]) - (r.x[2] - r.x[0]) * (r.y[1] - r.y[0]);
-  ok = ok && (r.area != 0.0f) && isfinite(r.area);
-  if (ok) {
-    const float xmin = fminf(fminf(r.x[0], r.x[1]), r.x[2]), xmax = fmaxf(fmaxf(r.x[0], r.x[1]), r.x[2]);
-    const float ymin = fminf(fminf(r.y[0], r.y[1]), r.y[2]), ymax = fmaxf(fmaxf(r.y[0], r.y[1]), r.y[2]);
-    // pixel i is a candidate when xmin - 1 <= i <= xmax (a superset of the
-    // centres i + 0.5 inside [xmin, xmax]); the coverage test decides.
-    r.i0 = clamp_floor(xmin - 1.0f, 0, cam.width - 1);
-    r.i1 = clamp_floor(xmax, -1, cam.width - 1);
-    r.j0 = clamp_floor(ymin - 1.0f, 0, cam.height - 1);
-    r.j1 = clamp_floor(ymax, -1, cam.height - 1);
-    if (xmax < -1.0f || ymax < -1.0f) r.i1 = -1;
+  if (!counts) return;  // the adjoint's setup: records only (uniform over the grid)
+  for (int h = threadIdx.x; h < kBinHash; h += SHV_BLOCK) {
+    sh.key[h] = 0;
+    sh.cnt[h] = 0;
   }
-  rec[f] = r;
-  int tx0, tx1, ty0, ty1;
-  if (counts && tile_range(r, tx0, tx1, ty0, ty1)) {
+  __syncthreads();
+  int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+  bool binned = false;
+  if (live && tile_range(r, tx0, tx1, ty0, ty1)) {
     if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) {
       big_list[atomicAdd(big_count, 1)] = (int32_t)f;
     } else {
+      binned = true;
+      // per tile: the rank within the block's count (>= 0), or, with the
+      // table full, -1 - the slot taken from the global counter
       int k = 0;
-      for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) slots[kMaxBinTiles * f + k++] = atomicAdd(&counts[ty * tiles_x + tx], 1);
+      for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const int tile = ty * tiles_x + tx;
+          int h = bin_hash(tile), found = -1;
+          for (int probe = 0; probe < kBinHash; ++probe) {
+            const int prev = atomicCAS(&sh.key[h], 0, tile + 1);
+            if (prev == 0 || prev == tile + 1) {
+              found = h;
+              break;
+            }
+            h = (h + 1) & (kBinHash - 1);
+          }
+          slots[kMaxBinTiles * f + k++] =
+              found >= 0 ? atomicAdd(&sh.cnt[found], 1) : -1 - atomicAdd(&counts[tile], 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kBinHash; h += SHV_BLOCK) {
+    const int key = sh.key[h];
+    if (key != 0) sh.base[h] = atomicAdd(&counts[key - 1], sh.cnt[h]);
+  }
+  __syncthreads();
+  if (!binned) return;
+  int k = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      int32_t* sl = &slots[kMaxBinTiles * f + k++];
+      const int v = *sl;
+      if (v < 0) {
+        *sl = -1 - v;
+        continue;
+      }
+      const int tile = ty * tiles_x + tx;
+      int h = bin_hash(tile);
+      for (int probe = 0; probe < kBinHash && sh.key[h] != tile + 1; ++probe) h = (h + 1) & (kBinHash - 1);
+      *sl = sh.base[h] + v;
     }
   }
 }
 
-// Exclusive scan of the tile counts into offsets[0 .. n] (one block: each
-// thread sums a contiguous run, the run totals are scanned in LDS in log2
-// steps, then each thread writes its run's offsets).
+// Exclusive scans, one block: the tile counts into offsets[0 .. n], and the
+// tiles' chunk counts (64 entries of the tile's list and the shared list per
+// chunk) into chunk_off[0 .. n].  Each thread sums a contiguous run, the run
+// totals are scanned in LDS in log2 steps, then each thread writes its run.
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __restrict__ counts, int n,
-                                                           int32_t* __restrict__ offsets) {
-  __shared__ int32_t part[2][SHV_BLOCK];
+                                                           const int32_t* __restrict__ big_count,
+                                                           int32_t* __restrict__ offsets,
+                                                           int32_t* __restrict__ chunk_off) {
+  __shared__ int32_t part[2][2][SHV_BLOCK];
+  const int nbig = *big_count;
   const int per = (n + SHV_BLOCK - 1) / SHV_BLOCK;
   const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
-  int32_t sum = 0;
-  for (int t = b; t < e; ++t) sum += counts[t];
+  int32_t sum = 0, csum = 0;
+  for (int t = b; t < e; ++t) {
+    const int32_t c = counts[t];
+    sum += c;
+    csum += (c + nbig + 63) / 64;
+  }
   int cur = 0;
-  part[0][threadIdx.x] = sum;
+  part[0][0][threadIdx.x] = sum;
+  part[0][1][threadIdx.x] = csum;
   __syncthreads();
   for (int d = 1; d < SHV_BLOCK; d <<= 1) {
-    const int32_t v = part[cur][threadIdx.x] + (threadIdx.x >= (unsigned)d ? part[cur][threadIdx.x - d] : 0);
-    part[cur ^ 1][threadIdx.x] = v;
+    const bool has = threadIdx.x >= (unsigned)d;
+    const int32_t v = part[cur][0][threadIdx.x] + (has ? part[cur][0][threadIdx.x - d] : 0);
+    const int32_t w = part[cur][1][threadIdx.x] + (has ? part[cur][1][threadIdx.x - d] : 0);
+    part[cur ^ 1][0][threadIdx.x] = v;
+    part[cur ^ 1][1][threadIdx.x] = w;
     cur ^= 1;
     __syncthreads();
   }
-  int32_t run = part[cur][threadIdx.x] - sum;  // exclusive prefix of this thread's run
+  int32_t run = part[cur][0][threadIdx.x] - sum;  // exclusive prefixes of this thread's run
+  int32_t crun = part[cur][1][threadIdx.x] - csum;
   for (int t = b; t < e; ++t) {
+    const int32_t c = counts[t];
     offsets[t] = run;
-    run += counts[t];
+    chunk_off[t] = crun;
+    run += c;
+    crun += (c + nbig + 63) / 64;
   }
-  if (threadIdx.x == SHV_BLOCK - 1) offsets[n] = part[cur][threadIdx.x];
+  if (threadIdx.x == SHV_BLOCK - 1) {
+    offsets[n] = part[cur][0][threadIdx.x];
+    chunk_off[n] = part[cur][1][threadIdx.x];
+  }
 }
 
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_bin(const FaceRec* __restrict__ rec, int64_t T, int tiles_x,
@@ -184,9 +266,14 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_bin(const FaceRec* __restr
   const FaceRec r = rec[f];
   int tx0, tx1, ty0, ty1;
   if (!tile_range(r, tx0, tx1, ty0, ty1) || (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kMaxBinTiles) return;
+  const int64_t cap = (int64_t)kMaxBinTiles * T;
   int k = 0;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) list[offsets[ty * tiles_x + tx] + slots[kMaxBinTiles * f + k++]] = (int32_t)f;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int64_t pos = (int64_t)offsets[ty * tiles_x + tx] + slots[kMaxBinTiles * f + k++];
+      if (pos >= 0 && pos < cap) list[pos] = (int32_t)f;  // always true; checked all the same
+    }
+  }
 }
 
 struct RasterShared {
@@ -217,32 +304,41 @@ __device__ __forceinline__ bool cover(const FaceRec& r, int i, int j, float px, 
   return true;
 }
 
-// One wave per (tile, chunk of 64 list entries), chunks y, y + gridDim.y, ...
-// of the tile's list followed by the shared list.  Each lane keeps its
-// pixel's smallest (depth, face) and merges it into zbuf with one atomic
-// max of the bit-inverted key (depth bits above the face index: positive
-// floats order like their bits), which is the lexicographic minimum whatever
-// the order of the merges.
+// Waves stride over the chunks of all tiles (chunk_off: the scan of the
+// tiles' chunk counts); a chunk is 64 entries of its tile's list followed by
+// the shared list, and its tile is found by binary search.  Each lane keeps
+// its pixel's smallest (depth, face) over the chunk and merges it into zbuf
+// with one atomic max of the bit-inverted key (depth bits above the face
+// index: positive floats order like their bits), which is the lexicographic
+// minimum whatever the order of the merges.
 __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __restrict__ rec, int64_t T,
                                                               const int32_t* __restrict__ offsets,
+                                                              const int32_t* __restrict__ chunk_off,
                                                               const int32_t* __restrict__ list,
                                                               const int32_t* __restrict__ big_count,
                                                               const int32_t* __restrict__ big_list, int width,
-                                                              int height, int tiles_x,
+                                                              int height, int tiles_x, int tiles,
                                                               unsigned long long* __restrict__ zbuf) {
   __shared__ RasterShared sh;
-  const int tile = blockIdx.x;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int ti0 = tx * kTile, tj0 = ty * kTile;
-  const int ti1 = min(ti0 + kTile, width) - 1, tj1 = min(tj0 + kTile, height) - 1;
-  const int i = ti0 + (threadIdx.x % kTile), j = tj0 + (threadIdx.x / kTile);
-  const float px = (float)i + 0.5f, py = (float)j + 0.5f;
   const int lane = threadIdx.x;
-  const int b0 = offsets[tile], nb = offsets[tile + 1] - b0;
-  const int n = nb + *big_count;
-  unsigned long long best = 0ull;  // inverted key: 0 = nothing
-  for (int c0 = (int)blockIdx.y * kTileThreads; c0 < n; c0 += (int)gridDim.y * kTileThreads) {
-    const int e = c0 + lane;
+  const int total = chunk_off[tiles];
+  const int nbig = *big_count;
+  for (int c = blockIdx.x; c < total; c += gridDim.x) {
+    int lo = 0, hi = tiles;  // chunk_off[lo] <= c < chunk_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (chunk_off[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    const int tile = lo;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int ti0 = tx * kTile, tj0 = ty * kTile;
+    const int ti1 = min(ti0 + kTile, width) - 1, tj1 = min(tj0 + kTile, height) - 1;
+    const int i = ti0 + (lane % kTile), j = tj0 + (lane / kTile);
+    const float px = (float)i + 0.5f, py = (float)j + 0.5f;
+    const int b0 = offsets[tile], nb = offsets[tile + 1] - b0;
+    const int n = nb + nbig;
+    const int e = (c - chunk_off[tile]) * kTileThreads + lane;
     bool meets = false;
     if (e < n) {
       const int32_t f = e < nb ? list[b0 + e] : big_list[e - nb];
@@ -255,6 +351,7 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
     }
     uint64_t mask = __ballot(meets);
     __syncthreads();
+    unsigned long long best = 0ull;  // inverted key: 0 = nothing
     while (mask) {
       const int k = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
@@ -264,9 +361,9 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
           ~(((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)(uint32_t)sh.ids[k]);
       best = key > best ? key : best;
     }
+    if (best != 0ull && i <= ti1 && j <= tj1) atomicMax(&zbuf[(int64_t)j * width + i], best);
     __syncthreads();  // the chunk's records are no longer read
   }
-  if (best != 0ull && i <= ti1 && j <= tj1) atomicMax(&zbuf[(int64_t)j * width + i], best);
 }
 
 // Per pixel: the winning face from the depth buffer, its weights again (the
@@ -435,10 +532,10 @@ int64_t raster_tiles(int width, int height) {
 // entries per face at most) and the shared list (one per face at most).
 size_t raster_bin_bytes(int64_t T, int width, int height) {
   const int64_t tiles = raster_tiles(width, height);
-  return (size_t)width * height * 8 + (size_t)(2 * (tiles + 1) + 1 + (2 * kMaxBinTiles + 1) * T) * 4;
+  return (size_t)width * height * 8 + (size_t)(3 * (tiles + 1) + 1 + (2 * kMaxBinTiles + 1) * T) * 4;
 }
 
-constexpr int kZbufSplit = 8;  // waves per tile (chunks of 64 list entries each)
+constexpr int kZbufWaves = 4096;  // waves of the depth-buffer pass (16 per CU), striding over the chunks
 
 hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
                                  const RasterCam& cam, float* image, int32_t* face_id, void* rec, void* bins,
@@ -449,7 +546,8 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
   unsigned long long* zbuf = (unsigned long long*)bins;
   int32_t* counts = (int32_t*)(zbuf + npix);
   int32_t* offsets = counts + (tiles + 1);
-  int32_t* big_count = offsets + (tiles + 1);
+  int32_t* chunk_off = offsets + (tiles + 1);
+  int32_t* big_count = chunk_off + (tiles + 1);
   int32_t* slots = big_count + 1;
   int32_t* list = slots + kMaxBinTiles * T;
   int32_t* big_list = list + kMaxBinTiles * T;
@@ -462,11 +560,11 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
   if (T > 0) {
     k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
         verts, V, faces, T, cam, (FaceRec*)rec, tiles_x, counts, slots, big_count, big_list);
-    k_raster_scan<<<1, SHV_BLOCK, 0, st>>>(counts, (int)tiles, offsets);
+    k_raster_scan<<<1, SHV_BLOCK, 0, st>>>(counts, (int)tiles, big_count, offsets, chunk_off);
     k_raster_bin<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>((const FaceRec*)rec, T, tiles_x,
                                                                                     offsets, slots, list);
-    k_raster_zbuf<<<dim3((unsigned)tiles, kZbufSplit), kTileThreads, 0, st>>>(
-        (const FaceRec*)rec, T, offsets, list, big_count, big_list, cam.width, cam.height, tiles_x, zbuf);
+    k_raster_zbuf<<<kZbufWaves, kTileThreads, 0, st>>>((const FaceRec*)rec, T, offsets, chunk_off, list, big_count,
+                                                       big_list, cam.width, cam.height, tiles_x, (int)tiles, zbuf);
   }
   k_raster_resolve<<<(unsigned)((npix + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
       (const FaceRec*)rec, zbuf, faces, radiance, cam.width, npix, image, face_id);
