@@ -213,47 +213,52 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
 
 // Exclusive scans, one block: the tile counts into offsets[0 .. n], and the
 // tiles' chunk counts (64 entries of the tile's list and the shared list per
-// chunk) into chunk_off[0 .. n].  Each thread sums a contiguous run, the run
-// totals are scanned in LDS in log2 steps, then each thread writes its run.
+// chunk) into chunk_off[0 .. n].  The chunk offsets are 64-bit: every tile
+// scans the whole shared list, so their total grows as tiles x shared-list
+// length and passes 2^31 on large images with many large faces.  Each thread
+// sums a contiguous run, the run totals are scanned in LDS in log2 steps,
+// then each thread writes its run.
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __restrict__ counts, int n,
                                                            const int32_t* __restrict__ big_count,
                                                            int32_t* __restrict__ offsets,
-                                                           int32_t* __restrict__ chunk_off) {
-  __shared__ int32_t part[2][2][SHV_BLOCK];
+                                                           int64_t* __restrict__ chunk_off) {
+  __shared__ int32_t part[2][SHV_BLOCK];
+  __shared__ int64_t cpart[2][SHV_BLOCK];
   const int nbig = *big_count;
   const int per = (n + SHV_BLOCK - 1) / SHV_BLOCK;
   const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
-  int32_t sum = 0, csum = 0;
+  int32_t sum = 0;
+  int64_t csum = 0;
   for (int t = b; t < e; ++t) {
     const int32_t c = counts[t];
     sum += c;
-    csum += (c + nbig + 63) / 64;
+    csum += ((int64_t)c + nbig + 63) / 64;
   }
   int cur = 0;
-  part[0][0][threadIdx.x] = sum;
-  part[0][1][threadIdx.x] = csum;
+  part[0][threadIdx.x] = sum;
+  cpart[0][threadIdx.x] = csum;
   __syncthreads();
   for (int d = 1; d < SHV_BLOCK; d <<= 1) {
     const bool has = threadIdx.x >= (unsigned)d;
-    const int32_t v = part[cur][0][threadIdx.x] + (has ? part[cur][0][threadIdx.x - d] : 0);
-    const int32_t w = part[cur][1][threadIdx.x] + (has ? part[cur][1][threadIdx.x - d] : 0);
-    part[cur ^ 1][0][threadIdx.x] = v;
-    part[cur ^ 1][1][threadIdx.x] = w;
+    const int32_t v = part[cur][threadIdx.x] + (has ? part[cur][threadIdx.x - d] : 0);
+    const int64_t w = cpart[cur][threadIdx.x] + (has ? cpart[cur][threadIdx.x - d] : 0);
+    part[cur ^ 1][threadIdx.x] = v;
+    cpart[cur ^ 1][threadIdx.x] = w;
     cur ^= 1;
     __syncthreads();
   }
-  int32_t run = part[cur][0][threadIdx.x] - sum;  // exclusive prefixes of this thread's run
-  int32_t crun = part[cur][1][threadIdx.x] - csum;
+  int32_t run = part[cur][threadIdx.x] - sum;  // exclusive prefixes of this thread's run
+  int64_t crun = cpart[cur][threadIdx.x] - csum;
   for (int t = b; t < e; ++t) {
     const int32_t c = counts[t];
     offsets[t] = run;
     chunk_off[t] = crun;
     run += c;
-    crun += (c + nbig + 63) / 64;
+    crun += ((int64_t)c + nbig + 63) / 64;
   }
   if (threadIdx.x == SHV_BLOCK - 1) {
-    offsets[n] = part[cur][0][threadIdx.x];
-    chunk_off[n] = part[cur][1][threadIdx.x];
+    offsets[n] = part[cur][threadIdx.x];
+    chunk_off[n] = cpart[cur][threadIdx.x];
   }
 }
 
@@ -313,7 +318,7 @@ __device__ __forceinline__ bool cover(const FaceRec& r, int i, int j, float px, 
 // minimum whatever the order of the merges.
 __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __restrict__ rec, int64_t T,
                                                               const int32_t* __restrict__ offsets,
-                                                              const int32_t* __restrict__ chunk_off,
+                                                              const int64_t* __restrict__ chunk_off,
                                                               const int32_t* __restrict__ list,
                                                               const int32_t* __restrict__ big_count,
                                                               const int32_t* __restrict__ big_list, int width,
@@ -321,9 +326,9 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
                                                               unsigned long long* __restrict__ zbuf) {
   __shared__ RasterShared sh;
   const int lane = threadIdx.x;
-  const int total = chunk_off[tiles];
+  const int64_t total = chunk_off[tiles];
   const int nbig = *big_count;
-  for (int c = blockIdx.x; c < total; c += gridDim.x) {
+  for (int64_t c = blockIdx.x; c < total; c += gridDim.x) {
     int lo = 0, hi = tiles;  // chunk_off[lo] <= c < chunk_off[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -338,7 +343,8 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
     const float px = (float)i + 0.5f, py = (float)j + 0.5f;
     const int b0 = offsets[tile], nb = offsets[tile + 1] - b0;
     const int n = nb + nbig;
-    const int e = (c - chunk_off[tile]) * kTileThreads + lane;
+    // below (nb + nbig) + 63 <= 17 T + 63 < 2^31 for T < 2^26
+    const int e = (int)(c - chunk_off[tile]) * kTileThreads + lane;
     bool meets = false;
     if (e < n) {
       const int32_t f = e < nb ? list[b0 + e] : big_list[e - nb];
@@ -527,12 +533,16 @@ int64_t raster_tiles(int width, int height) {
 }
 
 // Forward scratch after the face records: the depth buffer (one 64-bit key
-// per pixel), counts and offsets ([tiles + 1] each), the shared-list count,
+// per pixel), the tile counts ([tiles + 1]), the shared-list count and one
+// pad word (the three cleared together), the tile offsets ([tiles + 1]), the
+// chunk offsets ([tiles + 1], 64-bit; 2 npix + 2 tiles + 4 words precede
+// them, an even number, so they are 8-byte aligned),
 // the faces' slots (kMaxBinTiles per face), the tile lists (kMaxBinTiles
 // entries per face at most) and the shared list (one per face at most).
 size_t raster_bin_bytes(int64_t T, int width, int height) {
   const int64_t tiles = raster_tiles(width, height);
-  return (size_t)width * height * 8 + (size_t)(3 * (tiles + 1) + 1 + (2 * kMaxBinTiles + 1) * T) * 4;
+  return (size_t)width * height * 8 + (size_t)(tiles + 1) * 8 +
+         (size_t)(2 * (tiles + 1) + 2 + (2 * kMaxBinTiles + 1) * T) * 4;
 }
 
 constexpr int kZbufWaves = 4096;  // waves of the depth-buffer pass (16 per CU), striding over the chunks
@@ -545,17 +555,15 @@ hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* f
   const int64_t npix = (int64_t)cam.width * cam.height;
   unsigned long long* zbuf = (unsigned long long*)bins;
   int32_t* counts = (int32_t*)(zbuf + npix);
-  int32_t* offsets = counts + (tiles + 1);
-  int32_t* chunk_off = offsets + (tiles + 1);
-  int32_t* big_count = chunk_off + (tiles + 1);
-  int32_t* slots = big_count + 1;
+  int32_t* big_count = counts + (tiles + 1);
+  int32_t* offsets = big_count + 2;
+  int64_t* chunk_off = (int64_t*)(offsets + (tiles + 1));  // 2 npix + 2 tiles + 4 words in
+  int32_t* slots = (int32_t*)(chunk_off + (tiles + 1));
   int32_t* list = slots + kMaxBinTiles * T;
   int32_t* big_list = list + kMaxBinTiles * T;
   // zero the depth buffer, the counts and the shared-list count (a fill
   // kernel, also under stream capture)
-  hipError_t e = launch_fill_zero((float*)zbuf, 2 * npix + (tiles + 1), st);
-  if (e != hipSuccess) return e;
-  e = launch_fill_zero((float*)big_count, 1, st);
+  hipError_t e = launch_fill_zero((float*)zbuf, 2 * npix + (tiles + 1) + 1, st);
   if (e != hipSuccess) return e;
   if (T > 0) {
     k_raster_setup<<<(unsigned)((T + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(

@@ -502,3 +502,35 @@ def scene_mesh_body(seed=0, segments=24, spacing=None, n_bands=8, width=512, hei
     return dict(points=_f32(verts), normals=_f32(nrm), albedo=_f32(albedo), spheres=_f32(spheres),
                 light=_f32(light), n_bands=n_bands, faces=faces.astype(np.int32), camera=_f32(P),
                 width=width, height=height, grad_image=_f32(gI))
+
+
+def scene_raster_stress(seed=8, width=100, height=90, n_big=160, n_small=2400, n_dup=40):
+    """Unconnected triangles that load the rasteriser's binning: n_big large
+    ones (0.8 to 2.5 m across, many spanning more than 16 of the 8 x 8 pixel
+    tiles) spread over and past the frame, n_small small ones (4 to 12 cm)
+    packed in front of them in a patch of a few tiles, and the first n_dup
+    large ones repeated at the end of the face list (equal depths: ties).
+    Each triangle's corners sit at angles 120 degrees apart (jittered) around
+    its centre, so none is a sliver.  Camera 4 m away, focal length 50 px."""
+    rng = np.random.default_rng(seed)
+
+    def triangles(c, r):
+        n = len(c)
+        th = (rng.uniform(0, 2 * np.pi, n)[:, None] + 2 * np.pi * np.arange(3)[None, :] / 3
+              + rng.uniform(-0.3, 0.3, (n, 3)))
+        v = np.stack([c[:, 0:1] + r[:, None] * np.cos(th), c[:, 1:2] + rng.uniform(-0.2, 0.2, (n, 3)) * r[:, None],
+                      c[:, 2:3] + r[:, None] * np.sin(th)], -1)
+        return v.reshape(-1, 3)
+
+    cb = np.stack([rng.uniform(-2.5, 2.5, n_big), rng.uniform(-1.0, 1.0, n_big), rng.uniform(-2.5, 2.5, n_big)], 1)
+    vb = triangles(cb, rng.uniform(0.8, 2.5, n_big))
+    cs = np.stack([rng.uniform(0.1, 0.5, n_small), rng.uniform(1.0, 1.4, n_small), rng.uniform(-0.4, 0.0, n_small)], 1)
+    vs = triangles(cs, rng.uniform(0.04, 0.12, n_small))
+    verts = np.concatenate([vb, vs])
+    faces = np.arange(len(verts)).reshape(-1, 3)
+    faces = np.concatenate([faces, faces[:n_dup]])
+    P = look_at_camera((0, 4, 0), (0, 0, 0), (0, 0, 1), 50, width, height)
+    radiance = rng.uniform(0.0, 2.0, len(verts))
+    gI = rng.standard_normal((height, width))
+    return dict(points=_f32(verts), faces=faces.astype(np.int32), camera=_f32(P), width=width, height=height,
+                radiance=_f32(radiance), grad_image=_f32(gI), n_dup=n_dup)

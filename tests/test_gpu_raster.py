@@ -112,3 +112,12 @@ def test_raster_empty_mesh_gives_a_black_image():
                                   scenegen.look_at_camera((0, 4, 0), (0, 0, 0), (0, 0, 1), 50, 32, 16), 32, 16,
                                   np.ones((16, 32), np.float32))
     assert (fid == -1).all() and not img.any() and not gB.any() and not gv.any()
+
+
+def test_raster_stress_binning_and_depth_ties():
+    """Faces spanning more than 16 tiles (the shared list, scanned by every
+    tile), a tile list of more than eight 64-entry chunks, and exact depth
+    ties with later twins of the same faces (the lower index wins): every
+    pixel's face bit-exact, image and gradients to the usual bars."""
+    sc = scenegen.scene_raster_stress()
+    check(sc["points"], sc["faces"], sc["radiance"], sc["camera"], sc["width"], sc["height"], sc["grad_image"])

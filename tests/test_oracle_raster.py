@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+import scenegen
 from oracle import raster
 
 W, H = 48, 40
@@ -169,3 +170,32 @@ def test_gradients_against_central_differences():
             e[k, d] = h
             fd = (loss(v64 + e, B64) - loss(v64 - e, B64)) / (2 * h)
             assert abs(fd - float(gv[k, d])) < 1e-5 * max(1.0, abs(fd))
+
+
+def test_stress_scene_loads_the_binning_as_intended():
+    """The rasteriser's stress scene (its GPU parity test relies on this):
+    faces spanning more than 16 tiles, a tile list of several 64-entry chunks,
+    and pixels whose nearest face has an exact twin later in the list; the
+    twins never win (ties go to the lower index)."""
+    sc = scenegen.scene_raster_stress()
+    v, f, P, W, H = sc["points"], sc["faces"], sc["camera"], sc["width"], sc["height"]
+    sx, sy, w = raster.project_f32(v, P)
+    assert (w > 1.0).all()
+    tiles = np.zeros(((H + 7) // 8, (W + 7) // 8), int)
+    spanning = 0
+    for a, b, c in f:
+        xs, ys = sx[[a, b, c]], sy[[a, b, c]]
+        i0, i1 = max(int(np.floor(xs.min() - 0.5)), 0), min(int(np.ceil(xs.max() - 0.5)), W - 1)
+        j0, j1 = max(int(np.floor(ys.min() - 0.5)), 0), min(int(np.ceil(ys.max() - 0.5)), H - 1)
+        if i0 > i1 or j0 > j1:
+            continue
+        if (i1 // 8 - i0 // 8 + 1) * (j1 // 8 - j0 // 8 + 1) > 16:
+            spanning += 1
+        else:
+            tiles[j0 // 8:j1 // 8 + 1, i0 // 8:i1 // 8 + 1] += 1
+    assert spanning > 64 and tiles.max() > 8 * 64
+    fid = raster.rasterize_ids(v, f, P, W, H)
+    n_dup = sc["n_dup"]
+    assert (fid >= 0).mean() > 0.9
+    assert np.isin(fid, np.arange(n_dup)).sum() > 1000
+    assert not (fid >= len(f) - n_dup).any()
