@@ -215,50 +215,83 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
 // tiles' chunk counts (64 entries of the tile's list and the shared list per
 // chunk) into chunk_off[0 .. n].  The chunk offsets are 64-bit: every tile
 // scans the whole shared list, so their total grows as tiles x shared-list
-// length and passes 2^31 on large images with many large faces.  Each thread
-// sums a contiguous run, the run totals are scanned in LDS in log2 steps,
-// then each thread writes its run.
+// length and passes 2^31 on large images with many large faces.  The counts
+// go through LDS in segments of kScanSeg with a running carry: a coalesced
+// load of the segment, a run of kScanPer consecutive counts summed by each
+// thread, the run totals scanned in log2 steps, each thread's run of offsets
+// back into LDS, and a coalesced store of the segment.  Entry t of a segment
+// sits at t + t / kScanPer in LDS, so that the runs' accesses (stride
+// kScanPer + 1 words) fall in distinct banks.
+constexpr int kScanPer = 16;
+constexpr int kScanSeg = kScanPer * SHV_BLOCK;
+
 __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __restrict__ counts, int n,
                                                            const int32_t* __restrict__ big_count,
                                                            int32_t* __restrict__ offsets,
                                                            int64_t* __restrict__ chunk_off) {
+  __shared__ int32_t seg[kScanSeg + kScanSeg / kScanPer];
+  __shared__ int64_t cseg[kScanSeg + kScanSeg / kScanPer];
   __shared__ int32_t part[2][SHV_BLOCK];
   __shared__ int64_t cpart[2][SHV_BLOCK];
   const int nbig = *big_count;
-  const int per = (n + SHV_BLOCK - 1) / SHV_BLOCK;
-  const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
-  int32_t sum = 0;
-  int64_t csum = 0;
-  for (int t = b; t < e; ++t) {
-    const int32_t c = counts[t];
-    sum += c;
-    csum += ((int64_t)c + nbig + 63) / 64;
-  }
-  int cur = 0;
-  part[0][threadIdx.x] = sum;
-  cpart[0][threadIdx.x] = csum;
-  __syncthreads();
-  for (int d = 1; d < SHV_BLOCK; d <<= 1) {
-    const bool has = threadIdx.x >= (unsigned)d;
-    const int32_t v = part[cur][threadIdx.x] + (has ? part[cur][threadIdx.x - d] : 0);
-    const int64_t w = cpart[cur][threadIdx.x] + (has ? cpart[cur][threadIdx.x - d] : 0);
-    part[cur ^ 1][threadIdx.x] = v;
-    cpart[cur ^ 1][threadIdx.x] = w;
-    cur ^= 1;
+  const int x = threadIdx.x;
+  int32_t carry = 0;
+  int64_t ccarry = 0;
+  for (int base = 0; base < n; base += kScanSeg) {
+    const int m = min(kScanSeg, n - base);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int t = k * SHV_BLOCK + x;
+      seg[t + t / kScanPer] = t < m ? counts[base + t] : 0;
+    }
     __syncthreads();
+    int32_t v[kScanPer];
+    int32_t sum = 0;
+    int64_t csum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = seg[x * (kScanPer + 1) + k];
+      sum += v[k];
+      csum += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + 63) / 64 : 0;
+    }
+    int cur = 0;
+    part[0][x] = sum;
+    cpart[0][x] = csum;
+    __syncthreads();
+    for (int d = 1; d < SHV_BLOCK; d <<= 1) {
+      const bool has = x >= d;
+      const int32_t a = part[cur][x] + (has ? part[cur][x - d] : 0);
+      const int64_t b = cpart[cur][x] + (has ? cpart[cur][x - d] : 0);
+      part[cur ^ 1][x] = a;
+      cpart[cur ^ 1][x] = b;
+      cur ^= 1;
+      __syncthreads();
+    }
+    int32_t run = carry + part[cur][x] - sum;  // exclusive prefixes of this thread's run
+    int64_t crun = ccarry + cpart[cur][x] - csum;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      seg[x * (kScanPer + 1) + k] = run;
+      cseg[x * (kScanPer + 1) + k] = crun;
+      run += v[k];
+      crun += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + 63) / 64 : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int t = k * SHV_BLOCK + x;
+      if (t < m) {
+        offsets[base + t] = seg[t + t / kScanPer];
+        chunk_off[base + t] = cseg[t + t / kScanPer];
+      }
+    }
+    carry += part[cur][SHV_BLOCK - 1];
+    ccarry += cpart[cur][SHV_BLOCK - 1];
+    __syncthreads();  // seg and part are rewritten by the next segment
   }
-  int32_t run = part[cur][threadIdx.x] - sum;  // exclusive prefixes of this thread's run
-  int64_t crun = cpart[cur][threadIdx.x] - csum;
-  for (int t = b; t < e; ++t) {
-    const int32_t c = counts[t];
-    offsets[t] = run;
-    chunk_off[t] = crun;
-    run += c;
-    crun += ((int64_t)c + nbig + 63) / 64;
-  }
-  if (threadIdx.x == SHV_BLOCK - 1) {
-    offsets[n] = part[cur][threadIdx.x];
-    chunk_off[n] = cpart[cur][threadIdx.x];
+  if (x == 0) {
+    offsets[n] = carry;
+    chunk_off[n] = ccarry;
   }
 }
 
