@@ -21,7 +21,7 @@
 // also give each face its slot in each tile's list; a scan turns the counts
 // into offsets and a binning pass scatters the faces to their slots (the
 // order within a list varies from run to run).  Then one wave
-// per (tile, chunk of 64 entries of its list and the shared list) tests its
+// per (tile, chunk of kChunk entries of its list and the shared list) tests its
 // 8 x 8 pixels against the chunk's faces, staged in LDS, and merges each
 // pixel's smallest (depth, face index) pair into a 64-bit depth buffer with
 // an atomic; the result does not depend on the order of the lists or of the
@@ -51,6 +51,10 @@ namespace shv {
 constexpr float kRasterMinW = 1e-6f;
 constexpr int kTile = 8;                 // one wave per 8 x 8 tile
 constexpr int kTileThreads = kTile * kTile;
+// Entries of a tile's list (and the shared list after it) per wave of the
+// depth-buffer pass: short chunks give many short waves, which hide the
+// latency of the per-pixel divisions better than few long ones.
+constexpr int kChunk = 8;
 constexpr int kMaxBinTiles = 16;
 
 struct alignas(16) FaceRec {
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_setup(const float* __restr
 }
 
 // Exclusive scans, one block: the tile counts into offsets[0 .. n], and the
-// tiles' chunk counts (64 entries of the tile's list and the shared list per
+// tiles' chunk counts (kChunk entries of the tile's list and the shared list per
 // chunk) into chunk_off[0 .. n].  The chunk offsets are 64-bit: every tile
 // scans the whole shared list, so their total grows as tiles x shared-list
 // length and passes 2^31 on large images with many large faces.  The counts
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __rest
     for (int k = 0; k < kScanPer; ++k) {
       v[k] = seg[x * (kScanPer + 1) + k];
       sum += v[k];
-      csum += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + 63) / 64 : 0;
+      csum += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + kChunk - 1) / kChunk : 0;
     }
     int cur = 0;
     part[0][x] = sum;
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_scan(const int32_t* __rest
       seg[x * (kScanPer + 1) + k] = run;
       cseg[x * (kScanPer + 1) + k] = crun;
       run += v[k];
-      crun += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + 63) / 64 : 0;
+      crun += x * kScanPer + k < m ? ((int64_t)v[k] + nbig + kChunk - 1) / kChunk : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -315,8 +319,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_bin(const FaceRec* __restr
 }
 
 struct RasterShared {
-  FaceRec recs[kTileThreads];
-  int32_t ids[kTileThreads];
+  FaceRec recs[kChunk];
+  int32_t ids[kChunk];
 };
 
 // Coverage and depth of one pixel centre for one face: false if the face does
@@ -343,8 +347,13 @@ __device__ __forceinline__ bool cover(const FaceRec& r, int i, int j, float px, 
 }
 
 // Waves stride over the chunks of all tiles (chunk_off: the scan of the
-// tiles' chunk counts); a chunk is 64 entries of its tile's list followed by
-// the shared list, and its tile is found by binary search.  Each lane keeps
+// tiles' chunk counts); a chunk is kChunk entries of its tile's list followed by
+// the shared list.  Its tile is the last t with chunk_off[t] <= c, found by a
+// 64-way search: the wave's lanes probe 64 evenly spaced offsets of the
+// interval at once, and the count of probes at or below c (they form a
+// prefix, the offsets being non-decreasing) picks the sub-interval.  Each
+// round shrinks the interval to at most a 64th, so 4,097 offsets take two
+// rounds of dependent loads where a binary search takes twelve.  Each lane keeps
 // its pixel's smallest (depth, face) over the chunk and merges it into zbuf
 // with one atomic max of the bit-inverted key (depth bits above the face
 // index: positive floats order like their bits), which is the lexicographic
@@ -363,10 +372,14 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
   const int nbig = *big_count;
   for (int64_t c = blockIdx.x; c < total; c += gridDim.x) {
     int lo = 0, hi = tiles;  // chunk_off[lo] <= c < chunk_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (chunk_off[mid] <= c) lo = mid;
-      else hi = mid;
+    for (int round = 0; round < 8 && hi - lo > 1; ++round) {  // tiles < 2^24: four rounds suffice
+      const int64_t span = hi - lo;
+      const int probe = lo + (int)(((int64_t)(lane + 1) * span) >> 6);  // lane 63 probes hi
+      const bool le = probe < hi && chunk_off[probe] <= c;
+      const int k = __popcll(__ballot(le));  // probes of lanes 0 .. k-1 are <= c, that of lane k is not
+      const int nlo = k > 0 ? lo + (int)(((int64_t)k * span) >> 6) : lo;
+      hi = lo + (int)(((int64_t)(k + 1) * span) >> 6);
+      lo = nlo;
     }
     const int tile = lo;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -376,10 +389,10 @@ __global__ __launch_bounds__(kTileThreads) void k_raster_zbuf(const FaceRec* __r
     const float px = (float)i + 0.5f, py = (float)j + 0.5f;
     const int b0 = offsets[tile], nb = offsets[tile + 1] - b0;
     const int n = nb + nbig;
-    // below (nb + nbig) + 63 <= 17 T + 63 < 2^31 for T < 2^26
-    const int e = (int)(c - chunk_off[tile]) * kTileThreads + lane;
+    // below (nb + nbig) + kChunk <= 17 T + kChunk < 2^31 for T < 2^26
+    const int e = (int)(c - chunk_off[tile]) * kChunk + lane;
     bool meets = false;
-    if (e < n) {
+    if (lane < kChunk && e < n) {
       const int32_t f = e < nb ? list[b0 + e] : big_list[e - nb];
       if (f >= 0 && (int64_t)f < T) {  // every list entry is a face index; checked all the same
         const FaceRec r = rec[f];
@@ -578,7 +591,7 @@ size_t raster_bin_bytes(int64_t T, int width, int height) {
          (size_t)(2 * (tiles + 1) + 2 + (2 * kMaxBinTiles + 1) * T) * 4;
 }
 
-constexpr int kZbufWaves = 4096;  // waves of the depth-buffer pass (16 per CU), striding over the chunks
+constexpr int kZbufWaves = 8192;  // waves of the depth-buffer pass (32 per CU), striding over the chunks
 
 hipError_t launch_raster_forward(const float* verts, int64_t V, const int32_t* faces, int64_t T, const float* radiance,
                                  const RasterCam& cam, float* image, int32_t* face_id, void* rec, void* bins,
