@@ -535,28 +535,43 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_face_grads(const FaceRec* 
 
 // Per vertex: the corners of its incident faces in incidence order, then the
 // projection's adjoint.  inc holds 3 f + k for corner k of face f.
-__global__ __launch_bounds__(SHV_BLOCK) void k_raster_vertex_grads(const float* __restrict__ verts, int64_t V,
+constexpr int kVertThreads = 64;  // small blocks: V / 64 blocks spread over all CUs
+constexpr int kIncBatch = 8;      // incident corners whose loads are issued together
+
+__global__ __launch_bounds__(kVertThreads) void k_raster_vertex_grads(const float* __restrict__ verts, int64_t V,
                                                                    int64_t T, RasterCam cam,
                                                                    const int32_t* __restrict__ inc_ptr,
                                                                    const int32_t* __restrict__ inc,
                                                                    const float* __restrict__ part,
                                                                    float* __restrict__ grad_radiance,
                                                                    float* __restrict__ grad_verts) {
-  const int64_t v = (int64_t)blockIdx.x * SHV_BLOCK + threadIdx.x;
+  const int64_t v = (int64_t)blockIdx.x * kVertThreads + threadIdx.x;
   if (v >= V) return;
   const int64_t lim = 3 * T;
   int64_t b = inc_ptr[v], e = inc_ptr[v + 1];
   b = b < 0 ? 0 : (b > lim ? lim : b);
   e = e < b ? b : (e > lim ? lim : e);
   float gB = 0.0f, gx = 0.0f, gy = 0.0f, gw = 0.0f;
-  for (int64_t t = b; t < e; ++t) {
-    const int64_t c = inc[t];
-    if (c < 0 || c >= lim) continue;
-    const float* p = part + 4 * c;
-    gB += p[0];
-    gx += p[1];
-    gy += p[2];
-    gw += p[3];
+  // The corners' sums in incidence order; each batch issues its index loads,
+  // then its 16-byte partial loads, together.
+  for (int64_t t0 = b; t0 < e; t0 += kIncBatch) {
+    int64_t cs[kIncBatch];
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) cs[k] = t0 + k < e ? (int64_t)inc[t0 + k] : -1;
+    float4 q[kIncBatch];
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k)
+      q[k] = cs[k] >= 0 && cs[k] < lim ? *reinterpret_cast<const float4*>(part + 4 * cs[k])
+                                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int k = 0; k < kIncBatch; ++k) {
+      if (cs[k] >= 0 && cs[k] < lim) {
+        gB += q[k].x;
+        gx += q[k].y;
+        gy += q[k].z;
+        gw += q[k].w;
+      }
+    }
   }
   if (grad_radiance) grad_radiance[v] = gB;
   if (grad_verts) {
@@ -636,7 +651,7 @@ hipError_t launch_raster_backward(const float* grad_image, const float* verts, i
         (const FaceRec*)rec, T, faces, radiance, grad_image, face_id, cam.width, part);
   }
   if (V > 0) {
-    k_raster_vertex_grads<<<(unsigned)((V + SHV_BLOCK - 1) / SHV_BLOCK), SHV_BLOCK, 0, st>>>(
+    k_raster_vertex_grads<<<(unsigned)((V + kVertThreads - 1) / kVertThreads), kVertThreads, 0, st>>>(
         verts, V, T, cam, inc_ptr, inc, part, grad_radiance, grad_verts);
   }
   return hipGetLastError();
