@@ -508,10 +508,12 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_raster_face_grads(const FaceRec* 
   if (live && r.i0 <= r.i1 && r.j0 <= r.j1) {
     const int32_t* fv = faces + 3 * f;
     const float B[3] = {radiance[fv[0]], radiance[fv[1]], radiance[fv[2]]};
+    // the box is clamped to the image: at most 2^14 x 2^14 pixels, so 32-bit
+    // indices (and divisions) suffice
     const int bw = r.i1 - r.i0 + 1;
-    const int64_t n = (int64_t)bw * (r.j1 - r.j0 + 1);
-    for (int64_t t = sub; t < n; t += kFaceLanes) {
-      const int i = r.i0 + (int)(t % bw), j = r.j0 + (int)(t / bw);
+    const int n = bw * (r.j1 - r.j0 + 1);
+    for (int t = sub; t < n; t += kFaceLanes) {
+      const int i = r.i0 + t % bw, j = r.j0 + t / bw;
       const int64_t pix = (int64_t)j * width + i;
       if (face_id[pix] != (int32_t)f) continue;
       float gB[3], gx[3], gy[3], gw[3];
