@@ -65,8 +65,9 @@ hipError_t launch_sum_chunks(const float* part, int nchunks, int64_t len, float*
 
 // out[c] = sum_r part[r * cols + c] for the 16 columns c = 16 cb .. 16 cb + 15.
 // Thread t owns column 16 cb + (t % 16) and row group g = t / 16 (16 groups);
-// it sums rows g, g + 16, g + 32, ... in increasing order (loads issued 8 rows
-// at a time; each wave reads four contiguous 64-byte row segments), then the
+// it sums rows g, g + 16, g + 32, ... in increasing order (loads issued 16 rows
+// at a time, the last batch predicated; each wave reads four contiguous
+// 64-byte row segments), then the
 // 16 group partials of a column are added in group order.  The canonical
 // order of every column reduction (receiver tiles -> sphere and lighting
 // gradients).
@@ -79,15 +80,15 @@ __device__ __forceinline__ void reduce_columns(const float* __restrict__ part, i
   const int c = cb * kColsPerBlock + l;
   float a = 0.0f;
   if (c < cols) {
-    int r = g;
-    for (; r + 7 * kRowGroups < rows; r += 8 * kRowGroups) {
-      float v[8];
+    for (int r = g; r < rows; r += 16 * kRowGroups) {
+      float v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(r + u * kRowGroups) * cols + c];
+      for (int u = 0; u < 16; ++u)
+        v[u] = r + u * kRowGroups < rows ? part[(int64_t)(r + u * kRowGroups) * cols + c] : 0.0f;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a += v[u];
+      for (int u = 0; u < 16; ++u)
+        if (r + u * kRowGroups < rows) a += v[u];
     }
-    for (; r < rows; r += kRowGroups) a += part[(int64_t)r * cols + c];
   }
   buf[threadIdx.x] = a;
   __syncthreads();
