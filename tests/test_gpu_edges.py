@@ -208,3 +208,43 @@ def test_zero_radius_spheres_are_invisible():
     assert rel_max(h["B"], h2["B"]) < 1e-6
     assert np.all(np.isfinite(h["grad_spheres"]))
     assert np.allclose(h["grad_spheres"][keep], h2["grad_spheres"], rtol=1e-5, atol=1e-6 * np.abs(h2["grad_spheres"]).max())
+
+
+def _mode_flags(mode):
+    L = lib()
+    return {"product": L.SHV_FLAG_EXP_PRODUCT, "quadrature": L.SHV_FLAG_EXP_QUADRATURE,
+            "taylor2": L.SHV_FLAG_EXP_TAYLOR | L.SHV_FLAG_EXP_TAYLOR_ORDER(2)}[mode]
+
+
+@pytest.mark.parametrize("mode", ["product", "quadrature", "taylor2"])
+def test_exponential_modes_without_spheres(mode):
+    """No occluders under every other way of forming V: V is the unoccluded
+    sqrt(4 pi) e_0, the point gradients are exactly zero, and the shading and
+    lighting gradient equal the oracle's."""
+    from oracle import method
+    sc = scenegen.scene_random_shell(3, 300, 0, 8)
+    sc["spheres"] = np.zeros((0, 4), np.float32)
+    w = sc["grad_radiance"]
+    h = run_hip(sc, w, flags=_mode_flags(mode))
+    o = {k: v.detach().numpy() for k, v in method.run_forward_backward(sc, w, exp_mode=mode).items()}
+    e0 = np.zeros(64)
+    e0[0] = np.sqrt(4 * np.pi)
+    assert np.abs(h["V"] - e0).max() < 1e-5
+    assert rel_max(h["B"], o["B"]) < 1e-5
+    assert h["grad_spheres"].shape == (0, 4)
+    assert np.all(h["grad_points"] == 0)
+    assert rel_l2(h["grad_light"], o["grad_light"]) < 1e-4
+
+
+@pytest.mark.parametrize("mode", ["product", "quadrature", "taylor2"])
+def test_exponential_modes_single_receiver_and_sphere(mode):
+    """One receiver (a block of 64 lanes with 63 idle) and one sphere under
+    every other way of forming V, against the oracle's same mode."""
+    from oracle import method
+    sc = scenegen.scene_random_shell(4, 1, 1, 5)
+    w = sc["grad_radiance"]
+    h = run_hip(sc, w, flags=_mode_flags(mode))
+    o = {k: v.detach().numpy() for k, v in method.run_forward_backward(sc, w, exp_mode=mode).items()}
+    assert rel_l2(h["V"], o["V"]) < 1e-5 and rel_max(h["B"], o["B"]) < 1e-5
+    for key in ("grad_points", "grad_spheres", "grad_light", "grad_normals", "grad_albedo"):
+        assert rel_l2(h[key], o[key]) < 1e-4, key
