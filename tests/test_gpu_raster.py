@@ -106,6 +106,17 @@ def test_raster_wide_image_scans_in_several_segments():
     check(sc["points"], sc["faces"], B, sc["camera"], sc["width"], sc["height"], sc["grad_image"])
 
 
+@pytest.mark.parametrize("width,height", [(1, 1), (7, 3)])
+def test_raster_tiny_images(width, height):
+    """The whole body inside one tile smaller than 8 x 8: most of the 42,480
+    faces miss every pixel centre or have an empty box, and a pixel's
+    nearest face is found among thousands of candidates."""
+    sc = scenegen.scene_mesh_body(width=width, height=height)
+    rng = np.random.default_rng(9)
+    B = rng.uniform(0.0, 2.0, len(sc["points"])).astype(np.float32)
+    check(sc["points"], sc["faces"], B, sc["camera"], width, height, sc["grad_image"])
+
+
 def test_raster_degenerate_faces():
     """A face behind the camera, a zero-area face and a face with an index
     outside [0, V) are not drawn; the rest is unchanged (the oracle sees the
