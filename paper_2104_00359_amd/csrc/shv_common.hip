@@ -47,8 +47,16 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st) {
 __device__ __forceinline__ void sum_chunks_at(const float* __restrict__ part, int nchunks, int64_t len, int64_t j,
                                               float* __restrict__ out) {
   if (j >= len) return;
+  // chunks added in increasing order; their loads issued eight at a time
   float a = part[j];
-  for (int c = 1; c < nchunks; ++c) a += part[(int64_t)c * len + j];
+  for (int c0 = 1; c0 < nchunks; c0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = c0 + u < nchunks ? part[(int64_t)(c0 + u) * len + j] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < nchunks) a += v[u];
+  }
   out[j] = a;
 }
 
