@@ -118,14 +118,19 @@ def test_raster_tiny_images(width, height):
 
 
 def test_raster_degenerate_faces():
-    """A face behind the camera, a zero-area face and a face with an index
-    outside [0, V) are not drawn; the rest is unchanged (the oracle sees the
-    invalid face as a zero-area one)."""
+    """A face behind the camera, a face with one corner behind it (its
+    projection flips across the image), a zero-area face and a face with an
+    index outside [0, V) are not drawn; the rest is unchanged (the oracle sees
+    the invalid face as a zero-area one)."""
     sc = scenegen.scene_mesh_body(width=64, height=64)
     verts = sc["points"].copy()
     faces = sc["faces"].copy()
-    verts = np.concatenate([verts, np.array([[0.0, 10.0, 1.0], [0.2, 10.0, 1.0], [0.0, 10.0, 1.2]], np.float32)])
-    extra = np.array([[len(verts) - 3, len(verts) - 2, len(verts) - 1], [5, 5, 7], [0, 1, 2]], np.int32)
+    eye_y = float(np.mean(sc["points"][:, 1])) + 4.0
+    behind = np.array([[0.0, 10.0, 1.0], [0.2, 10.0, 1.0], [0.0, 10.0, 1.2]], np.float32)
+    straddle = np.array([[-0.3, 0.0, 0.9], [0.3, 0.0, 0.9], [0.0, eye_y + 1.0, 1.1]], np.float32)
+    verts = np.concatenate([verts, behind, straddle])
+    n0 = len(verts) - 6
+    extra = np.array([[n0, n0 + 1, n0 + 2], [5, 5, 7], [0, 1, 2], [n0 + 3, n0 + 4, n0 + 5]], np.int32)
     faces = np.concatenate([extra, faces])
     rng = np.random.default_rng(6)
     B = rng.uniform(0.0, 2.0, len(verts)).astype(np.float32)
@@ -137,7 +142,7 @@ def test_raster_degenerate_faces():
     fid, img, gB, gv = run_raster(verts, bad, B, sc["camera"], 64, 64, gI, inc_faces=ref)
     ofid, oimg = raster.render(verts, ref, B, sc["camera"], 64, 64)
     assert np.array_equal(fid, ofid)
-    assert not np.isin(fid, [0, 1, 2]).any()
+    assert not np.isin(fid, [0, 1, 2, 3]).any()
     assert rel_max(img, oimg.numpy()) <= 3e-4
     ogB, ogv = raster.render_backward(verts, ref, B, sc["camera"], ofid, gI)
     assert rel_l2(gB, ogB.numpy()) <= 1e-4 and rel_l2(gv, ogv.numpy()) <= 1.5e-3
