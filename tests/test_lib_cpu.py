@@ -271,6 +271,14 @@ def test_raster_incidence_and_argument_checks(L):
     with pytest.raises(RuntimeError):
         L.shv_raster_incidence_build(bad, T, V, ptr, idx)
     assert L.shv_raster_workspace_bytes(V, T, 64, 48) >= T * (64 + 17 * 4)
+    # the forward's scratch: 64-byte face records, then an 8-byte depth key per
+    # pixel, 64-bit chunk offsets and 32-bit counts and offsets per tile (plus
+    # one), the shared-list count and a pad word, 16 slots and 16 list
+    # entries per face and the shared list
+    for (v, t, w, h) in [(V, T, 64, 48), (100, 1, 1, 1), (5000, 9000, 1024, 600), (3, 1, 16384, 16384)]:
+        tiles = ((w + 7) // 8) * ((h + 7) // 8)
+        layout = 8 * w * h + 8 * (tiles + 1) + 4 * (2 * (tiles + 1) + 2 + 33 * t)
+        assert L.shv_raster_workspace_bytes(v, t, w, h) >= 64 * t + layout, (v, t, w, h)
     assert L.shv_raster_workspace_bytes(-1, T, 64, 48) == 0
     assert L.shv_raster_workspace_bytes(V, T, 0, 48) == 0
     assert L.shv_raster_workspace_bytes(V, 1 << 26, 64, 48) == 0
