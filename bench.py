@@ -1,43 +1,30 @@
 """Benchmark: point-sphere pair evaluations per second, forward + backward.
 
-Default workload (one step = the whole differentiable path on one scene
-resident in HBM): the body-like scene (20,000 receivers on 24 capsules, 128
-spheres, 8 bands, k = 4), synthetic and seeded, through the fused
-sh_render_forward (visibility + shading) and sh_render_backward (gradients
-for receivers, normals, albedo, spheres and lighting) of the C ABI
-(``--path separate`` uses the four separate entry points instead; the results
-are bit-identical; ``--path separate --flags 4`` takes the exponential by
-quadrature projection on MFMA instead of scaling and squaring, and
-``--path separate --flags 8`` forms V by the direct product chain of Eq. 12).
+Default workload (``--workload batched64``): 64 independent scenes (P ~
+U{5k..50k}, S ~ U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b; 270,399,872
+pairs), resident in HBM.  One step = the batched forward + backward of all 64
+(sh_solve_batched's launches) replayed from the library's HIP graph
+(shv_graph_launch: table copy + one graph launch).  The timed steps carry no
+profiling; per-kernel durations come from HIP events around every launch of
+a separate window of eager sh_solve_batched steps on the same stream, after
+the timed region.  The same line carries, as extra keys:
 
-``--workload serve``: Poisson arrivals of forward + backward requests (90%
-from the 64-scene distribution, 10% at 262,144 receivers x 512 spheres)
-against the continuous-batching server and against one request at a time,
-per arrival rate; prints throughput and p50 / p99 latency.
+* ``sequential``: the 64 scenes through 64 single-scene sh_render_forward +
+  sh_render_backward calls, eager;
+* ``serve``: Poisson arrivals at 2,000 requests/s (90% from the 64-scene
+  distribution, 10% at 262,144 receivers x 512 spheres) against the
+  continuous-batching server (graph mode) and one request at a time, with
+  throughput and p50 / p99 latency;
+* ``body``: the body-like scene (20,000 receivers x 128 spheres, n = 8)
+  through sh_render_forward / sh_render_backward;
+* ``cpu_baseline``: the FP64 oracle on the host's cores, a process pool over
+  receiver chunks (all cores and single core, forward and forward +
+  backward), on a bounded seeded sample.
 
-``--workload rgb``: the body-like scene with three colour channels (albedo
-and lighting per channel, one shared visibility, Eq. 8 per channel); one step
-= sh_visibility_forward, sh_shade_channels, sh_shade_channels_backward and
-sh_visibility_backward.  ``--workload envmap``: the lighting of a synthetic
-3 x 512 x 1024 equirectangular map projected onto 8 bands (Eq. 9) through
-sh_envmap_project; throughput in map pixels per second.
-
-``--workload inverse``: one gradient-descent iteration of the inverse problem
-on the body-like scene, every step in the library: the embedded deformation
-driven by the spheres (each attached to its 625 nearest receivers) and a global
-pose, visibility and shading, the mean-squared loss against a target rendered
-from a perturbed scene, their adjoints, and the parameter update.
-
-``--workload batched64``: 64 independent scenes (P ~ U{5k..50k}, S ~
-U{32..256}, n ~ U{4, 6, 8}, seeds 100 + b); one step = the batched forward +
-backward over all 64, replayed from one captured graph; the same 64 scenes
-through 64 sequential single-scene forward + backward calls are timed beside
-it.
-
-Prints one JSON line with the throughput, a roofline entry for the dominant
-kernel (its average launch time from HIP events recorded around every launch
-on the launch stream, during eager steps) and the FP64 oracle timed on a
-bounded sample on the host's cores.
+Other workloads (``--workload``): body, gbuffer (512 x 512 receivers x 256
+spheres), icosphere, serve (a sweep of arrival rates), rgb, envmap, inverse,
+image; ``--path separate`` and ``--flags`` select the separate entry points
+and the other ways of forming V on the single-scene workloads.
 """
 from __future__ import annotations
 
@@ -59,15 +46,19 @@ METRIC = "point-sphere pair evals/s fwd+bwd"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="body",
-                    choices=["body", "gbuffer", "icosphere", "batched64", "serve", "rgb", "envmap", "inverse",
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="batched64",
+                    choices=["batched64", "body", "gbuffer", "icosphere", "serve", "rgb", "envmap", "inverse",
                              "image"])
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="steps of the separate per-kernel timing window (0: steps / 4, at least 5)")
     ap.add_argument("--channels", type=int, default=3, help="rgb / envmap: colour channels")
     ap.add_argument("--map", default="512x1024", help="envmap: H x W of the equirectangular map")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target duration of the oracle CPU baseline sample (0 disables it)")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="total duration of the oracle CPU baseline's four timed legs (0 disables it)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-core CPU baseline (0: the CPUs this process may run on, at most 16)")
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--path", default="render", choices=["render", "separate"])
     ap.add_argument("--flags", type=int, default=0,
@@ -75,13 +66,17 @@ def parse():
                          "quadrature exponential, 8 the direct product chain of Eq. 12, 16 | (K << 8) the "
                          "Taylor series of order K (different approximations; separate entry points only)")
     ap.add_argument("--no-graph", action="store_true",
-                    help="batched64: time eager batched calls instead of graph replays")
+                    help="batched64: time eager sh_solve_batched calls instead of graph launches")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batched64: leave out the serve, sequential and body legs (profiling runs)")
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
                     help="serve: Poisson arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=4.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--chunk-pairs", type=int, default=32 << 20, help="serve: pair bound of a request range")
     ap.add_argument("--step-pairs", type=int, default=128 << 20, help="serve: pair bound of a step")
-    ap.add_argument("--modes", default="continuous,one_at_a_time", help="serve: scheduler modes to sweep")
+    ap.add_argument("--modes", default="continuous,one_at_a_time",
+                    help="serve: scheduler modes to sweep (continuous = graph steps, continuous_eager, "
+                         "one_at_a_time)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device once (a plain copy kernel "
                          "of known size, to calibrate HBM byte counters)")
@@ -106,6 +101,15 @@ def make_scene(name):
     return sc, desc
 
 
+def workload_scenes(name):
+    """Host scenes of a workload (the CPU baseline's workers rebuild them from
+    the same seeds)."""
+    import scenegen
+    if name == "batched64":
+        return [scenegen.scene_batched(b) for b in range(64)]
+    return [make_scene(name)[0]]
+
+
 def saved_buffer_floats(lib, P, prm):
     """Floats of a state buffer that serves both the fused render entry points
     and the separate visibility ones (whose state grows with the Taylor
@@ -113,39 +117,126 @@ def saved_buffer_floats(lib, P, prm):
     return max(lib.shv_render_saved_floats(P, prm), lib.shv_saved_floats(P, prm), 1)
 
 
-def cpu_baseline(scenes, k, seconds, exp_mode="squaring"):
-    """The FP64 oracle (autograd for the backward) on seeded samples of
-    receivers (chunks of 256, all spheres), cycling over ``scenes`` until
-    ``seconds`` have elapsed or every receiver is done."""
-    import numpy as np
+# ---------------------------------------------------------------- CPU baseline
+# The FP64 oracle timed on the host's cores: a pool of processes, one thread
+# each, over chunks of 256 receivers (all spheres of the scene), cycling over
+# the scenes; each scene contributes a fixed seeded subset of at most 8,192
+# receivers (pairs/s is linear in the receiver count).
+
+CPU_CHUNK = 256
+CPU_SUBSET = 8192
+_CPU = {}
+
+
+def _cpu_init(workload, k, exp_mode):
     import torch
+    torch.set_num_threads(1)
+    _CPU.update(scenes=workload_scenes(workload), k=k, mode=exp_mode)
+
+
+def _cpu_task(task):
+    import numpy as np
 
     from oracle import method
-    perms = [np.random.default_rng(123 + i).permutation(sc["points"].shape[0]) for i, sc in enumerate(scenes)]
-    done = [0] * len(scenes)
-    pairs = 0
-    t0 = time.perf_counter()
-    i = 0
-    while time.perf_counter() - t0 < seconds:
-        j = i % len(scenes)
-        sc = scenes[j]
-        if done[j] < sc["points"].shape[0]:
-            idx = np.sort(perms[j][done[j]:done[j] + 256])
-            method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=k, idx=idx, exp_mode=exp_mode)
-            done[j] += len(idx)
-            pairs += len(idx) * sc["spheres"].shape[0]
-        elif all(d >= s["points"].shape[0] for d, s in zip(done, scenes)):
-            break
-        i += 1
-    dt = time.perf_counter() - t0
-    tot = sum(s["points"].shape[0] for s in scenes)
-    where = (f"{done[0]} of {tot} receivers (seeded permutation)" if len(scenes) == 1 else
-             f"{sum(done)} of {tot} receivers over {sum(1 for d in done if d)} of {len(scenes)} scenes "
-             "(seeded permutations, 256 per scene in turn)")
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{where} x all spheres, FP64 forward + autograd backward"
-                      f"{'' if exp_mode == 'squaring' else f' ({exp_mode} mode)'}, {dt:.1f} s"}
+    j, idx, backward = task
+    sc = _CPU["scenes"][j]
+    idx = np.asarray(idx)
+    if backward:
+        method.run_forward_backward(sc, sc["grad_radiance"][idx], n_squarings=_CPU["k"], idx=idx,
+                                    exp_mode=_CPU["mode"])
+    else:
+        method.run_forward(sc, n_squarings=_CPU["k"], idx=idx, exp_mode=_CPU["mode"])
+    return len(idx) * int(sc["spheres"].shape[0])
 
+
+def _cpu_tasks(scenes, backward):
+    """Chunks of each scene's seeded subset, scenes taken in turn."""
+    import numpy as np
+    per = []
+    for i, sc in enumerate(scenes):
+        P = sc["points"].shape[0]
+        sub = np.sort(np.random.default_rng(123 + i).permutation(P)[:CPU_SUBSET])
+        per.append([sub[a:a + CPU_CHUNK] for a in range(0, len(sub), CPU_CHUNK)])
+    out = []
+    for r in range(max(len(c) for c in per)):
+        for j, chunks in enumerate(per):
+            if r < len(chunks):
+                out.append((j, chunks[r].tolist(), backward))
+    return out
+
+
+def _cpu_leg(pool, procs, tasks, seconds):
+    """Pairs/s of the chunks completed: tasks are submitted while ``seconds``
+    have not passed, at most two per process in flight, and the ones in flight
+    at the deadline are finished and counted with the time they took."""
+    import collections
+    t0 = time.perf_counter()
+    it = iter(tasks)
+    inflight = collections.deque()
+
+    def submit():
+        task = next(it, None)
+        if task is not None:
+            inflight.append(pool.apply_async(_cpu_task, (task,)))
+
+    for _ in range(2 * procs):
+        submit()
+    pairs, n = 0, 0
+    while inflight:
+        pairs += inflight.popleft().get()
+        n += 1
+        if time.perf_counter() - t0 < seconds:
+            submit()
+    dt = time.perf_counter() - t0
+    return pairs / dt, n, dt
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, k, seconds, workers=0, exp_mode="squaring"):
+    """The oracle's pairs/s on the host: forward + backward (autograd) on all
+    cores is the reported value; single-core and forward-only figures are kept
+    beside it."""
+    import multiprocessing as mp
+
+    scenes = workload_scenes(workload)
+    avail = len(os.sched_getaffinity(0))
+    nw = workers if workers > 0 else min(avail, 16)
+    ctx = mp.get_context("spawn")
+    legs = {}
+    share = {"fwd_1": 0.15, "fwdbwd_1": 0.25, "fwd_all": 0.25, "fwdbwd_all": 0.35}
+    for name, procs in (("1", 1), ("all", nw)):
+        with ctx.Pool(procs, initializer=_cpu_init, initargs=(workload, k, exp_mode)) as pool:
+            pool.map(_cpu_task, [(0, [0], False)] * procs)        # start-up (imports, scenes) not timed
+            for kind, backward in (("fwd", False), ("fwdbwd", True)):
+                tasks = _cpu_tasks(scenes, backward)
+                rate, n, dt = _cpu_leg(pool, procs, tasks, seconds * share[f"{kind}_{name}"])
+                legs[f"{kind}_{name}"] = {"pairs_per_s": rate, "chunks": n, "seconds": round(dt, 2)}
+            pool.terminate()
+    total = sum(s["points"].shape[0] for s in scenes)
+    sub = sum(min(s["points"].shape[0], CPU_SUBSET) for s in scenes)
+    return {"value": legs["fwdbwd_all"]["pairs_per_s"], "unit": "pairs/s", "cores": nw, "kind": "oracle",
+            "sample": f"FP64 forward + autograd backward{'' if exp_mode == 'squaring' else f' ({exp_mode} mode)'}, "
+                      f"{nw} processes x 1 thread over chunks of {CPU_CHUNK} receivers x all spheres, from a seeded "
+                      f"subset of <= {CPU_SUBSET} receivers per scene ({sub} of {total} receivers over "
+                      f"{len(scenes)} scene(s)), {legs['fwdbwd_all']['chunks']} chunks in "
+                      f"{legs['fwdbwd_all']['seconds']} s",
+            "cpu_model": cpu_model(), "cpus_available": avail,
+            "forward_all_cores": legs["fwd_all"]["pairs_per_s"],
+            "forward_single_core": legs["fwd_1"]["pairs_per_s"],
+            "fwd_bwd_single_core": legs["fwdbwd_1"]["pairs_per_s"], "legs": legs}
+
+
+# ---------------------------------------------------------------- timing
 
 def kernel_table(prof):
     kernels = {}
@@ -222,39 +313,46 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def timed(step, stream, warmup, steps, profile, every=10):
-    """Average milliseconds per step over ``steps`` steps after ``warmup``.
-    With ``profile``, one step in ``every`` of the timed steps also records a
-    HIP event pair around each of its launches (on the launch stream), and
-    the library's per-kernel report over those sampled steps is returned.
-    Events around every launch would add about 4 us per launch to the timed
-    steps; sampling keeps that to a tenth."""
+def timed(step, stream, warmup, steps):
+    """Average milliseconds per step over ``steps`` steps after ``warmup``,
+    with nothing else in the timed region (no profiling)."""
     import torch
-
-    from paper_2104_00359_amd import _lib
     with torch.cuda.stream(stream):
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        if profile:
-            _lib.shv_profile_enable(True, capacity=40 * (steps // every + 1) + 64)
-            _lib.shv_profile_enable(False)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(steps):
-            sample = profile and i % every == 0
-            if sample:
-                _lib.shv_profile_enable(True, resume=True)
+        for _ in range(steps):
             step()
-            if sample:
-                _lib.shv_profile_enable(False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    return (t1 - t0) * 1e3 / steps, (_lib.shv_profile_report() if profile else None)
+    return (t1 - t0) * 1e3 / steps
 
 
-def sampled_steps(steps, every=10):
-    return (steps + every - 1) // every
+def profile_window(step, stream, steps):
+    """Per-kernel report ({name: (launches, total ms)}) of ``steps`` further
+    steps with a HIP event pair recorded around each launch on the launch
+    stream (the event pool is created before the window)."""
+    import torch
+
+    from paper_2104_00359_amd import _lib
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _lib.shv_profile_enable(True, capacity=64 * steps + 64)
+        for _ in range(steps):
+            step()
+        _lib.shv_profile_enable(False)
+        torch.cuda.synchronize()
+    return _lib.shv_profile_report()
+
+
+def timed_and_profiled(step, stream, args):
+    """(ms per step of the unprofiled timed steps, per-kernel report of the
+    separate window, steps in that window).  The window runs first, untimed
+    (it also brings the GPU to its working clocks)."""
+    n = args.profile_steps or max(args.steps // 4, 5)
+    prof = profile_window(step, stream, n)
+    return timed(step, stream, args.warmup, args.steps), prof, n
 
 
 def copy_calibration(args, dev, stream):
@@ -276,13 +374,14 @@ def finish_kernels(kernels):
     return kernels
 
 
-def bench_single(args):
+def bench_single(args, workload=None, with_cpu=True):
     import numpy as np
     import torch
 
     from paper_2104_00359_amd import _lib, ops, workmodel
 
-    sc, desc = make_scene(args.workload)
+    workload = workload or args.workload
+    sc, desc = make_scene(workload)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     ops.ensure_init(dev)
@@ -291,7 +390,9 @@ def bench_single(args):
     P = sc["points"].shape[0]
     S = sc["spheres"].shape[0]
     k = args.k
-    prm = _lib.params(n, 3.0, k, args.flags)
+    flags = args.flags if workload == args.workload else 0
+    path = args.path if workload == args.workload else "render"
+    prm = _lib.params(n, 3.0, k, flags)
 
     def t(a):
         return torch.as_tensor(np.ascontiguousarray(a)).to(dev)
@@ -301,6 +402,7 @@ def bench_single(args):
     gB = t(sc["grad_radiance"])
     vis = torch.empty(N, P, device=dev)
     saved = torch.empty(saved_buffer_floats(_lib, P, prm), device=dev)
+    sb = _lib.nbytes(saved)
     rad = torch.empty(P, device=dev)
     gV = torch.empty(N, P, device=dev)
     gN = torch.empty(3, P, device=dev)
@@ -313,105 +415,40 @@ def bench_single(args):
     stream = torch.cuda.Stream(device=dev)   # default priority
     st = stream.cuda_stream
 
-    if args.path == "render":
+    if path == "render":
         def step():
-            _lib.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, ws, nb, st)
-            _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, gP, gN, gA, gS, gL, ws, nb, st)
+            _lib.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, sb, ws, nb, st)
+            _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, sb, gP, gN, gA, gS, gL, ws, nb, st)
     else:
         def step():
-            _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+            _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, sb, ws, nb, st)
             _lib.sh_shade(vis, nrm, alb, lig, P, prm, rad, ws, nb, st)
             _lib.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, gN, gA, gL, ws, nb, st)
-            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
+            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, sb, gP, gS, ws, nb, st)
 
-    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    ms, prof, nprof = timed_and_profiled(step, stream, args)
     copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
-    order = (args.flags >> 8) & 15 if args.flags & _lib.SHV_FLAG_EXP_TAYLOR else 0
-    roof = roofline(kernels, sampled_steps(args.steps),
-                    lambda name: workmodel.kernel_work(name, n, k, P, S, order=order))
+    order = (flags >> 8) & 15 if flags & _lib.SHV_FLAG_EXP_TAYLOR else 0
+    roof = roofline(kernels, nprof, lambda name: workmodel.kernel_work(name, n, k, P, S, order=order))
     if roof is not None:
-        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
-    mode = {4: "quadrature", 8: "product"}.get(args.flags, f"taylor{order}" if order else "squaring")
-    cpu = cpu_baseline([sc], k, args.cpu_seconds, mode) if args.cpu_seconds > 0 else None
+        roof["traffic"] = measured_traffic(workload, roof["kernel"])
+    mode = {4: "quadrature", 8: "product"}.get(flags, f"taylor{order}" if order else "squaring")
+    cpu = (cpu_baseline(workload, k, args.cpu_seconds, args.cpu_workers, mode)
+           if with_cpu and args.cpu_seconds > 0 else None)
     return {
         "metric": METRIC, "value": P * S / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0,
-                   "entry_points": args.path, "visibility": mode},
-        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
+                   "entry_points": path, "visibility": mode},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels), "profiled_steps": nprof,
     }
 
 
-def bench_batched(args):
-    import torch
-
-    import scenegen
-    from paper_2104_00359_amd import _lib, batch, ops, workmodel
-
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    ops.ensure_init(dev)
-    k = args.k
-    scenes = [scenegen.scene_batched(b) for b in range(64)]
-    bufs = [batch.scene_buffers(sc, dev, n_squarings=k) for sc in scenes]
-    rb = batch.RenderBatch(bufs, dev)
-    pairs = rb.pairs
-    stream = torch.cuda.Stream(device=dev)   # default priority
-    st = stream.cuda_stream
-
-    def batched():
-        rb.forward(stream)
-        rb.backward(stream)
-
-    def sequential():
-        for b in bufs:
-            o, prm = b.out, b.params()
-            ws_bytes = o["ws"].numel()
-            _lib.sh_render_forward(b.points, b.normals, b.albedo, b.spheres, b.light, b.P, b.S, prm, o["vis"],
-                                   o["radiance"], o["saved"], o["ws"], ws_bytes, st)
-            _lib.sh_render_backward(b.grad_radiance, b.points, b.normals, b.albedo, b.spheres, b.P, b.S, prm,
-                                    o["vis"], o["saved"], o["grad_points"], o["grad_normals"], o["grad_albedo"],
-                                    o["grad_spheres"], o["grad_light"], o["ws"], ws_bytes, st)
-
-    # per-kernel times from eager batched steps
-    steps_prof = max(args.steps // 4, 5)
-    ms_eager, prof = timed(batched, stream, args.warmup, steps_prof, True, every=1)
-    ms_seq, _ = timed(sequential, stream, max(args.warmup // 4, 2), max(args.steps // 4, 5), False)
-    if args.no_graph:
-        ms, mode = ms_eager, "eager batched calls"
-    else:
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            batched()
-        torch.cuda.synchronize()
-        ms, _ = timed(g.replay, stream, args.warmup, args.steps, False)
-        mode = "one captured graph (all batched phases) per step"
-    kernels = kernel_table(prof)
-    desc = [(b.n_bands, k, b.P, b.S) for b in bufs]
-    roof = roofline(kernels, steps_prof, lambda name: workmodel.batch_work(name, desc))
-    cpu = cpu_baseline(scenes, k, args.cpu_seconds) if args.cpu_seconds > 0 else None
-    return {
-        "metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "64 independent scenes: P ~ U{5000..50000}, S ~ U{32..256}, n ~ U{4,6,8} "
-                               "(seeds 100+b), k=4, fwd+bwd, batched",
-                   "scenes": 64, "pairs_per_step": pairs, "receivers": sum(b.P for b in bufs),
-                   "n_squarings": k, "eps": 3.0, "launch": mode},
-        "batched_eager": {"ms_per_step": ms_eager, "value": pairs / (ms_eager * 1e-3)},
-        "sequential": {"ms_per_step": ms_seq, "value": pairs / (ms_seq * 1e-3),
-                       "what": "64 x (sh_render_forward + sh_render_backward), eager"},
-        "speedup_vs_sequential": ms_seq / ms,
-        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels),
-    }
-
-
-def bench_serve(args):
-    """Poisson load against the continuous-batching server and against one
-    request at a time (single-scene calls), per arrival rate."""
+def serve_leg(args, rate, duration, modes):
+    """Poisson arrivals at ``rate`` for ``duration`` seconds per scheduler mode;
+    one result dict per mode."""
     import dataclasses
 
     import numpy as np
@@ -421,14 +458,12 @@ def bench_serve(args):
     from paper_2104_00359_amd import batch, serve
 
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     small = [batch.scene_buffers(scenegen.scene_batched(b), dev) for b in range(64)]
     large = [batch.scene_buffers(scenegen.large_request_scene(500 + i), dev) for i in range(4)]
     free, _ = torch.cuda.mem_get_info(dev)
     budget = int(free - (16 << 30))
-    rates = [float(r) for r in args.rates.split(",")]
     pick_rng = np.random.default_rng(7)
-    n_max = int(max(rates) * args.duration * 1.5 + 100)
+    n_max = int(rate * duration * 1.5 + 100)
     is_large = pick_rng.random(n_max) < 0.1
     which = np.where(is_large, pick_rng.integers(0, 4, n_max), pick_rng.integers(0, 64, n_max))
 
@@ -438,23 +473,132 @@ def bench_serve(args):
 
     mean_pairs = float(np.mean([(large[w] if l else small[w]).P * (large[w] if l else small[w]).S
                                 for l, w in zip(is_large[:2000], which[:2000])]))
-    results = {m: [] for m in args.modes.split(",")}
-    for mode in results:
-        for rate in rates:
-            if mode in ("continuous", "continuous_graph"):
-                ex = serve.GpuExecutor(dev, graphs=mode == "continuous_graph")
-                sched = serve.Scheduler(ex, budget, chunk_pairs=args.chunk_pairs, step_pairs=args.step_pairs,
-                                        max_inflight=2, keep_results=False, admit_ahead=4 * args.step_pairs)
-            else:
-                ex = serve.GpuExecutor(dev, single_scene=True)
-                sched = serve.Scheduler(ex, budget, chunk_pairs=None, max_active=1, max_inflight=1,
-                                        keep_results=False)
-            sched.start()
-            r = serve.run_load(sched, make_request, rate, args.duration, warmup=0.5, seed=7, drain=15.0)
-            sched.stop(timeout=30)
-            torch.cuda.synchronize()
-            print(f"[serve] {mode} rate {rate:g}: {json.dumps(r)}", file=sys.stderr, flush=True)
-            results[mode].append(r)
+    out = {}
+    for mode in modes:
+        if mode in ("continuous", "continuous_eager"):
+            ex = serve.GpuExecutor(dev, graphs=mode == "continuous")
+            sched = serve.Scheduler(ex, budget, chunk_pairs=args.chunk_pairs, step_pairs=args.step_pairs,
+                                    max_inflight=2, keep_results=False, admit_ahead=4 * args.step_pairs)
+        else:
+            ex = serve.GpuExecutor(dev, single_scene=True, graphs=False)
+            sched = serve.Scheduler(ex, budget, chunk_pairs=None, max_active=1, max_inflight=1, keep_results=False)
+        sched.start()
+        r = serve.run_load(sched, make_request, rate, duration, warmup=0.5, seed=7, drain=15.0)
+        sched.stop(timeout=30)
+        torch.cuda.synchronize()
+        if ex.graph is not None:
+            r["graph_steps"], r["eager_steps"] = ex.graph.graph_steps, ex.graph.eager_steps
+        ex.close()
+        print(f"[serve] {mode} rate {rate:g}: {json.dumps(r)}", file=sys.stderr, flush=True)
+        out[mode] = r
+    return out, budget, mean_pairs
+
+
+def bench_batched(args):
+    import torch
+
+    import scenegen
+    from paper_2104_00359_amd import _lib, batch, ops, workmodel
+
+    # the host baseline first: its worker processes start before this one holds the GPU busy
+    cpu = cpu_baseline("batched64", args.k, args.cpu_seconds, args.cpu_workers) if args.cpu_seconds > 0 else None
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ops.ensure_init(dev)
+    k = args.k
+    scenes = [scenegen.scene_batched(b) for b in range(64)]
+    bufs = [batch.scene_buffers(sc, dev, n_squarings=k) for sc in scenes]
+    rb = batch.RenderBatch(bufs, dev)
+    records = [b.record() for b in bufs]
+    pairs = rb.pairs
+    stream = torch.cuda.Stream(device=dev)   # default priority
+    st = stream.cuda_stream
+
+    def eager():
+        _lib.sh_solve_batched(rb.table, rb.grid, rb.tab._handle(stream))
+
+    graph = None
+    if args.no_graph:
+        step, mode = eager, "eager sh_solve_batched calls"
+    else:
+        graph = _lib.shv_graph_create(rb.grid, len(records))
+
+        def step():
+            _lib.shv_graph_launch(graph, records, st)
+        mode = "shv_graph_launch: table copy + one graph of all batched phases per step"
+    # The untimed legs run first (they also bring the GPU to its working
+    # clocks); then the warm-up and the timed steps.
+    nprof = args.profile_steps or max(args.steps // 4, 5)
+    prof = profile_window(eager, stream, nprof)
+    extras = {}
+    if not args.no_extras:
+        def sequential():
+            for b in bufs:
+                o, prm = b.out, b.params()
+                wsb = o["ws"].numel()
+                _lib.sh_render_forward(b.points, b.normals, b.albedo, b.spheres, b.light, b.P, b.S, prm, o["vis"],
+                                       o["radiance"], o["saved"], _lib.nbytes(o["saved"]), o["ws"], wsb, st)
+                _lib.sh_render_backward(b.grad_radiance, b.points, b.normals, b.albedo, b.spheres, b.P, b.S, prm,
+                                        o["vis"], o["saved"], _lib.nbytes(o["saved"]), o["grad_points"],
+                                        o["grad_normals"], o["grad_albedo"], o["grad_spheres"], o["grad_light"],
+                                        o["ws"], wsb, st)
+        nseq = max(args.steps // 5, 3)
+        ms_seq = timed(sequential, stream, 2, nseq)
+        ms_eager = timed(eager, stream, 2, max(args.steps // 5, 3))
+        extras["sequential"] = {"ms_per_step": ms_seq, "value": pairs / (ms_seq * 1e-3), "steps": nseq,
+                                "what": "64 x (sh_render_forward + sh_render_backward), eager"}
+        extras["batched_eager"] = {"ms_per_step": ms_eager, "value": pairs / (ms_eager * 1e-3),
+                                   "what": "sh_solve_batched, eager launches"}
+    ms = timed(step, stream, args.warmup, args.steps)
+    copy_calibration(args, dev, stream)
+    kernels = kernel_table(prof)
+    desc = [(b.n_bands, k, b.P, b.S) for b in bufs]
+    roof = roofline(kernels, nprof, lambda name: workmodel.batch_work(name, desc))
+    if roof is not None:
+        roof["traffic"] = measured_traffic("batched64", roof["kernel"])
+    out = {
+        "metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 independent scenes: P ~ U{5000..50000}, S ~ U{32..256}, n ~ U{4,6,8} "
+                               "(seeds 100+b), k=4, eps=3, fwd+bwd with all five gradients, batched",
+                   "scenes": 64, "pairs_per_step": pairs, "receivers": sum(b.P for b in bufs),
+                   "n_squarings": k, "eps": 3.0, "launch": mode},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels), "profiled_steps": nprof,
+    }
+    out.update(extras)
+    if "sequential" in out:
+        out["speedup_vs_sequential"] = out["sequential"]["ms_per_step"] / ms
+    if graph is not None:
+        torch.cuda.synchronize()
+        _lib.shv_graph_destroy(graph)
+    if not args.no_extras:
+        res, budget, mean_pairs = serve_leg(args, 2000.0, 2.5, ["continuous", "one_at_a_time"])
+        out["serve"] = {"rate_rps": 2000.0, "duration_s": 2.5, "warmup_s": 0.5, "memory_budget_gb":
+                        round(budget / 2**30, 1), "mean_pairs_per_request": mean_pairs,
+                        "requests": "90% from the 64-scene distribution, 10% at 262144 x 512 (n 8); Poisson, seed 7",
+                        **{m: {key: r[key] for key in ("throughput_rps", "pairs_per_s", "p50_ms", "p99_ms",
+                                                      "completed", "unfinished", "failed")} for m, r in res.items()}}
+        body = bench_single(args, "body", with_cpu=False)
+        out["body"] = {key: body[key] for key in ("value", "ms_per_step", "roofline", "kernels")}
+        out["body"]["workload"] = body["config"]["workload"]
+    return out
+
+
+def bench_serve(args):
+    """Poisson load against the continuous-batching server (graph steps, and
+    eager steps with ``continuous_eager``) and against one request at a time
+    (single-scene calls), per arrival rate."""
+    import torch
+    torch.cuda.set_device(0)
+    rates = [float(r) for r in args.rates.split(",")]
+    modes = args.modes.split(",")
+    results = {m: [] for m in modes}
+    budget = mean_pairs = None
+    for rate in rates:
+        res, budget, mean_pairs = serve_leg(args, rate, args.duration, modes)
+        for m in modes:
+            results[m].append(res[m])
     best = max((r for r in results.get("continuous", []) if r["p99_ms"] is not None and r["unfinished"] == 0),
                key=lambda r: r["throughput_rps"] or 0, default=None)
     return {
@@ -496,6 +640,7 @@ def bench_rgb(args):
     alb, lig, gB = t(ch["albedo"].T), t(ch["light"]), t(ch["grad_radiance"].T)
     vis = torch.empty(N, P, device=dev)
     saved = torch.empty(_lib.shv_saved_floats(P, prm), device=dev)
+    sb = _lib.nbytes(saved)
     rad = torch.empty(C, P, device=dev)
     gV, gN, gA = torch.empty(N, P, device=dev), torch.empty(3, P, device=dev), torch.empty(C, P, device=dev)
     gL, gP, gS = torch.empty(C, N, device=dev), torch.empty(3, P, device=dev), torch.empty(S, 4, device=dev)
@@ -505,15 +650,14 @@ def bench_rgb(args):
     st = stream.cuda_stream
 
     def step():
-        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, sb, ws, nb, st)
         _lib.sh_shade_channels(vis, nrm, alb, lig, C, P, prm, rad, ws, nb, st)
         _lib.sh_shade_channels_backward(gB, vis, nrm, alb, lig, C, P, prm, gV, gN, gA, gL, ws, nb, st)
-        _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
+        _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, sb, gP, gS, ws, nb, st)
 
-    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    ms, prof, nprof = timed_and_profiled(step, stream, args)
     kernels = kernel_table(prof)
-    roof = roofline(kernels, sampled_steps(args.steps),
-                    lambda name: workmodel.kernel_work(name, n, k, P, S, channels=C))
+    roof = roofline(kernels, nprof, lambda name: workmodel.kernel_work(name, n, k, P, S, channels=C))
     if roof is not None:
         roof["traffic"] = measured_traffic("rgb", roof["kernel"])
     return {
@@ -551,11 +695,10 @@ def bench_envmap(args):
     def step():
         _lib.sh_envmap_project(img, C, H, W, prm, out, ws, nb, st)
 
-    ms, prof = timed(step, stream, args.warmup, args.steps, True)
+    ms, prof, nprof = timed_and_profiled(step, stream, args)
     kernels = kernel_table(prof)
     pixels = C * H * W
-    roof = roofline(kernels, sampled_steps(args.steps),
-                    lambda name: workmodel.kernel_work(name, n, 0, 0, 0, pixels=pixels))
+    roof = roofline(kernels, nprof, lambda name: workmodel.kernel_work(name, n, 0, 0, 0, pixels=pixels))
     cpu = None
     if args.cpu_seconds > 0:
         from oracle import sh
@@ -607,9 +750,9 @@ def bench_inverse(args):
         target = make.rad.clone()
         ip = inverse.InverseProblem(graph, sc["albedo"], sc["light"], target, n, lr=1e-2, n_squarings=k)
     torch.cuda.synchronize()
-    ms, prof = timed(ip.step, stream, args.warmup, args.steps, True)
+    ms, prof, nprof = timed_and_profiled(ip.step, stream, args)
     kernels = kernel_table(prof)
-    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
+    roof = roofline(kernels, nprof, lambda name: workmodel.kernel_work(name, n, k, P, S))
     if roof is not None:
         roof["traffic"] = measured_traffic("inverse", roof["kernel"])
     return {
@@ -663,9 +806,9 @@ def bench_image(args):
         ip = inverse.InverseProblem(graph, sc["albedo"], sc["light"], target, n, lr=IMAGE_LR, n_squarings=k,
                                     faces=sc["faces"], camera=cam)
     torch.cuda.synchronize()
-    ms, prof = timed(ip.step, stream, args.warmup, args.steps, True)
+    ms, prof, nprof = timed_and_profiled(ip.step, stream, args)
     kernels = kernel_table(prof)
-    roof = roofline(kernels, sampled_steps(args.steps), lambda name: workmodel.kernel_work(name, n, k, P, S))
+    roof = roofline(kernels, nprof, lambda name: workmodel.kernel_work(name, n, k, P, S))
     if roof is not None:
         roof["traffic"] = measured_traffic("image", roof["kernel"])
     return {

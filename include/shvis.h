@@ -133,13 +133,17 @@ size_t shv_workspace_bytes(int64_t P, int64_t S, const shv_params* prm);
  *   points  [3][P]  receiver positions x
  *   spheres [S][4]  occluders (cx, cy, cz, r), r >= 0
  *   vis     [N][P]  out: V(x)
- *   saved   [(1 + k N)][P]  out: state for sh_visibility_backward (may be
- *                   NULL when no backward will follow)
+ *   saved   out: state for sh_visibility_backward, shv_saved_floats(P, prm)
+ *           FP32 values ((1 + k N) P for the default exponential); may be
+ *           NULL when no backward will follow (saved_bytes is then ignored)
+ *   saved_bytes  size of the saved buffer in bytes; a non-NULL saved smaller
+ *           than 4 shv_saved_floats(P, prm) bytes is refused with
+ *           SHV_ERR_WORKSPACE before anything is launched
  * A receiver inside a sphere (r >= |c - x|) sees a hemisphere cap; a sphere
  * centred exactly on the receiver contributes nothing. */
 shv_status sh_visibility_forward(const float* points, int64_t P, const float* spheres, int64_t S,
-                                 const shv_params* prm, float* vis, float* saved, void* ws,
-                                 size_t ws_bytes, hipStream_t stream);
+                                 const shv_params* prm, float* vis, float* saved, size_t saved_bytes,
+                                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Diffuse SH shading B = a (L . (V * H)) (Eq. 8), H the clamped cosine
  * rotated to n / |n| (Eqs. 10-11).
@@ -314,36 +318,44 @@ shv_status sh_l2_loss(const float* value, const float* target, int64_t n, float*
 shv_status sh_sgd_step(float* x, const float* grad, int64_t n, float lr, hipStream_t stream);
 
 /* Adjoint of sh_visibility_forward for the cotangent grad_vis [N][P]:
- *   vis, saved  the forward's outputs for the same inputs and parameters
+ *   vis, saved  the forward's outputs for the same inputs and parameters;
+ *   saved_bytes the saved buffer's size in bytes (at least
+ *               4 shv_saved_floats(P, prm), else SHV_ERR_WORKSPACE before any
+ *               launch; saved may be NULL when that is 0)
  *   grad_points [3][P], grad_spheres [S][4] (d/d(cx, cy, cz, r), summed over
  *   receivers); either may be NULL.  Per-pair terms are recomputed, not
  *   stored. */
 shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const float* points,
                                   int64_t P, const float* spheres, int64_t S,
-                                  const shv_params* prm, const float* saved, float* grad_points,
-                                  float* grad_spheres, void* ws, size_t ws_bytes,
+                                  const shv_params* prm, const float* saved, size_t saved_bytes,
+                                  float* grad_points, float* grad_spheres, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
 
 /* Fused render path: the same results as sh_visibility_forward followed by
  * sh_shade (bit-identical), in two launches.  `saved` holds
  * shv_render_saved_floats() values: the visibility state followed by the lit
- * transfer matrix M(L) (N x N); it may be NULL when no backward follows. */
+ * transfer matrix M(L) (N x N); it may be NULL when no backward follows.
+ * saved_bytes is its size in bytes: a non-NULL saved smaller than
+ * 4 shv_render_saved_floats(P, prm) bytes is refused with SHV_ERR_WORKSPACE
+ * before anything is launched. */
 int64_t shv_render_saved_floats(int64_t P, const shv_params* prm);
 shv_status sh_render_forward(const float* points, const float* normals, const float* albedo,
                              const float* spheres, const float* light, int64_t P, int64_t S,
                              const shv_params* prm, float* vis, float* radiance, float* saved,
-                             void* ws, size_t ws_bytes, hipStream_t stream);
+                             size_t saved_bytes, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Fused adjoint of sh_render_forward for the cotangent grad_radiance [P]: the
  * same results as sh_shade_backward followed by sh_visibility_backward
  * (bit-identical), in three launches.  vis and saved come from
- * sh_render_forward with the same inputs; every gradient output may be NULL. */
+ * sh_render_forward with the same inputs (saved_bytes at least
+ * 4 shv_render_saved_floats(P, prm), else SHV_ERR_WORKSPACE before any
+ * launch); every gradient output may be NULL. */
 shv_status sh_render_backward(const float* grad_radiance, const float* points, const float* normals,
                               const float* albedo, const float* spheres, int64_t P, int64_t S,
                               const shv_params* prm, const float* vis, const float* saved,
-                              float* grad_points, float* grad_normals, float* grad_albedo,
-                              float* grad_spheres, float* grad_light, void* ws, size_t ws_bytes,
-                              hipStream_t stream);
+                              size_t saved_bytes, float* grad_points, float* grad_normals,
+                              float* grad_albedo, float* grad_spheres, float* grad_light, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
 
 /* Batched render path: many independent scenes (each with its own P, S,
  * n_bands and k) forward and backward in one launch per phase and group of
@@ -352,7 +364,8 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
  *
  * Scene description (host structure; every pointer is a device pointer as in
  * the single-scene calls).  ws must hold shv_workspace_bytes(P, S, &params)
- * bytes and saved shv_render_saved_floats(P, &params) floats; grad_* may be
+ * bytes and saved shv_render_saved_floats(P, &params) floats (saved_bytes
+ * says how many bytes it has; a smaller buffer is refused); grad_* may be
  * NULL; grad_radiance is read by the backward only, which skips a scene whose
  * grad_radiance is NULL (its gradient outputs are left unwritten). */
 typedef struct shv_scene {
@@ -365,6 +378,7 @@ typedef struct shv_scene {
   float* vis;                 /* [N][P] out */
   float* radiance;            /* [P] out */
   float* saved;               /* shv_render_saved_floats() out / in */
+  size_t saved_bytes;         /* size of saved in bytes (checked by shv_batch_table_build) */
   float* grad_points;         /* [3][P] out or NULL */
   float* grad_normals;        /* [3][P] out or NULL */
   float* grad_albedo;         /* [P] out or NULL */
@@ -429,11 +443,54 @@ shv_status sh_render_batched_forward(const void* table_device, const shv_batch_g
  * scene's grad_radiance, vis and saved. */
 shv_status sh_render_batched_backward(const void* table_device, const shv_batch_grid* grid, hipStream_t stream);
 
+/* Forward and backward of every scene of the batch in one call: exactly the
+ * launches of sh_render_batched_forward followed by those of
+ * sh_render_batched_backward (every scene's grad_radiance is read), so the
+ * results are bit-identical to those two calls and to single-scene
+ * sh_render_forward / sh_render_backward. */
+shv_status sh_solve_batched(const void* table_device, const shv_batch_grid* grid, hipStream_t stream);
+
+/* ---- sh_solve_batched replayed from a HIP graph (a whole batched
+ * forward + backward in one graph launch, for serving loops that issue many
+ * small steps) ----
+ * shv_graph_create captures sh_solve_batched into a HIP graph once, over a
+ * device copy of the work table that the graph object owns (room for
+ * max_scenes scenes).  groups selects the launch groups the graph holds:
+ * every entry of groups that is > 0 (pair[n], exp[layout][n], finalize) puts
+ * that group's launch into the graph, captured with that block count.  Each
+ * shv_graph_launch then
+ *   - packs the table of `scenes` on the host (the checks of
+ *     shv_batch_table_build, errors name the scene) into one of four pinned
+ *     staging slots (waiting, if need be, until that slot's previous copy
+ *     has run),
+ *   - refuses, with SHV_ERR_UNSUPPORTED before anything is enqueued, a batch
+ *     that needs a group the graph does not hold (or, with
+ *     SHV_GRAPH_FIXED_GRID, more blocks in a group than captured),
+ *   - sets every graph launch to the exact block count the table needs (1
+ *     block, which exits at once, for a group with no work this time), unless
+ *     SHV_GRAPH_FIXED_GRID keeps the captured counts (blocks past a group's
+ *     work exit at once),
+ *   - enqueues on `stream`: a wait for the graph's previous launch (so
+ *     launches on different streams are ordered), the copy of the table into
+ *     the graph's device buffer, and the graph.
+ * Results are bit-identical to sh_solve_batched on the same table.  The
+ * graph object is not thread-safe: one thread launches it at a time.
+ * shv_graph_create and shv_graph_destroy allocate and free (device table,
+ * pinned staging, the graph); shv_graph_launch allocates nothing.
+ * shv_graph_destroy waits for the graph's last launch to finish. */
+#define SHV_GRAPH_FIXED_GRID 1u
+typedef struct shv_graph shv_graph;
+shv_status shv_graph_create(const shv_batch_grid* groups, int32_t max_scenes, uint32_t flags, shv_graph** graph);
+shv_status shv_graph_launch(shv_graph* graph, const shv_scene* scenes, int32_t n_scenes, hipStream_t stream);
+shv_status shv_graph_destroy(shv_graph* graph);
+
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream.  shv_profile_enable(1) starts a new collection (at most
  * `capacity` launches are recorded; later ones are counted but not timed);
  * shv_profile_enable(0) pauses recording and shv_profile_enable(2) resumes
- * it, adding to the current collection (to time a sample of the launches).  shv_profile_report() must be called
+ * it, adding to the current collection (to time a sample of the launches;
+ * resuming never creates events, so it adds nothing to a timed region).
+ * shv_profile_report() must be called
  * after the stream has drained: it writes "name count total_ms\n" lines into
  * buf (NUL-terminated, truncated to len) and returns the number of bytes
  * needed. */

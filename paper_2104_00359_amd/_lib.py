@@ -12,7 +12,10 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libshvis.so")
+# SHV_LIBRARY selects another build of the same library (the host-sanitized
+# one of build_sanitized.py, for CPU tests); by default the in-tree product
+# build is loaded.
+LIB_PATH = os.environ.get("SHV_LIBRARY") or os.path.join(HERE, "libshvis.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -38,7 +41,8 @@ EXPORTED = [
     "shv_l2_workspace_bytes", "sh_l2_loss", "sh_sgd_step",
     "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
     "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
-    "sh_render_batched_forward", "sh_render_batched_backward",
+    "sh_render_batched_forward", "sh_render_batched_backward", "sh_solve_batched",
+    "shv_graph_create", "shv_graph_launch", "shv_graph_destroy",
     "shv_profile_enable", "shv_profile_report",
 ]
 
@@ -52,6 +56,7 @@ SHV_FLAG_EXP_QUADRATURE = 4
 SHV_FLAG_EXP_PRODUCT = 8
 SHV_FLAG_EXP_TAYLOR = 16
 SHV_MAX_TAYLOR_ORDER = 8
+SHV_GRAPH_FIXED_GRID = 1
 
 
 def SHV_FLAG_EXP_TAYLOR_ORDER(K):
@@ -67,7 +72,8 @@ class shv_params(ctypes.Structure):
 class shv_scene(ctypes.Structure):
     """One scene of a batched render (field order and types as in the C struct)."""
     _fields_ = [(name, ctypes.c_void_p) for name in (
-        "points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved",
+        "points", "normals", "albedo", "spheres", "light", "grad_radiance", "vis", "radiance", "saved")] + [
+        ("saved_bytes", ctypes.c_size_t)] + [(name, ctypes.c_void_p) for name in (
         "grad_points", "grad_normals", "grad_albedo", "grad_spheres", "grad_light", "ws")] + [
         ("ws_bytes", ctypes.c_size_t), ("P", ctypes.c_int64), ("S", ctypes.c_int64), ("params", shv_params),
         ("range_begin", ctypes.c_int64), ("range_end", ctypes.c_int64), ("defer_reductions", ctypes.c_int32)]
@@ -111,10 +117,10 @@ _sig = {
     "shv_last_error": (ctypes.c_char_p, []),
     "shv_saved_floats": (_I64, [_I64, _PRM]),
     "shv_workspace_bytes": (_SZ, [_I64, _I64, _PRM]),
-    "sh_visibility_forward": (ctypes.c_int32, [_P, _I64, _P, _I64, _PRM, _P, _P, _P, _SZ, _P]),
+    "sh_visibility_forward": (ctypes.c_int32, [_P, _I64, _P, _I64, _PRM, _P, _P, _SZ, _P, _SZ, _P]),
     "sh_shade": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _PRM, _P, _P, _SZ, _P]),
     "sh_shade_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _PRM, _P, _P, _P, _P, _P, _SZ, _P]),
-    "sh_visibility_backward": (ctypes.c_int32, [_P, _P, _P, _I64, _P, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
+    "sh_visibility_backward": (ctypes.c_int32, [_P, _P, _P, _I64, _P, _I64, _PRM, _P, _SZ, _P, _P, _P, _SZ, _P]),
     "shv_channels_workspace_bytes": (_SZ, [_I64, ctypes.c_int, _PRM]),
     "sh_shade_channels": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int, _I64, _PRM, _P, _P, _SZ, _P]),
     "sh_shade_channels_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int, _I64, _PRM, _P, _P, _P, _P,
@@ -134,14 +140,19 @@ _sig = {
     "sh_l2_loss": (ctypes.c_int32, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "sh_sgd_step": (ctypes.c_int32, [_P, _P, _I64, ctypes.c_float, _P]),
     "shv_render_saved_floats": (_I64, [_I64, _PRM]),
-    "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _SZ, _P]),
-    "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _P, _P, _P, _P, _P,
-                                            _SZ, _P]),
+    "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _SZ, _P, _SZ, _P]),
+    "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _SZ, _P, _P, _P, _P, _P,
+                                            _P, _SZ, _P]),
     "shv_batch_table_bytes": (_SZ, [ctypes.c_int32]),
     "shv_batch_table_build": (ctypes.c_int32, [ctypes.POINTER(shv_scene), ctypes.c_int32, _P, _SZ]),
     "shv_batch_table_grid": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid)]),
     "sh_render_batched_forward": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid), _P]),
     "sh_render_batched_backward": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid), _P]),
+    "sh_solve_batched": (ctypes.c_int32, [_P, ctypes.POINTER(shv_batch_grid), _P]),
+    "shv_graph_create": (ctypes.c_int32, [ctypes.POINTER(shv_batch_grid), ctypes.c_int32, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "shv_graph_launch": (ctypes.c_int32, [_P, ctypes.POINTER(shv_scene), ctypes.c_int32, _P]),
+    "shv_graph_destroy": (ctypes.c_int32, [_P]),
     "shv_profile_enable": (ctypes.c_int32, [ctypes.c_int, ctypes.c_int32]),
     "shv_profile_report": (_I64, [ctypes.c_char_p, _I64]),
 }
@@ -196,9 +207,17 @@ def raw(name: str):
     return getattr(_lib, name)
 
 
-def sh_visibility_forward(points, P, spheres, S, prm, vis, saved, ws, ws_bytes, stream):
+def nbytes(t) -> int:
+    """Size in bytes of a buffer argument (0 for None)."""
+    if t is None:
+        return 0
+    return int(t.numel()) * int(t.element_size())
+
+
+def sh_visibility_forward(points, P, spheres, S, prm, vis, saved, saved_bytes, ws, ws_bytes, stream):
     _check(_lib.sh_visibility_forward(ptr(points), int(P), ptr(spheres), int(S), ctypes.byref(prm), ptr(vis),
-                                      ptr(saved), ptr(ws), int(ws_bytes), stream), "sh_visibility_forward")
+                                      ptr(saved), int(saved_bytes), ptr(ws), int(ws_bytes), stream),
+           "sh_visibility_forward")
 
 
 def sh_shade(vis, normals, albedo, light, P, prm, radiance, ws, ws_bytes, stream):
@@ -302,30 +321,30 @@ def sh_sgd_step(x, grad, n, lr, stream):
     _check(_lib.sh_sgd_step(ptr(x), ptr(grad), int(n), float(lr), stream), "sh_sgd_step")
 
 
-def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, grad_points, grad_spheres, ws,
-                           ws_bytes, stream):
+def sh_visibility_backward(grad_vis, vis, points, P, spheres, S, prm, saved, saved_bytes, grad_points, grad_spheres,
+                           ws, ws_bytes, stream):
     _check(_lib.sh_visibility_backward(ptr(grad_vis), ptr(vis), ptr(points), int(P), ptr(spheres), int(S),
-                                       ctypes.byref(prm), ptr(saved), ptr(grad_points), ptr(grad_spheres),
-                                       ptr(ws), int(ws_bytes), stream), "sh_visibility_backward")
+                                       ctypes.byref(prm), ptr(saved), int(saved_bytes), ptr(grad_points),
+                                       ptr(grad_spheres), ptr(ws), int(ws_bytes), stream), "sh_visibility_backward")
 
 
 def shv_render_saved_floats(P: int, prm: shv_params) -> int:
     return int(_lib.shv_render_saved_floats(int(P), ctypes.byref(prm)))
 
 
-def sh_render_forward(points, normals, albedo, spheres, light, P, S, prm, vis, radiance, saved, ws, ws_bytes,
-                      stream):
+def sh_render_forward(points, normals, albedo, spheres, light, P, S, prm, vis, radiance, saved, saved_bytes, ws,
+                      ws_bytes, stream):
     _check(_lib.sh_render_forward(ptr(points), ptr(normals), ptr(albedo), ptr(spheres), ptr(light), int(P), int(S),
-                                  ctypes.byref(prm), ptr(vis), ptr(radiance), ptr(saved), ptr(ws), int(ws_bytes),
-                                  stream), "sh_render_forward")
+                                  ctypes.byref(prm), ptr(vis), ptr(radiance), ptr(saved), int(saved_bytes), ptr(ws),
+                                  int(ws_bytes), stream), "sh_render_forward")
 
 
-def sh_render_backward(grad_radiance, points, normals, albedo, spheres, P, S, prm, vis, saved, grad_points,
-                       grad_normals, grad_albedo, grad_spheres, grad_light, ws, ws_bytes, stream):
+def sh_render_backward(grad_radiance, points, normals, albedo, spheres, P, S, prm, vis, saved, saved_bytes,
+                       grad_points, grad_normals, grad_albedo, grad_spheres, grad_light, ws, ws_bytes, stream):
     _check(_lib.sh_render_backward(ptr(grad_radiance), ptr(points), ptr(normals), ptr(albedo), ptr(spheres), int(P),
-                                   int(S), ctypes.byref(prm), ptr(vis), ptr(saved), ptr(grad_points),
-                                   ptr(grad_normals), ptr(grad_albedo), ptr(grad_spheres), ptr(grad_light), ptr(ws),
-                                   int(ws_bytes), stream), "sh_render_backward")
+                                   int(S), ctypes.byref(prm), ptr(vis), ptr(saved), int(saved_bytes),
+                                   ptr(grad_points), ptr(grad_normals), ptr(grad_albedo), ptr(grad_spheres),
+                                   ptr(grad_light), ptr(ws), int(ws_bytes), stream), "sh_render_backward")
 
 
 def shv_batch_table_bytes(n_scenes: int) -> int:
@@ -362,10 +381,40 @@ def sh_render_batched_backward(table_device, grid, stream):
            "sh_render_batched_backward")
 
 
+def sh_solve_batched(table_device, grid, stream):
+    _check(_lib.sh_solve_batched(ptr(table_device), ctypes.byref(grid), stream), "sh_solve_batched")
+
+
+def shv_graph_create(groups, max_scenes: int, flags: int = 0) -> int:
+    """Handle (an opaque address) of a new graph of sh_solve_batched."""
+    h = ctypes.c_void_p()
+    _check(_lib.shv_graph_create(ctypes.byref(groups), int(max_scenes), int(flags), ctypes.byref(h)),
+           "shv_graph_create")
+    return h.value
+
+
+def shv_graph_launch(graph: int, scenes, stream, unsupported_ok: bool = False) -> bool:
+    """scenes: a sequence of shv_scene (host records).  With ``unsupported_ok``
+    a batch the graph does not hold (SHV_ERR_UNSUPPORTED: nothing was
+    enqueued) returns False instead of raising."""
+    n = len(scenes)
+    arr = (shv_scene * max(n, 1))(*scenes)
+    st = _lib.shv_graph_launch(graph, arr, n, stream)
+    if unsupported_ok and st == SHV_ERR_UNSUPPORTED:
+        return False
+    _check(st, "shv_graph_launch")
+    return True
+
+
+def shv_graph_destroy(graph: int) -> None:
+    _check(_lib.shv_graph_destroy(graph), "shv_graph_destroy")
+
+
 def shv_profile_enable(enable: bool, capacity: int = 4096, resume: bool = False) -> None:
-    """Start (or with ``resume`` continue) recording per-launch events; False pauses."""
+    """Start (or with ``resume`` continue, without growing the event pool)
+    recording per-launch events; False pauses."""
     mode = (2 if resume else 1) if enable else 0
-    _check(_lib.shv_profile_enable(mode, int(capacity)), "shv_profile_enable")
+    _check(_lib.shv_profile_enable(mode, 0 if resume else int(capacity)), "shv_profile_enable")
 
 
 def shv_profile_report() -> dict:

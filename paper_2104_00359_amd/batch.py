@@ -109,6 +109,7 @@ class SceneBuffers:
         r.spheres, r.light = _lib.ptr(self.spheres), _lib.ptr(self.light)
         r.grad_radiance = _lib.ptr(self.grad_radiance)
         r.vis, r.radiance, r.saved = _lib.ptr(o["vis"]), _lib.ptr(o["radiance"]), _lib.ptr(o["saved"])
+        r.saved_bytes = _lib.nbytes(o["saved"])
         r.grad_points, r.grad_normals = _lib.ptr(o["grad_points"]), _lib.ptr(o["grad_normals"])
         r.grad_albedo, r.grad_spheres = _lib.ptr(o["grad_albedo"]), _lib.ptr(o["grad_spheres"])
         r.grad_light = _lib.ptr(o["grad_light"])

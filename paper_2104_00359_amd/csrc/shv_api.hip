@@ -57,10 +57,15 @@ std::vector<ProfRec> g_prof;      // event pool
 int64_t g_prof_used = 0;          // records filled
 std::map<std::string, int64_t> g_prof_untimed;
 
+// Set while a graph is being captured on this thread: event records would
+// become graph nodes, so launches are not timed then.
+thread_local bool g_capturing = false;
+
 struct ProfScope {
   ProfRec* rec = nullptr;
   hipStream_t st;
   ProfScope(const char* name, hipStream_t s) : st(s) {
+    if (g_capturing) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     if (g_prof_used < (int64_t)g_prof.size()) {
@@ -329,6 +334,22 @@ shv_status check_ws(void* ws, size_t ws_bytes, size_t needed) {
   return SHV_OK;
 }
 
+// The forward's saved state: `floats` FP32 values in a buffer of `bytes`
+// bytes.  A NULL buffer is accepted where the state is optional (a forward
+// with no backward to follow) or empty.
+shv_status check_saved(const void* saved, size_t bytes, int64_t floats, bool required) {
+  if (!saved) {
+    if (required && floats > 0) return set_error(SHV_ERR_INVALID_ARG, "saved is NULL (need %lld floats)",
+                                                 (long long)floats);
+    return SHV_OK;
+  }
+  if (((uintptr_t)saved) & 3u) return set_error(SHV_ERR_INVALID_ARG, "saved must be 4-byte aligned");
+  if (bytes / 4 < (size_t)floats)
+    return set_error(SHV_ERR_WORKSPACE, "saved has %zu bytes, needs %lld (%lld floats)", bytes,
+                     (long long)floats * 4, (long long)floats);
+  return SHV_OK;
+}
+
 shv_status check_camera(const shv_camera* cam, shv::RasterCam& rc) {
   if (!cam) return set_error(SHV_ERR_INVALID_ARG, "camera is NULL");
   if (cam->width < 1 || cam->height < 1 || cam->width > SHV_MAX_IMAGE_SIDE || cam->height > SHV_MAX_IMAGE_SIDE)
@@ -420,12 +441,12 @@ int64_t shv_render_saved_floats(int64_t P, const shv_params* prm) {
 
 shv_status sh_render_forward(const float* points, const float* normals, const float* albedo, const float* spheres,
                              const float* light, int64_t P, int64_t S, const shv_params* prm, float* vis,
-                             float* radiance, float* saved, void* ws, size_t ws_bytes, hipStream_t stream) {
+                             float* radiance, float* saved, size_t saved_bytes, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
   SHV_TRY(check_params(prm));
   SHV_TRY(no_quadrature(prm));
   SHV_TRY(check_sizes(P, S));
-  SHV_TRY(check_device());
-  if (P == 0) return SHV_OK;
+  if (P == 0) return check_device();
   SHV_TRY(need(points, "points"));
   SHV_TRY(need(normals, "normals"));
   SHV_TRY(need(albedo, "albedo"));
@@ -437,7 +458,9 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
     SHV_TRY(aligned16(spheres, "spheres"));
   }
   const int nb = prm->n_bands;
+  SHV_TRY(check_saved(saved, saved_bytes, shv_render_saved_floats(P, prm), false));
   SHV_TRY(check_ws(ws, ws_bytes, render_fwd_bytes(P, S, nb)));
+  SHV_TRY(check_device());
   float* Fpart = (float*)ws;
   const int64_t N = (int64_t)nb * nb;
   float* M = saved ? saved + (1 + (int64_t)prm->n_squarings * N) * P : (float*)((char*)ws + fwd_bytes(P, S, nb));
@@ -454,16 +477,16 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
 
 shv_status sh_render_backward(const float* grad_radiance, const float* points, const float* normals,
                               const float* albedo, const float* spheres, int64_t P, int64_t S, const shv_params* prm,
-                              const float* vis, const float* saved, float* grad_points, float* grad_normals,
-                              float* grad_albedo, float* grad_spheres, float* grad_light, void* ws, size_t ws_bytes,
-                              hipStream_t stream) {
+                              const float* vis, const float* saved, size_t saved_bytes, float* grad_points,
+                              float* grad_normals, float* grad_albedo, float* grad_spheres, float* grad_light,
+                              void* ws, size_t ws_bytes, hipStream_t stream) {
   SHV_TRY(check_params(prm));
   SHV_TRY(no_quadrature(prm));
   SHV_TRY(check_sizes(P, S));
-  SHV_TRY(check_device());
   const int nb = prm->n_bands;
   const int N = nb * nb;
   if (P == 0) {
+    SHV_TRY(check_device());
     if (grad_light)
       SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_light, N, stream); }));
     if (grad_spheres && S > 0)
@@ -480,8 +503,10 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
     SHV_TRY(need(spheres, "spheres"));
     SHV_TRY(aligned16(spheres, "spheres"));
   }
+  SHV_TRY(check_saved(saved, saved_bytes, shv_render_saved_floats(P, prm), true));
   RenderBwdWs L;
   SHV_TRY(check_ws(ws, ws_bytes, render_bwd_bytes(P, S, nb, &L)));
+  SHV_TRY(check_device());
   float* W = (float*)((char*)ws + L.W);
   float* gp = (float*)((char*)ws + L.gp);
   float* gs = (float*)((char*)ws + L.gs);
@@ -509,12 +534,11 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
 }
 
 shv_status sh_visibility_forward(const float* points, int64_t P, const float* spheres, int64_t S,
-                                 const shv_params* prm, float* vis, float* saved, void* ws, size_t ws_bytes,
-                                 hipStream_t stream) {
+                                 const shv_params* prm, float* vis, float* saved, size_t saved_bytes, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
   SHV_TRY(check_params(prm));
   SHV_TRY(check_sizes(P, S));
-  SHV_TRY(check_device());
-  if (P == 0) return SHV_OK;
+  if (P == 0) return check_device();
   SHV_TRY(need(points, "points"));
   SHV_TRY(need(vis, "vis"));
   if (S > 0) {
@@ -522,8 +546,10 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
     SHV_TRY(aligned16(spheres, "spheres"));
   }
   const int nb = prm->n_bands;
+  SHV_TRY(check_saved(saved, saved_bytes, shv_saved_floats(P, prm), false));
   if (product(prm)) {
     SHV_TRY(check_product_size(P, S, nb));
+    SHV_TRY(check_device());
     SHV_TRY(launch("prod_fwd", stream, [&] {
       return shv::launch_prod_fwd(nb, points, P, spheres, (int)S, prm->eps, vis, nullptr, stream);
     }));
@@ -531,6 +557,7 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
   }
   const size_t base = fwd_bytes(P, S, nb);
   SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
+  SHV_TRY(check_device());
   float* Fpart = (float*)ws;
   const shv::Split sp = shv::choose_split(P, S);
   SHV_TRY(launch("pair_fwd", stream, [&] {
@@ -879,12 +906,12 @@ shv_status sh_sgd_step(float* x, const float* grad, int64_t n, float lr, hipStre
 
 shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const float* points, int64_t P,
                                   const float* spheres, int64_t S, const shv_params* prm, const float* saved,
-                                  float* grad_points, float* grad_spheres, void* ws, size_t ws_bytes,
-                                  hipStream_t stream) {
+                                  size_t saved_bytes, float* grad_points, float* grad_spheres, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
   SHV_TRY(check_params(prm));
   SHV_TRY(check_sizes(P, S));
-  SHV_TRY(check_device());
   if (P == 0 || (!grad_points && !grad_spheres)) {
+    SHV_TRY(check_device());
     if (grad_spheres && S > 0)
       SHV_TRY(launch("fill_zero", stream, [&] { return shv::launch_fill_zero(grad_spheres, 4 * S, stream); }));
     return SHV_OK;
@@ -892,7 +919,7 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   SHV_TRY(need(grad_vis, "grad_vis"));
   SHV_TRY(need(vis, "vis"));
   SHV_TRY(need(points, "points"));
-  if (!product(prm)) SHV_TRY(need(saved, "saved"));
+  SHV_TRY(check_saved(saved, saved_bytes, shv_saved_floats(P, prm), true));
   if (S > 0) {
     SHV_TRY(need(spheres, "spheres"));
     SHV_TRY(aligned16(spheres, "spheres"));
@@ -903,6 +930,7 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
     SHV_TRY(check_product_size(P, S, nb));
     ProdWs L;
     SHV_TRY(check_ws(ws, ws_bytes, prod_bytes(P, S, nb, &L)));
+    SHV_TRY(check_device());
     float* states = (float*)((char*)ws + L.states);
     float* gs = (float*)((char*)ws + L.gs);
     if (S > 0) {
@@ -924,6 +952,7 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   VisBwdWs L;
   const size_t base = visbwd_bytes(P, S, nb, &L);
   SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
+  SHV_TRY(check_device());
   float* W = (float*)((char*)ws + L.W);
   float* gp = (float*)((char*)ws + L.gp);
   float* gs = (float*)((char*)ws + L.gs);
@@ -995,6 +1024,7 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
       if (what) st = set_error(SHV_ERR_INVALID_ARG, "%s is NULL", what);
       else if (in.S > 0 && (((uintptr_t)in.spheres) & 15u)) st = set_error(SHV_ERR_INVALID_ARG, "spheres misaligned");
     }
+    if (st == SHV_OK && in.P > 0) st = check_saved(in.saved, in.saved_bytes, shv_render_saved_floats(in.P, prm), true);
     if (st == SHV_OK) st = check_ws(in.ws, in.ws_bytes, in.P > 0 ? shv_workspace_bytes(in.P, in.S, prm) : 0);
     if (st == SHV_OK && !(in.range_begin == 0 && in.range_end == 0)) {
       const int64_t a = in.range_begin, e = in.range_end;
@@ -1116,21 +1146,36 @@ static shv_status check_grid(const shv_batch_grid* g) {
   return SHV_OK;
 }
 
+// Timing name of a batched launch: phase, band count and (exponential
+// phases) the one-wave layout, e.g. "batch_pair_bwd/n8",
+// "batch_exp_shade_fwd/n4/one".
+static const char* batch_name(int phase, int nb, int lay) {
+  static const std::vector<std::string> table = [] {
+    static const char* base[4] = {"batch_pair_fwd", "batch_exp_shade_fwd", "batch_exp_shade_bwd", "batch_pair_bwd"};
+    std::vector<std::string> t;
+    for (int p = 0; p < 4; ++p)
+      for (int n = 0; n <= SHV_MAX_BANDS_API; ++n)
+        for (int l = 0; l < 2; ++l)
+          t.push_back(std::string(base[p]) + "/n" + std::to_string(n) + ((p == 1 || p == 2) && l == 0 ? "/one" : ""));
+    return t;
+  }();
+  return table[((size_t)phase * (SHV_MAX_BANDS_API + 1) + nb) * 2 + lay].c_str();
+}
+
 // Launches of one phase for every group with a non-empty grid.
 static shv_status batched_phase(int phase, const shv_batch_grid* g, const void* table, hipStream_t stream) {
-  static const char* names[4] = {"batch_pair_fwd", "batch_exp_shade_fwd", "batch_exp_shade_bwd", "batch_pair_bwd"};
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
     if (phase == 0 || phase == 3) {
       const int64_t blocks = g->pair[nb];
       if (blocks > 0)
-        SHV_TRY(launch(names[phase], stream,
+        SHV_TRY(launch(batch_name(phase, nb, 1), stream,
                        [&] { return shv::launch_batch_nb(nb, phase, false, table, blocks, stream); }));
       continue;
     }
     for (int lay = 1; lay >= 0; --lay) {
       const int64_t blocks = g->exp[lay][nb];
       if (blocks > 0)
-        SHV_TRY(launch(names[phase], stream,
+        SHV_TRY(launch(batch_name(phase, nb, lay), stream,
                        [&] { return shv::launch_batch_nb(nb, phase, lay == 1, table, blocks, stream); }));
     }
   }
@@ -1158,6 +1203,263 @@ shv_status sh_render_batched_backward(const void* table, const shv_batch_grid* g
   return SHV_OK;
 }
 
+shv_status sh_solve_batched(const void* table, const shv_batch_grid* grid, hipStream_t stream) {
+  SHV_TRY(need(table, "table"));
+  SHV_TRY(check_grid(grid));
+  SHV_TRY(check_device());
+  for (int phase = 0; phase < 4; ++phase) SHV_TRY(batched_phase(phase, grid, table, stream));
+  if (grid->finalize > 0)
+    SHV_TRY(launch("batch_finalize", stream,
+                   [&] { return shv::launch_batch_finalize(table, grid->finalize, stream); }));
+  return SHV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ graphs
+
+struct shv_graph {
+  static constexpr int kSlots = 4;
+  int device = -1;
+  int32_t max_scenes = 0;
+  uint32_t flags = 0;
+  size_t table_bytes = 0;
+  void* table_dev = nullptr;            // device copy of the table the graph reads
+  void* staging[kSlots] = {};           // pinned host tables
+  hipEvent_t staged[kSlots] = {};       // recorded after each slot's copy
+  bool slot_pending[kSlots] = {};
+  int next_slot = 0;
+  hipEvent_t done = nullptr;            // recorded after the last launch
+  bool launched = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  shv_batch_grid captured{};            // block counts the graph was captured with
+  // one entry per launch, in launch order: its group and its node
+  struct Node {
+    int kind;   // 0..3 batched phase, 4 finalize
+    int nb;
+    int lay;
+    hipGraphNode_t node;
+    hipKernelNodeParams params;
+  };
+  std::vector<Node> nodes;
+  const void* arg_table = nullptr;      // storage of the kernels' one argument
+  void* args[1] = {nullptr};
+};
+
+namespace {
+
+int64_t grid_entry(const shv_batch_grid& g, int kind, int nb, int lay) {
+  if (kind == 4) return g.finalize;
+  if (kind == 0 || kind == 3) return g.pair[nb];
+  return g.exp[lay][nb];
+}
+
+void graph_free(shv_graph* g) {
+  if (!g) return;
+  if (g->done) (void)hipEventSynchronize(g->done);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (int i = 0; i < shv_graph::kSlots; ++i) {
+    if (g->staged[i]) (void)hipEventDestroy(g->staged[i]);
+    if (g->staging[i]) (void)hipHostFree(g->staging[i]);
+  }
+  if (g->done) (void)hipEventDestroy(g->done);
+  if (g->table_dev) (void)hipFree(g->table_dev);
+  delete g;
+}
+
+#define SHV_HIP(call, what)                                                                    \
+  do {                                                                                         \
+    hipError_t _e = (call);                                                                    \
+    if (_e != hipSuccess) return set_error(SHV_ERR_HIP, "%s: %s", what, hipGetErrorString(_e)); \
+  } while (0)
+
+// Captures the launches of sh_solve_batched for the groups of g->captured,
+// in the order sh_solve_batched issues them, and pairs each launch with its
+// node by walking the captured chain from its root.
+shv_status graph_capture(shv_graph* g) {
+  hipStream_t cs = nullptr;
+  SHV_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  std::vector<shv_graph::Node> order;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  shv_status st = SHV_OK;
+  if (e == hipSuccess) {
+    g_capturing = true;
+    const shv_batch_grid& cap = g->captured;
+    for (int phase = 0; phase < 4 && st == SHV_OK; ++phase) {
+      for (int nb = 1; nb <= SHV_MAX_BANDS_API && st == SHV_OK; ++nb) {
+        if (phase == 0 || phase == 3) {
+          if (cap.pair[nb] > 0) {
+            st = launch("graph", cs, [&] { return shv::launch_batch_nb(nb, phase, false, g->table_dev, cap.pair[nb], cs); });
+            order.push_back({phase, nb, 0, nullptr, {}});
+          }
+          continue;
+        }
+        for (int lay = 1; lay >= 0 && st == SHV_OK; --lay) {
+          if (cap.exp[lay][nb] > 0) {
+            st = launch("graph", cs,
+                        [&] { return shv::launch_batch_nb(nb, phase, lay == 1, g->table_dev, cap.exp[lay][nb], cs); });
+            order.push_back({phase, nb, lay, nullptr, {}});
+          }
+        }
+      }
+    }
+    if (st == SHV_OK && cap.finalize > 0) {
+      st = launch("graph", cs, [&] { return shv::launch_batch_finalize(g->table_dev, cap.finalize, cs); });
+      order.push_back({4, 0, 0, nullptr, {}});
+    }
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (st == SHV_OK && e2 != hipSuccess)
+      st = set_error(SHV_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+  } else {
+    st = set_error(SHV_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(cs);
+  SHV_TRY(st);
+  if (!g->graph) return set_error(SHV_ERR_HIP, "capture produced no graph");
+  // walk the chain: one root, each node with at most one dependent
+  hipGraphNode_t cur = nullptr;
+  size_t nroot = 1;
+  SHV_HIP(hipGraphGetRootNodes(g->graph, &cur, &nroot), "hipGraphGetRootNodes");
+  if (nroot != 1) return set_error(SHV_ERR_HIP, "captured graph has %zu roots, expected 1", nroot);
+  for (size_t i = 0; i < order.size(); ++i) {
+    if (!cur) return set_error(SHV_ERR_HIP, "captured graph has %zu nodes, expected %zu", i, order.size());
+    hipGraphNodeType ty;
+    SHV_HIP(hipGraphNodeGetType(cur, &ty), "hipGraphNodeGetType");
+    if (ty != hipGraphNodeTypeKernel) return set_error(SHV_ERR_HIP, "captured node %zu is not a kernel", i);
+    order[i].node = cur;
+    SHV_HIP(hipGraphKernelNodeGetParams(cur, &order[i].params), "hipGraphKernelNodeGetParams");
+    size_t ndep = 0;
+    SHV_HIP(hipGraphNodeGetDependentNodes(cur, nullptr, &ndep), "hipGraphNodeGetDependentNodes");
+    if (ndep > 1) return set_error(SHV_ERR_HIP, "captured node %zu has %zu dependents", i, ndep);
+    hipGraphNode_t nxt = nullptr;
+    if (ndep == 1) {
+      size_t one = 1;
+      SHV_HIP(hipGraphNodeGetDependentNodes(cur, &nxt, &one), "hipGraphNodeGetDependentNodes");
+    }
+    cur = nxt;
+  }
+  if (cur) return set_error(SHV_ERR_HIP, "captured graph has more nodes than launches");
+  g->arg_table = g->table_dev;
+  g->args[0] = &g->arg_table;
+  for (auto& n : order) {
+    n.params.kernelParams = g->args;
+    n.params.extra = nullptr;
+  }
+  g->nodes = std::move(order);
+  SHV_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  return SHV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shv_status shv_graph_create(const shv_batch_grid* groups, int32_t max_scenes, uint32_t flags, shv_graph** out) {
+  SHV_TRY(need(out, "graph"));
+  *out = nullptr;
+  SHV_TRY(check_grid(groups));
+  if (max_scenes < 1 || max_scenes > (1 << 20))
+    return set_error(SHV_ERR_INVALID_ARG, "max_scenes=%d outside [1, 2^20]", max_scenes);
+  if (flags & ~SHV_GRAPH_FIXED_GRID) return set_error(SHV_ERR_INVALID_ARG, "unknown graph flags 0x%x", flags);
+  bool any = groups->finalize > 0;
+  for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb)
+    any = any || groups->pair[nb] > 0 || groups->exp[0][nb] > 0 || groups->exp[1][nb] > 0;
+  if (!any) return set_error(SHV_ERR_INVALID_ARG, "groups selects no launch");
+  SHV_TRY(check_device());
+  shv_graph* g = new shv_graph();
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  g->device = dev;
+  g->max_scenes = max_scenes;
+  g->flags = flags;
+  g->captured = *groups;
+  g->table_bytes = shv::batch_table_bytes(max_scenes);
+  if (e == hipSuccess) e = hipMalloc(&g->table_dev, g->table_bytes);
+  for (int i = 0; i < shv_graph::kSlots && e == hipSuccess; ++i) {
+    e = hipHostMalloc(&g->staging[i], g->table_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->staged[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    // an empty table until the first launch writes one
+    shv::BatchHeader h{};
+    e = hipMemcpy(g->table_dev, &h, sizeof(h), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    const shv_status st = set_error(SHV_ERR_HIP, "shv_graph_create: %s", hipGetErrorString(e));
+    graph_free(g);
+    return st;
+  }
+  const shv_status st = graph_capture(g);
+  if (st != SHV_OK) {
+    const std::string msg = g_last_error;
+    graph_free(g);
+    return set_error(st, "shv_graph_create: %s", msg.c_str());
+  }
+  *out = g;
+  return SHV_OK;
+}
+
+shv_status shv_graph_launch(shv_graph* g, const shv_scene* scenes, int32_t n_scenes, hipStream_t stream) {
+  SHV_TRY(need(g, "graph"));
+  if (n_scenes < 0 || n_scenes > g->max_scenes)
+    return set_error(SHV_ERR_INVALID_ARG, "n_scenes=%d outside [0, %d]", n_scenes, g->max_scenes);
+  int dev = -1;
+  SHV_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != g->device) return set_error(SHV_ERR_INVALID_ARG, "graph belongs to device %d, current is %d", g->device, dev);
+  const int slot = g->next_slot;
+  if (g->slot_pending[slot]) SHV_HIP(hipEventSynchronize(g->staged[slot]), "hipEventSynchronize");
+  g->slot_pending[slot] = false;
+  SHV_TRY(shv_batch_table_build(scenes, n_scenes, g->staging[slot], g->table_bytes));
+  shv_batch_grid need_grid;
+  SHV_TRY(shv_batch_table_grid(g->staging[slot], &need_grid));
+  const bool fixed = (g->flags & SHV_GRAPH_FIXED_GRID) != 0;
+  // every group with work must be in the graph (and fit it with fixed grids)
+  for (int nb = 0; nb <= SHV_MAX_BANDS_API; ++nb) {
+    for (int kind = 0; kind < 3; ++kind) {
+      const int64_t want = kind == 0 ? need_grid.pair[nb] : need_grid.exp[kind - 1][nb];
+      const int64_t have = kind == 0 ? g->captured.pair[nb] : g->captured.exp[kind - 1][nb];
+      if (want > 0 && (have <= 0 || (fixed && want > have)))
+        return set_error(SHV_ERR_UNSUPPORTED, "batch needs %lld blocks in the %s group of %d bands; the graph holds %lld",
+                         (long long)want, kind == 0 ? "pair" : (kind == 1 ? "one-wave exponential" : "four-wave exponential"),
+                         nb, (long long)have);
+    }
+  }
+  if (need_grid.finalize > 0 && (g->captured.finalize <= 0 || (fixed && need_grid.finalize > g->captured.finalize)))
+    return set_error(SHV_ERR_UNSUPPORTED, "batch needs %lld finalize blocks; the graph holds %lld",
+                     (long long)need_grid.finalize, (long long)g->captured.finalize);
+  if (!fixed) {
+    for (auto& n : g->nodes) {
+      const int64_t want = grid_entry(need_grid, n.kind, n.nb, n.lay);
+      const unsigned blocks = (unsigned)std::max<int64_t>(want, 1);
+      if (n.params.gridDim.x != blocks) {
+        n.params.gridDim = dim3(blocks, 1, 1);
+        SHV_HIP(hipGraphExecKernelNodeSetParams(g->exec, n.node, &n.params), "hipGraphExecKernelNodeSetParams");
+      }
+    }
+  }
+  if (g->launched) SHV_HIP(hipStreamWaitEvent(stream, g->done, 0), "hipStreamWaitEvent");
+  const size_t bytes = shv::batch_table_bytes(n_scenes);
+  SHV_HIP(hipMemcpyAsync(g->table_dev, g->staging[slot], bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync");
+  SHV_HIP(hipEventRecord(g->staged[slot], stream), "hipEventRecord");
+  g->slot_pending[slot] = true;
+  g->next_slot = (slot + 1) % shv_graph::kSlots;
+  SHV_TRY(launch("graph_solve", stream, [&] { return hipGraphLaunch(g->exec, stream); }));
+  SHV_HIP(hipEventRecord(g->done, stream), "hipEventRecord");
+  g->launched = true;
+  return SHV_OK;
+}
+
+shv_status shv_graph_destroy(shv_graph* g) {
+  graph_free(g);
+  return SHV_OK;
+}
+
 shv_status shv_profile_enable(int enable, int32_t capacity) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!enable) {
@@ -1165,7 +1467,9 @@ shv_status shv_profile_enable(int enable, int32_t capacity) {
     return SHV_OK;
   }
   if (capacity < 0) return set_error(SHV_ERR_INVALID_ARG, "negative capacity");
-  while ((int64_t)g_prof.size() < capacity) {
+  // Resuming (2) never grows the pool: creating events inside a timed region
+  // would be timed with it.
+  while (enable != 2 && (int64_t)g_prof.size() < capacity) {
     ProfRec r{nullptr, nullptr, nullptr};
     hipError_t e1 = hipEventCreate(&r.a);
     hipError_t e2 = hipEventCreate(&r.b);

@@ -151,7 +151,7 @@ class InverseProblem:
         g, st, P, S = self.graph, _stream(), self.P, self.S
         _lib.sh_deform_forward(g.c, self.params, self.pts, self.nrm, self.sph, g.ws, g.ws.numel(), st)
         _lib.sh_render_forward(self.pts, self.nrm, self.albedo, self.sph, self.light, P, S, self.prm, self.vis,
-                               self.rad, self.saved, self.ws_r, self.ws_r.numel(), st)
+                               self.rad, self.saved, _lib.nbytes(self.saved), self.ws_r, self.ws_r.numel(), st)
         r = self.raster
         if r is None:
             _lib.sh_l2_loss(self.rad, self.target, P, self.gB, self.loss, self.ws_l, self.ws_l.numel(), st)
@@ -163,7 +163,8 @@ class InverseProblem:
             _lib.sh_raster_backward(r["gI"], self.pts, P, r["faces"], r["T"], self.rad, r["cam"], r["face_id"],
                                     r["inc_ptr"], r["inc_idx"], self.gB, r["gPr"], r["ws"], r["ws"].numel(), st)
         _lib.sh_render_backward(self.gB, self.pts, self.nrm, self.albedo, self.sph, P, S, self.prm, self.vis,
-                                self.saved, self.gP, self.gN, None, self.gS, None, self.ws_r, self.ws_r.numel(), st)
+                                self.saved, _lib.nbytes(self.saved), self.gP, self.gN, None, self.gS, None, self.ws_r,
+                                self.ws_r.numel(), st)
         if r is not None:
             # the vertices' positions reach the loss through the shading and
             # through the rasteriser: gP <- gP - (-1) gPr

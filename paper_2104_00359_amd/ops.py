@@ -28,15 +28,48 @@ def ensure_init(device: torch.device) -> None:
 
 
 def workspace(device: torch.device, nbytes: int) -> torch.Tensor:
-    """A per-device, grow-only scratch buffer (reused across calls on the
-    same stream order)."""
-    key = (device.type, device.index)
+    """A grow-only scratch buffer per (device, current stream).  Calls on one
+    stream run in stream order, so they can share it; calls on different
+    streams get different buffers.  The buffer is allocated on the stream
+    that uses it, so when it grows the caching allocator reuses the old block
+    only after the work already queued on that stream."""
+    stream = torch.cuda.current_stream(device)
+    key = (device.type, device.index, stream.cuda_stream)
     with _ws_lock:
         buf = _ws_cache.get(key)
         if buf is None or buf.numel() < nbytes:
-            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            with torch.cuda.stream(stream):
+                buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
             _ws_cache[key] = buf
         return buf
+
+
+def _shape_error(op: str, name: str, t, want) -> ValueError:
+    got = tuple(t.shape) if isinstance(t, torch.Tensor) else type(t).__name__
+    return ValueError(f"{op}: {name} must be {want}, got {got}")
+
+
+def check_inputs(op: str, specs) -> None:
+    """Argument checks before anything reaches the library, which sees bare
+    pointers and cannot check them: every input is a floating-point tensor of
+    the stated shape (``specs``: (name, tensor, shape) with ints or None for
+    any size), and all live on one HIP device."""
+    dev = None
+    for name, t, shape in specs:
+        if not isinstance(t, torch.Tensor):
+            raise _shape_error(op, name, t, "a tensor")
+        if not t.is_floating_point():
+            raise ValueError(f"{op}: {name} must be a floating-point tensor, got {t.dtype}")
+        if t.dim() != len(shape) or any(w is not None and g != w for g, w in zip(t.shape, shape)):
+            raise _shape_error(op, name, t, "[" + ", ".join("*" if w is None else str(w) for w in shape) + "]")
+    for name, t, _ in specs:
+        if t.device.type != "cuda":
+            raise RuntimeError(f"{op} runs on the GPU only; {name} is on {t.device} (move the inputs to a HIP "
+                               "device)")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise RuntimeError(f"{op}: {name} is on {t.device}, the other inputs on {dev}")
 
 
 def _stream() -> int:
@@ -58,21 +91,22 @@ class ShadeSH(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings):
+        P = points.shape[0] if isinstance(points, torch.Tensor) and points.dim() == 2 else None
+        S = spheres.shape[0] if isinstance(spheres, torch.Tensor) and spheres.dim() == 2 else None
+        N = int(n_bands) * int(n_bands)
+        check_inputs("shade_sh", [("points", points, (P, 3)), ("normals", normals, (P, 3)),
+                                  ("albedo", albedo, (P,)), ("spheres", spheres, (S, 4)), ("light", light, (N,))])
         dev = points.device
-        if dev.type != "cuda":
-            raise RuntimeError("shade_sh runs on the GPU only; move the inputs to a HIP device")
         ensure_init(dev)
         prm = _lib.params(n_bands, eps, n_squarings)
-        P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
         pts, nrm = _soa(points), _soa(normals)
         alb, sph, L = _f32(albedo), _f32(spheres), _f32(light)
-        if L.numel() != N:
-            raise ValueError(f"light has {L.numel()} coefficients, expected {N} for {n_bands} bands")
         vis = torch.empty(N, P, dtype=torch.float32, device=dev)
-        saved = torch.empty(_lib.shv_render_saved_floats(P, prm), dtype=torch.float32, device=dev)
+        saved = torch.empty(max(_lib.shv_render_saved_floats(P, prm), 1), dtype=torch.float32, device=dev)
         rad = torch.empty(P, dtype=torch.float32, device=dev)
         ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
-        _lib.sh_render_forward(pts, nrm, alb, sph, L, P, S, prm, vis, rad, saved, ws, ws.numel(), _stream())
+        _lib.sh_render_forward(pts, nrm, alb, sph, L, P, S, prm, vis, rad, saved, _lib.nbytes(saved), ws, ws.numel(),
+                               _stream())
         ctx.save_for_backward(pts, nrm, alb, sph, vis, saved)
         ctx.cfg = (n_bands, eps, n_squarings)
         return rad
@@ -92,8 +126,8 @@ class ShadeSH(torch.autograd.Function):
         gS = torch.empty(S, 4, dtype=torch.float32, device=dev) if need_s else None
         gL = torch.empty(N, dtype=torch.float32, device=dev) if need_l else None
         ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
-        _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, gP, gN, gA, gS, gL, ws, ws.numel(),
-                                _stream())
+        _lib.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, _lib.nbytes(saved), gP, gN, gA, gS, gL,
+                                ws, ws.numel(), _stream())
         return (gP.t() if gP is not None else None, gN.t() if gN is not None else None, gA, gS, gL,
                 None, None, None)
 
@@ -131,9 +165,8 @@ class VisibilitySH(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, points, spheres, n_bands, eps, n_squarings, flags):
+        check_inputs("visibility_sh", [("points", points, (None, 3)), ("spheres", spheres, (None, 4))])
         dev = points.device
-        if dev.type != "cuda":
-            raise RuntimeError("visibility_sh runs on the GPU only; move the inputs to a HIP device")
         ensure_init(dev)
         prm = _lib.params(n_bands, eps, n_squarings, flags)
         P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
@@ -141,7 +174,7 @@ class VisibilitySH(torch.autograd.Function):
         vis = torch.empty(N, P, dtype=torch.float32, device=dev)
         saved = torch.empty(max(_lib.shv_saved_floats(P, prm), 1), dtype=torch.float32, device=dev)
         ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
-        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), _stream())
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, _lib.nbytes(saved), ws, ws.numel(), _stream())
         ctx.save_for_backward(pts, sph, vis, saved)
         ctx.cfg = (n_bands, eps, n_squarings, flags)
         return vis.t()
@@ -158,7 +191,8 @@ class VisibilitySH(torch.autograd.Function):
         gP = torch.empty(3, P, dtype=torch.float32, device=dev) if need_p else None
         gS = torch.empty(max(S, 1), 4, dtype=torch.float32, device=dev) if need_s else None
         ws = workspace(dev, _lib.shv_workspace_bytes(P, S, prm))
-        _lib.sh_visibility_backward(_soa(grad_vis), vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), _stream())
+        _lib.sh_visibility_backward(_soa(grad_vis), vis, pts, P, sph, S, prm, saved, _lib.nbytes(saved), gP, gS, ws,
+                                    ws.numel(), _stream())
         return (gP.t() if gP is not None else None, gS[:S] if gS is not None else None, None, None, None, None)
 
 
@@ -176,24 +210,23 @@ class ShadeSHChannels(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, points, normals, albedo, spheres, light, n_bands, eps, n_squarings, flags=0):
+        P = points.shape[0] if isinstance(points, torch.Tensor) and points.dim() == 2 else None
+        S = spheres.shape[0] if isinstance(spheres, torch.Tensor) and spheres.dim() == 2 else None
+        C = light.shape[0] if isinstance(light, torch.Tensor) and light.dim() == 2 else None
+        N = int(n_bands) * int(n_bands)
+        check_inputs("shade_sh_channels", [("points", points, (P, 3)), ("normals", normals, (P, 3)),
+                                           ("albedo", albedo, (P, C)), ("spheres", spheres, (S, 4)),
+                                           ("light", light, (C, N))])
         dev = points.device
-        if dev.type != "cuda":
-            raise RuntimeError("shade_sh_channels runs on the GPU only; move the inputs to a HIP device")
         ensure_init(dev)
         prm = _lib.params(n_bands, eps, n_squarings, flags)
-        P, S, N = points.shape[0], spheres.shape[0], n_bands * n_bands
-        if light.dim() != 2 or light.shape[1] != N:
-            raise ValueError(f"light must be [channels, {N}] for {n_bands} bands, got {tuple(light.shape)}")
-        C = light.shape[0]
-        if albedo.shape != (P, C):
-            raise ValueError(f"albedo must be [{P}, {C}], got {tuple(albedo.shape)}")
         pts, nrm = _soa(points), _soa(normals)
         alb, sph, L = _soa(albedo), _f32(spheres), _f32(light)
         vis = torch.empty(N, P, dtype=torch.float32, device=dev)
         saved = torch.empty(max(_lib.shv_saved_floats(P, prm), 1), dtype=torch.float32, device=dev)
         rad = torch.empty(C, P, dtype=torch.float32, device=dev)
         ws = workspace(dev, max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm)))
-        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, ws.numel(), _stream())
+        _lib.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, _lib.nbytes(saved), ws, ws.numel(), _stream())
         _lib.sh_shade_channels(vis, nrm, alb, L, C, P, prm, rad, ws, ws.numel(), _stream())
         ctx.save_for_backward(pts, nrm, alb, sph, L, vis, saved)
         ctx.cfg = (n_bands, eps, n_squarings, flags)
@@ -218,7 +251,8 @@ class ShadeSHChannels(torch.autograd.Function):
         ws = workspace(dev, max(_lib.shv_workspace_bytes(P, S, prm), _lib.shv_channels_workspace_bytes(P, C, prm)))
         _lib.sh_shade_channels_backward(gB, vis, nrm, alb, L, C, P, prm, gV, gN, gA, gL, ws, ws.numel(), _stream())
         if need_v:
-            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, ws.numel(), _stream())
+            _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, _lib.nbytes(saved), gP, gS, ws, ws.numel(),
+                                        _stream())
         return (gP.t() if gP is not None else None, gN.t() if gN is not None else None,
                 gA.t() if gA is not None else None, gS, gL, None, None, None, None)
 
@@ -239,14 +273,13 @@ def envmap_to_sh(image, n_bands: int):
     ``image`` [H, W] or [C, H, W] (row r covers polar angles [r, r+1] pi/H from
     +z, column x azimuths [x, x+1] 2 pi/W from +x towards +y) -> [N] or
     [C, N] with N = n_bands^2.  Forward only."""
+    if not isinstance(image, torch.Tensor) or image.dim() not in (2, 3):
+        raise _shape_error("envmap_to_sh", "image", image, "[H, W] or [C, H, W]")
+    check_inputs("envmap_to_sh", [("image", image, (None,) * image.dim())])
     dev = image.device
-    if dev.type != "cuda":
-        raise RuntimeError("envmap_to_sh runs on the GPU only; move the image to a HIP device")
     ensure_init(dev)
     mono = image.dim() == 2
     img = _f32(image[None] if mono else image)
-    if img.dim() != 3:
-        raise ValueError(f"image must be [H, W] or [C, H, W], got {tuple(image.shape)}")
     C, H, W = img.shape
     prm = _lib.params(n_bands)
     out = torch.empty(C, n_bands * n_bands, dtype=torch.float32, device=dev)

@@ -88,78 +88,95 @@ class Executor:
         pass
 
 
-def _round_up_pow2(x: int) -> int:
-    return 0 if x <= 0 else 1 << (int(x) - 1).bit_length()
+class StepGraph:
+    """The batched forward + backward of a serving step replayed from one HIP
+    graph of the library (shv_graph_create), captured once when the executor
+    starts, never on the serving path.
 
+    The graph holds the pair and four-wave exponential launches of the band
+    counts in ``bands`` and the closing reductions; each launch sets every
+    node to the exact block count its step needs, so one graph serves steps
+    of any size.  A step the graph does not hold (another band count, the
+    one-wave layout, more than ``max_scenes`` ranges) is launched eagerly
+    instead and counted in ``eager_steps``."""
 
-class StepGraphs:
-    """Captured graphs of the batched forward + backward, one per launch shape.
-
-    The graph is launched with per-group block counts that only grow (the
-    power of two at or above the largest count seen so far), so a new graph
-    is captured only when some group outgrows its capacity; each graph has a
-    device table buffer of its own, into which a step uploads its table (on
-    the same stream, so after the previous replay) before replaying.  Blocks
-    beyond a group's work exit at once, so one graph serves every table that
-    fits its grid."""
-
-    def __init__(self, device, stream, max_records: int = 1024):
-        import torch
-        self.torch = torch
+    def __init__(self, device, bands=(4, 6, 8), max_scenes: int = 1024):
         self.device = device
-        self.stream = stream
-        self.max_records = max_records
-        self.capacity = _lib.shv_batch_table_bytes(max_records)
-        self.cache = {}
-        self.captures = 0
-        self.cap = [0] * 28   # pair[9], exp[0][9], exp[1][9], finalize
+        self.max_scenes = int(max_scenes)
+        groups = _lib.shv_batch_grid()
+        for n in bands:
+            groups.pair[int(n)] = 1
+            groups.exp[1][int(n)] = 1
+        groups.finalize = 1
+        self.handle = _lib.shv_graph_create(groups, self.max_scenes)
+        self.graph_steps = 0
+        self.eager_steps = 0
 
-    def _key(self, grid):
-        cur = list(grid.pair) + list(grid.exp[0]) + list(grid.exp[1]) + [grid.finalize]
-        self.cap = [max(c, _round_up_pow2(x)) for c, x in zip(self.cap, cur)]
-        return tuple(self.cap)
-
-    def run(self, table_host, grid, n_records: int) -> bool:
-        """Enqueue one step; False when the table is larger than the graphs'
-        table buffers (the caller then launches eagerly)."""
-        torch = self.torch
-        if n_records > self.max_records:
+    def run(self, records, stream_handle) -> bool:
+        """Enqueue one step; False when the graph does not hold it (nothing
+        was enqueued, the caller launches it eagerly)."""
+        if len(records) > self.max_scenes:
+            self.eager_steps += 1
             return False
-        key = self._key(grid)
-        ent = self.cache.get(key)
-        if ent is None:
-            buf = torch.zeros(self.capacity, dtype=torch.uint8, device=self.device)
-            cap = _lib.shv_batch_grid()
-            for i in range(9):
-                cap.pair[i] = key[i]
-                cap.exp[0][i] = key[9 + i]
-                cap.exp[1][i] = key[18 + i]
-            cap.finalize = key[27]
-            g = torch.cuda.CUDAGraph()
-            torch.cuda.synchronize(self.device)
-            with torch.cuda.graph(g, stream=self.stream, capture_error_mode="thread_local"):
-                h = self.stream.cuda_stream
-                _lib.sh_render_batched_forward(buf, cap, h)
-                _lib.sh_render_batched_backward(buf, cap, h)
-            ent = (g, buf)
-            self.cache[key] = ent
-            self.captures += 1
-        g, buf = ent
-        n = table_host.numel()
-        with torch.cuda.stream(self.stream):
-            buf[:n].copy_(table_host, non_blocking=True)
-            g.replay()
-        return True
+        ok = _lib.shv_graph_launch(self.handle, records, stream_handle, unsupported_ok=True)
+        if ok:
+            self.graph_steps += 1
+        else:
+            self.eager_steps += 1
+        return ok
+
+    def close(self):
+        if self.handle:
+            _lib.shv_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+class _Markers:
+    """roctx ranges around serving steps (visible in rocprofv3 --marker-trace)
+    when the ROCm tracer library is present; otherwise nothing is recorded."""
+
+    def __init__(self):
+        import ctypes
+        import os
+        self.lib = None
+        for path in ("/opt/rocm/lib/libroctx64.so", "libroctx64.so"):
+            if path.startswith("/") and not os.path.exists(path):
+                continue
+            try:
+                lib = ctypes.CDLL(path)
+                lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                lib.roctxRangePushA.restype = ctypes.c_int
+                lib.roctxRangePop.restype = ctypes.c_int
+                self.lib = lib
+                break
+            except OSError:
+                continue
+
+    def push(self, text: str):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(text.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
 
 
 class GpuExecutor(Executor):
     """Steps as batched library calls on one stream (default priority).
-    With ``graphs`` each step replays a captured graph of the batched calls
-    (StepGraphs).  With ``single_scene`` a step holding one whole request goes
-    through the single-scene entry points instead (the one-request-at-a-time
-    baseline)."""
+    With ``graphs`` (the default) each step replays the library's HIP graph of
+    the batched forward + backward (StepGraph, captured at construction for
+    the band counts in ``bands``).  With ``single_scene`` a step holding one
+    whole request goes through the single-scene entry points instead (the
+    one-request-at-a-time baseline)."""
 
-    def __init__(self, device, stream=None, single_scene: bool = False, graphs: bool = False):
+    def __init__(self, device, stream=None, single_scene: bool = False, graphs: bool = True, bands=(4, 6, 8),
+                 max_scenes: int = 1024):
         import torch
 
         from .ops import ensure_init
@@ -168,7 +185,8 @@ class GpuExecutor(Executor):
         ensure_init(self.device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.single_scene = single_scene
-        self.graphs = StepGraphs(self.device, self.stream) if graphs else None
+        self.graph = StepGraph(self.device, bands, max_scenes) if graphs and not single_scene else None
+        self.markers = _Markers()
 
     def footprint(self, req):
         return req.scene.device_bytes()
@@ -180,37 +198,40 @@ class GpuExecutor(Executor):
         from .batch import Table
         torch = self.torch
         st = self.stream
-        if self.single_scene and len(items) == 1 and items[0][1] == 0 and items[0][2] == items[0][0].P:
-            b = items[0][0].scene
-            o, prm = b.out, b.params()
-            h = st.cuda_stream
-            _lib.sh_render_forward(b.points, b.normals, b.albedo, b.spheres, b.light, b.P, b.S, prm, o["vis"],
-                                   o["radiance"], o["saved"], o["ws"], o["ws"].numel(), h)
-            _lib.sh_render_backward(b.grad_radiance, b.points, b.normals, b.albedo, b.spheres, b.P, b.S, prm,
-                                    o["vis"], o["saved"], o["grad_points"], o["grad_normals"], o["grad_albedo"],
-                                    o["grad_spheres"], o["grad_light"], o["ws"], o["ws"].numel(), h)
-            tab = None
-        else:
-            recs = [req.scene.record(a, e, defer) for req, a, e, defer in items]
-            if self.graphs is not None:
-                host = torch.empty(_lib.shv_batch_table_bytes(len(recs)), dtype=torch.uint8, pin_memory=True)
-                _lib.shv_batch_table_build(recs, host)
-                grid = _lib.shv_batch_table_grid(host)
-                tab = host   # keeps the pinned source alive until the step completes
-                if not self.graphs.run(host, grid, len(recs)):
-                    tab = Table(recs, self.device, st)
-                    tab.forward(st)
-                    tab.backward(st)
+        h = st.cuda_stream
+        pairs = sum((e - a) * req.S for req, a, e, _ in items)
+        self.markers.push(f"shv_step ranges={len(items)} pairs={pairs}")
+        try:
+            if self.single_scene and len(items) == 1 and items[0][1] == 0 and items[0][2] == items[0][0].P:
+                b = items[0][0].scene
+                o, prm = b.out, b.params()
+                _lib.sh_render_forward(b.points, b.normals, b.albedo, b.spheres, b.light, b.P, b.S, prm, o["vis"],
+                                       o["radiance"], o["saved"], _lib.nbytes(o["saved"]), o["ws"], o["ws"].numel(),
+                                       h)
+                _lib.sh_render_backward(b.grad_radiance, b.points, b.normals, b.albedo, b.spheres, b.P, b.S, prm,
+                                        o["vis"], o["saved"], _lib.nbytes(o["saved"]), o["grad_points"],
+                                        o["grad_normals"], o["grad_albedo"], o["grad_spheres"], o["grad_light"],
+                                        o["ws"], o["ws"].numel(), h)
+                tab = None
             else:
-                tab = Table(recs, self.device, st)
-                tab.forward(st)
-                tab.backward(st)
-        ev = torch.cuda.Event()
-        ev.record(st)
+                recs = [req.scene.record(a, e, defer) for req, a, e, defer in items]
+                tab = None
+                if self.graph is None or not self.graph.run(recs, h):
+                    tab = Table(recs, self.device, st)
+                    _lib.sh_solve_batched(tab.device, tab.grid, tab._handle(st))
+            ev = torch.cuda.Event()
+            ev.record(st)
+        finally:
+            self.markers.pop()
         return ev, tab
 
     def done(self, token):
         return token[0].query()
+
+    def close(self):
+        if self.graph is not None:
+            self.torch.cuda.synchronize(self.device)
+            self.graph.close()
 
 
 class Scheduler:

@@ -236,12 +236,18 @@ BATCH_KERNELS = {"batch_pair_fwd": "pair_fwd", "batch_pair_bwd": "pair_bwd", "ba
 
 def batch_work(name: str, scenes):
     """(flops, unit count) of all launches of batched kernel ``name`` in one
-    batched call over ``scenes`` (tuples (n, k, P, S))."""
-    single = BATCH_KERNELS.get(name)
+    batched call over ``scenes`` (tuples (n, k, P, S)).  A name carrying a
+    band count ("batch_pair_bwd/n8", "batch_exp_shade_fwd/n4/one") counts the
+    scenes with that many bands only."""
+    parts = name.split("/")
+    single = BATCH_KERNELS.get(parts[0])
     if single is None:
         return None, None
+    only = int(parts[1][1:]) if len(parts) > 1 and parts[1].startswith("n") else None
     flops = units = 0
     for n, k, P, S in scenes:
+        if only is not None and n != only:
+            continue
         f, u = kernel_work(single, n, k, P, S)
         flops += f
         units += u

@@ -42,7 +42,7 @@ def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True, flags=0):
     nb = L.shv_workspace_bytes(P, S, prm)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     st = torch.cuda.current_stream().cuda_stream
-    L.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+    L.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, L.nbytes(saved), ws, nb, st)
     L.sh_shade(vis, nrm, alb, lig, P, prm, rad, ws, nb, st)
     out = {"V": vis.t().cpu().numpy(), "B": rad.cpu().numpy()}
     if grad_B is not None:
@@ -54,7 +54,7 @@ def run_hip(scene, grad_B=None, eps=3.0, k=4, want_grads=True, flags=0):
         gP = torch.empty(3, P, device=dev)
         gS = torch.empty(max(S, 1), 4, device=dev)
         L.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, gN, gA, gL, ws, nb, st)
-        L.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, gP, gS, ws, nb, st)
+        L.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, L.nbytes(saved), gP, gS, ws, nb, st)
         out.update(grad_points=gP.t().cpu().numpy(), grad_normals=gN.t().cpu().numpy(),
                    grad_albedo=gA.cpu().numpy(), grad_light=gL.cpu().numpy(),
                    grad_spheres=gS[:S].cpu().numpy())
@@ -85,14 +85,15 @@ def run_render(scene, grad_B, eps=3.0, k=4, flags=0, null=()):
     nb = L.shv_workspace_bytes(P, S, prm)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     st = torch.cuda.current_stream().cuda_stream
-    L.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, ws, nb, st)
+    L.sh_render_forward(pts, nrm, alb, sph, lig, P, S, prm, vis, rad, saved, L.nbytes(saved), ws, nb, st)
     out = {"V": vis.t().cpu().numpy(), "B": rad.cpu().numpy()}
     gB = to_dev(np.asarray(grad_B, np.float32))
     g = {"grad_points": torch.empty(3, P, device=dev), "grad_normals": torch.empty(3, P, device=dev),
          "grad_albedo": torch.empty(P, device=dev), "grad_spheres": torch.empty(max(S, 1), 4, device=dev),
          "grad_light": torch.empty(N, device=dev)}
     a = {k2: (None if k2 in null else v) for k2, v in g.items()}
-    L.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, a["grad_points"], a["grad_normals"],
+    L.sh_render_backward(gB, pts, nrm, alb, sph, P, S, prm, vis, saved, L.nbytes(saved), a["grad_points"],
+                         a["grad_normals"],
                          a["grad_albedo"], a["grad_spheres"], a["grad_light"], ws, nb, st)
     torch.cuda.synchronize()
     if "grad_points" not in null:

@@ -38,7 +38,7 @@ def _vis(L, sc, prm, dev, st):
     vis = torch.empty(n * n, P, device=dev)
     nb = L.shv_workspace_bytes(P, S, prm)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
-    L.sh_visibility_forward(to_dev(sc["points"].T), P, to_dev(sc["spheres"]), S, prm, vis, None, ws, nb, st)
+    L.sh_visibility_forward(to_dev(sc["points"].T), P, to_dev(sc["spheres"]), S, prm, vis, None, 0, ws, nb, st)
     return vis
 
 

@@ -110,9 +110,9 @@ def test_zero_receivers_is_noop_and_zeroes_reductions():
     gL = torch.full((16,), 7.0, device=dev)
     gS = torch.full((3, 4), 7.0, device=dev)
     sph = torch.ones(3, 4, device=dev)
-    L.sh_visibility_forward(None, 0, sph, 3, prm, None, None, None, 0, st)
+    L.sh_visibility_forward(None, 0, sph, 3, prm, None, None, 0, None, 0, st)
     L.sh_shade_backward(None, None, None, None, None, 0, prm, None, None, None, gL, None, 0, st)
-    L.sh_visibility_backward(None, None, None, 0, sph, 3, prm, None, None, gS, None, 0, st)
+    L.sh_visibility_backward(None, None, None, 0, sph, 3, prm, None, 0, None, gS, None, 0, st)
     torch.cuda.synchronize()
     assert torch.all(gL == 0) and torch.all(gS == 0)
 
@@ -134,12 +134,12 @@ def test_optional_outputs_may_be_null():
     nb = L.shv_workspace_bytes(P, S, prm)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     st = torch.cuda.current_stream().cuda_stream
-    L.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, ws, nb, st)
+    L.sh_visibility_forward(pts, P, sph, S, prm, vis, saved, L.nbytes(saved), ws, nb, st)
     gV = torch.empty(16, P, device=dev)
     gL = torch.empty(16, device=dev)
     L.sh_shade_backward(gB, vis, nrm, alb, lig, P, prm, gV, None, None, gL, ws, nb, st)
     gS = torch.empty(S, 4, device=dev)
-    L.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, None, gS, ws, nb, st)
+    L.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, L.nbytes(saved), None, gS, ws, nb, st)
     torch.cuda.synchronize()
     assert np.array_equal(gL.cpu().numpy(), full["grad_light"])
     assert np.array_equal(gS.cpu().numpy(), full["grad_spheres"])
@@ -157,19 +157,19 @@ def test_invalid_arguments_return_status_codes():
     vis = torch.zeros(16, 10, device=dev)
     ws = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
     good = L.params(4)
-    assert f(pts.data_ptr(), 10, sph.data_ptr(), 2, ctypes.byref(L.params(9)), vis.data_ptr(), None,
+    assert f(pts.data_ptr(), 10, sph.data_ptr(), 2, ctypes.byref(L.params(9)), vis.data_ptr(), None, 0,
              ws.data_ptr(), ws.numel(), st) == L.SHV_ERR_UNSUPPORTED
-    assert f(pts.data_ptr(), -1, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None,
+    assert f(pts.data_ptr(), -1, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None, 0,
              ws.data_ptr(), ws.numel(), st) == L.SHV_ERR_INVALID_ARG
-    assert f(None, 10, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None,
+    assert f(None, 10, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None, 0,
              ws.data_ptr(), ws.numel(), st) == L.SHV_ERR_INVALID_ARG
-    assert f(pts.data_ptr(), 10, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None,
+    assert f(pts.data_ptr(), 10, sph.data_ptr(), 2, ctypes.byref(good), vis.data_ptr(), None, 0,
              ws.data_ptr(), 16, st) == L.SHV_ERR_WORKSPACE
-    assert f(pts.data_ptr(), 10, sph.data_ptr() + 4, 2, ctypes.byref(good), vis.data_ptr(), None,
+    assert f(pts.data_ptr(), 10, sph.data_ptr() + 4, 2, ctypes.byref(good), vis.data_ptr(), None, 0,
              ws.data_ptr(), ws.numel(), st) == L.SHV_ERR_INVALID_ARG
     assert "aligned" in L.shv_last_error()
     with pytest.raises(RuntimeError):
-        L.sh_visibility_forward(pts, 10, sph, 2, L.params(0), vis, None, ws, ws.numel(), st)
+        L.sh_visibility_forward(pts, 10, sph, 2, L.params(0), vis, None, 0, ws, ws.numel(), st)
 
 
 def test_autograd_function_matches_c_abi():

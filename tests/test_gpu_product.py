@@ -122,7 +122,7 @@ def test_product_flag_is_rejected_by_the_fused_and_batched_paths():
     ops.ensure_init(torch.device("cuda", 0))
     prm = L.params(4, 3.0, 4, PROD)
     f = L.raw("sh_render_forward")
-    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, None, 0, None) == \
+    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, 0, None, 0, None) == \
         L.SHV_ERR_UNSUPPORTED
     assert L.shv_saved_floats(100, prm) == 0
     assert L.shv_workspace_bytes(100, 7, prm) >= 7 * 16 * 100 * 4

@@ -85,7 +85,7 @@ def test_quadrature_flag_is_rejected_by_the_fused_and_batched_paths():
     import ctypes
     prm = L.params(4, 3.0, 4, QUAD)
     f = L.raw("sh_render_forward")
-    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, None, 0, None) == \
+    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, 0, None, 0, None) == \
         L.SHV_ERR_UNSUPPORTED
     assert L.shv_saved_floats(100, prm) == max((1 + 4 * 16) * 100, 16 * 100)
     assert L.shv_saved_floats(100, L.params(4, 3.0, 0, QUAD)) == 16 * 100

@@ -24,7 +24,7 @@ def test_served_in_mix_equals_alone_bitwise(graphs):
              (95, 256, 7, 3)]
     pool = [scenegen.scene_random_shell(s, P, S, n) for s, P, S, n in specs]
     inputs = [batch.scene_buffers(sc, dev) for sc in pool]
-    ex = serve.GpuExecutor(dev, graphs=graphs)
+    ex = serve.GpuExecutor(dev, graphs=graphs, bands=(3, 4, 5, 6, 8))
     sched = serve.Scheduler(ex, memory_budget=16 << 30, chunk_pairs=300_000, step_pairs=1_500_000, max_inflight=2,
                             record_steps=True)
     rng = np.random.default_rng(5)
@@ -41,7 +41,11 @@ def test_served_in_mix_equals_alone_bitwise(graphs):
     reqs = [f.result(timeout=120) for f in futs]
     sched.stop(timeout=30)
     print(f"{sched.steps} steps; widest step {max(len(s) for s in sched.step_log)} ranges"
-          + (f"; {ex.graphs.captures} graphs captured" if graphs else ""), flush=True)
+          + (f"; {ex.graph.graph_steps} from the graph, {ex.graph.eager_steps} eager" if graphs else ""),
+          flush=True)
+    if graphs:
+        assert ex.graph.graph_steps > 0 and ex.graph.eager_steps == 0
+    ex.close()
     assert any(len(step) > 1 for step in sched.step_log)                   # requests shared steps
     assert any(d for step in sched.step_log for *_, d in step)              # some were split into ranges
     alone = {}

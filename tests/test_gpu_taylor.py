@@ -90,5 +90,5 @@ def test_taylor_flag_is_rejected_by_the_fused_path():
     ops.ensure_init(torch.device("cuda", 0))
     prm = L.params(4, 3.0, 4, _flags(3))
     f = L.raw("sh_render_forward")
-    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, None, 0, None) == \
+    assert f(None, None, None, None, None, 10, 1, ctypes.byref(prm), None, None, None, 0, None, 0, None) == \
         L.SHV_ERR_UNSUPPORTED

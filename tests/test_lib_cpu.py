@@ -62,19 +62,19 @@ def test_invalid_parameters_rejected_before_any_device_call(L):
     f = L.raw("sh_visibility_forward")
     st = None
     bad_bands = L.params(9)
-    assert f(None, 10, None, 0, ctypes.byref(bad_bands), None, None, None, 0, st) == L.SHV_ERR_UNSUPPORTED
+    assert f(None, 10, None, 0, ctypes.byref(bad_bands), None, None, 0, None, 0, st) == L.SHV_ERR_UNSUPPORTED
     assert "n_bands" in L.shv_last_error()
     bad_k = L.params(4, 3.0, 13)
-    assert f(None, 10, None, 0, ctypes.byref(bad_k), None, None, None, 0, st) == L.SHV_ERR_UNSUPPORTED
+    assert f(None, 10, None, 0, ctypes.byref(bad_k), None, None, 0, None, 0, st) == L.SHV_ERR_UNSUPPORTED
     neg = L.params(4)
-    assert f(None, -5, None, 0, ctypes.byref(neg), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert f(None, -5, None, 0, ctypes.byref(neg), None, None, 0, None, 0, st) == L.SHV_ERR_INVALID_ARG
     bad_eps = L.params(4, -1.0)
-    assert f(None, 10, None, 0, ctypes.byref(bad_eps), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+    assert f(None, 10, None, 0, ctypes.byref(bad_eps), None, None, 0, None, 0, st) == L.SHV_ERR_INVALID_ARG
     # unknown bit; both layouts; quadrature or product with another flag; Taylor without an order, with
     # order 9, with a layout flag; an order without the Taylor flag
     for bad_flags in (32, 3, 5, 6, 9, 12, 16, 16 | (9 << 8), 16 | (2 << 8) | 1, 2 << 8):
         flags = L.shv_params(4, 4, 3.0, bad_flags)
-        assert f(None, 10, None, 0, ctypes.byref(flags), None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
+        assert f(None, 10, None, 0, ctypes.byref(flags), None, None, 0, None, 0, st) == L.SHV_ERR_INVALID_ARG
     g = L.raw("sh_shade")
     assert g(None, None, None, None, 5, None, None, None, 0, st) == L.SHV_ERR_INVALID_ARG
 
@@ -130,6 +130,7 @@ def _fake_scene(L, P, S, n, k=4, flags=0, base=1 << 40):
         setattr(r, name, nxt())
     prm = L.params(n, 3.0, k, flags)
     r.ws_bytes = L.shv_workspace_bytes(P, S, prm)
+    r.saved_bytes = 4 * L.shv_render_saved_floats(P, prm)
     r.P, r.S, r.params = P, S, prm
     return r
 
@@ -300,3 +301,120 @@ def test_bench_state_buffer_covers_every_mode(L):
                 prm = L.params(8, 3.0, k, flags)
                 n = bench.saved_buffer_floats(L, P, prm)
                 assert n >= L.shv_saved_floats(P, prm) and n >= L.shv_render_saved_floats(P, prm)
+
+
+# Modes of forming V and the state each one's forward keeps for the backward.
+SAVED_MODES = {"squaring": 0, "quadrature": 4, "product": 8, "taylor2": 16 | (2 << 8)}
+
+
+@pytest.mark.parametrize("mode", sorted(SAVED_MODES))
+def test_undersized_saved_state_is_refused_before_any_device_call(L, mode):
+    """Every entry point that writes or reads the forward's state takes its
+    size and refuses a buffer one float short with SHV_ERR_WORKSPACE; the
+    refusal comes before the device is queried (there is none here), so a
+    wrong caller gets an error instead of an overrun on the GPU.  The product
+    chain keeps no state (its buffer may be NULL); for it the undersized
+    workspace is what is refused."""
+    P, S = 1000, 20
+    prm = L.params(4, 3.0, 4, SAVED_MODES[mode])
+    ptr = 1 << 40                                   # aligned fake device addresses, never dereferenced
+    floats = L.shv_saved_floats(P, prm)
+    ws_bytes = L.shv_workspace_bytes(P, S, prm)
+    fwd, bwd = L.raw("sh_visibility_forward"), L.raw("sh_visibility_backward")
+    if mode == "product":
+        assert floats == 0
+        assert fwd(ptr, P, ptr, S, ctypes.byref(prm), ptr, None, 0, ptr, 0, None) in (L.SHV_ERR_NOT_INITIALIZED,
+                                                                                      L.SHV_ERR_HIP)
+        assert bwd(ptr, ptr, ptr, P, ptr, S, ctypes.byref(prm), None, 0, ptr, ptr, ptr, ws_bytes - 256,
+                   None) == L.SHV_ERR_WORKSPACE
+        return
+    short = 4 * floats - 4
+    assert fwd(ptr, P, ptr, S, ctypes.byref(prm), ptr, ptr, short, ptr, ws_bytes, None) == L.SHV_ERR_WORKSPACE
+    assert "saved has" in L.shv_last_error()
+    assert bwd(ptr, ptr, ptr, P, ptr, S, ctypes.byref(prm), ptr, short, ptr, ptr, ptr, ws_bytes,
+               None) == L.SHV_ERR_WORKSPACE
+    assert bwd(ptr, ptr, ptr, P, ptr, S, ctypes.byref(prm), None, 0, ptr, ptr, ptr, ws_bytes,
+               None) == L.SHV_ERR_INVALID_ARG          # the backward needs the state
+    # exactly the size passes the check (the call then stops at the missing device)
+    assert fwd(ptr, P, ptr, S, ctypes.byref(prm), ptr, ptr, 4 * floats, ptr, ws_bytes, None) in (
+        L.SHV_ERR_NOT_INITIALIZED, L.SHV_ERR_HIP)
+
+
+def test_undersized_render_state_is_refused_before_any_device_call(L):
+    P, S = 777, 33
+    prm = L.params(8)
+    ptr = 1 << 40
+    floats = L.shv_render_saved_floats(P, prm)
+    assert floats == (1 + 4 * 64) * P + 64 * 64
+    ws_bytes = L.shv_workspace_bytes(P, S, prm)
+    f, b = L.raw("sh_render_forward"), L.raw("sh_render_backward")
+    short = 4 * floats - 4
+    assert f(ptr, ptr, ptr, ptr, ptr, P, S, ctypes.byref(prm), ptr, ptr, ptr, short, ptr, ws_bytes,
+             None) == L.SHV_ERR_WORKSPACE
+    assert b(ptr, ptr, ptr, ptr, ptr, P, S, ctypes.byref(prm), ptr, ptr, short, ptr, ptr, ptr, ptr, ptr, ptr,
+             ws_bytes, None) == L.SHV_ERR_WORKSPACE
+    assert f(ptr, ptr, ptr, ptr, ptr, P, S, ctypes.byref(prm), ptr, ptr, ptr + 2, 4 * floats, ptr, ws_bytes,
+             None) == L.SHV_ERR_INVALID_ARG             # misaligned state
+    # the batch table checks each scene's state size too, and names the scene
+    good = _fake_scene(L, 100, 10, 4)
+    bad = _fake_scene(L, 100, 10, 4, base=1 << 41)
+    bad.saved_bytes = good.saved_bytes - 4
+    buf = (ctypes.c_uint8 * L.shv_batch_table_bytes(2))()
+    L.shv_batch_table_build([good], buf)
+    with pytest.raises(RuntimeError, match="scene 1: saved has"):
+        L.shv_batch_table_build([good, bad], buf)
+
+
+def test_graph_arguments_rejected_before_any_device_call(L):
+    f = L.raw("shv_graph_create")
+    out = ctypes.c_void_p()
+    empty = L.shv_batch_grid()
+    assert f(ctypes.byref(empty), 16, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG      # no launch selected
+    assert "no launch" in L.shv_last_error()
+    g = L.shv_batch_grid()
+    g.pair[8] = 4
+    assert f(ctypes.byref(g), 0, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG           # max_scenes
+    assert f(ctypes.byref(g), 16, 6, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG          # unknown flags
+    assert f(ctypes.byref(g), 16, 0, None) == L.SHV_ERR_INVALID_ARG
+    g.pair[0] = 1
+    assert f(ctypes.byref(g), 16, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG          # 0 bands
+    assert out.value is None
+    assert L.raw("shv_graph_launch")(None, None, 0, None) == L.SHV_ERR_INVALID_ARG
+    assert L.raw("shv_graph_destroy")(None) == L.SHV_OK
+    s = L.raw("sh_solve_batched")
+    assert s(None, ctypes.byref(g), None) == L.SHV_ERR_INVALID_ARG
+
+
+def test_autograd_inputs_are_checked_before_the_library():
+    """The autograd functions check shapes, dtypes and devices of every input
+    themselves (the library sees bare pointers): a mismatch raises before any
+    device call, naming the input."""
+    import torch
+
+    from paper_2104_00359_amd import ops
+    P, S, n = 10, 3, 4
+    ok = dict(points=torch.zeros(P, 3), normals=torch.ones(P, 3), albedo=torch.ones(P),
+              spheres=torch.ones(S, 4), light=torch.zeros(n * n))
+    bad = {"normals": torch.ones(P - 1, 3), "albedo": torch.ones(P, 1), "spheres": torch.ones(S, 3),
+           "light": torch.zeros(n * n + 1), "points": torch.zeros(P, 4)}
+    for name, t in bad.items():
+        args = dict(ok, **{name: t})
+        with pytest.raises(ValueError, match=name):
+            ops.shade_sh(args["points"], args["normals"], args["albedo"], args["spheres"], args["light"], n)
+    with pytest.raises(ValueError, match="floating-point"):
+        ops.shade_sh(ok["points"], ok["normals"], torch.ones(P, dtype=torch.int32), ok["spheres"], ok["light"], n)
+    with pytest.raises(RuntimeError, match="GPU only"):
+        ops.shade_sh(ok["points"], ok["normals"], ok["albedo"], ok["spheres"], ok["light"], n)
+    with pytest.raises(ValueError, match="spheres"):
+        ops.visibility_sh(ok["points"], torch.ones(S, 3), n)
+    with pytest.raises(ValueError, match="points"):
+        ops.visibility_sh(torch.zeros(P, 2), ok["spheres"], n)
+    C = 3
+    with pytest.raises(ValueError, match="albedo"):
+        ops.shade_sh_channels(ok["points"], ok["normals"], torch.ones(P, C - 1), ok["spheres"],
+                              torch.zeros(C, n * n), n)
+    with pytest.raises(ValueError, match="light"):
+        ops.shade_sh_channels(ok["points"], ok["normals"], torch.ones(P, C), ok["spheres"],
+                              torch.zeros(C, n * n - 1), n)
+    with pytest.raises(ValueError, match="image"):
+        ops.envmap_to_sh(torch.zeros(8), n)
