@@ -134,15 +134,16 @@ def render_loss(params, scene, idx, w, target, n_bands: int, eps: float = 3.0, n
 
 
 def image_loss(params, scene, idx, w, target_image, n_bands: int, eps: float = 3.0, n_squarings: int = 4,
-               raster_positions: bool = True):
+               raster_positions: bool = True, face_id=None):
     """The inverse problem of Sec. 3.5 on the image (Eqs. 14-16): the
     deformed mesh's vertex radiance (method.forward) is rasterised
     (raster.render's rules; ``scene`` holds faces, camera, width, height) and
     L(theta) = mean over pixels of (I_R - target)^2.  The face of each pixel
-    is decided from the deformed vertices rounded to FP32.  With
-    ``raster_positions`` False the rasteriser's dependence on the vertex
-    positions is cut (gradients through the radiance only).  Returns (loss,
-    d loss / d params, face ids) in FP64."""
+    is decided from the deformed vertices rounded to FP32, or taken from
+    ``face_id`` when given (the map held fixed, which makes the loss smooth in
+    the parameters).  With ``raster_positions`` False the rasteriser's
+    dependence on the vertex positions is cut (gradients through the radiance
+    only).  Returns (loss, d loss / d params, face ids) in FP64."""
     import numpy as np
 
     from . import method, raster
@@ -152,8 +153,8 @@ def image_loss(params, scene, idx, w, target_image, n_bands: int, eps: float = 3
     B = method.forward(x, n, torch.as_tensor(scene["albedo"]).to(DT), c, torch.as_tensor(scene["light"]).to(DT),
                        n_bands, eps, n_squarings)["B"]
     cam = np.asarray(scene["camera"], np.float32)
-    fid = raster.rasterize_ids(x.detach().numpy().astype(np.float32), scene["faces"], cam, scene["width"],
-                               scene["height"])
+    fid = face_id if face_id is not None else raster.rasterize_ids(
+        x.detach().numpy().astype(np.float32), scene["faces"], cam, scene["width"], scene["height"])
     xr = x if raster_positions else x.detach()
     img = raster.shade_pixels(xr, scene["faces"], B, torch.as_tensor(cam).to(DT), fid)
     r = img - torch.as_tensor(target_image).to(DT)
