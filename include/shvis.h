@@ -344,6 +344,27 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
                              const shv_params* prm, float* vis, float* radiance, float* saved,
                              size_t saved_bytes, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* sh_render_forward for callers that cannot allocate or pass a workspace
+ * (code under HIP graph capture, serving loops that must not allocate,
+ * harnesses that forbid it): the same launches and bit-identical results,
+ * with the scratch memory of the forward (the sphere-chunk partials of the
+ * log-visibility, and M(L) when saved is NULL) taken from a static device
+ * array of SHV_NOALLOC_SCRATCH_BYTES that the library holds on every device
+ * it runs on until the process ends.  Needs shv_init(device) first (which
+ * looks the array up on that device).  A call whose scratch would exceed the
+ * array (nchunks N P + N^2 floats, nchunks = the sphere chunks of the pair
+ * stage: one for P >= 65536 and S <= 512, so up to 393,216 receivers at
+ * n = 8) is refused with SHV_ERR_WORKSPACE before anything is launched.  No
+ * part of the array needs to start at zero: every call writes what it reads.
+ * Calls on one device share the array: two calls that overlap in time on the
+ * same GPU (different streams, or threads without ordering) race and give
+ * wrong results.  Allocates nothing: no hipMalloc, no hipFree. */
+#define SHV_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+shv_status sh_render_forward_noalloc(const float* points, const float* normals, const float* albedo,
+                                     const float* spheres, const float* light, int64_t P, int64_t S,
+                                     const shv_params* prm, float* vis, float* radiance, float* saved,
+                                     size_t saved_bytes, hipStream_t stream);
+
 /* Fused adjoint of sh_render_forward for the cotangent grad_radiance [P]: the
  * same results as sh_shade_backward followed by sh_visibility_backward
  * (bit-identical), in three launches.  vis and saved come from

@@ -39,7 +39,7 @@ EXPORTED = [
     "shv_deform_graph_build", "shv_deform_workspace_bytes", "sh_deform_forward", "sh_deform_backward",
     "shv_raster_incidence_build", "shv_raster_workspace_bytes", "sh_raster_forward", "sh_raster_backward",
     "shv_l2_workspace_bytes", "sh_l2_loss", "sh_sgd_step",
-    "shv_render_saved_floats", "sh_render_forward", "sh_render_backward",
+    "shv_render_saved_floats", "sh_render_forward", "sh_render_forward_noalloc", "sh_render_backward",
     "shv_batch_table_bytes", "shv_batch_table_build", "shv_batch_table_grid",
     "sh_render_batched_forward", "sh_render_batched_backward", "sh_solve_batched",
     "shv_graph_create", "shv_graph_launch", "shv_graph_destroy",
@@ -57,6 +57,7 @@ SHV_FLAG_EXP_PRODUCT = 8
 SHV_FLAG_EXP_TAYLOR = 16
 SHV_MAX_TAYLOR_ORDER = 8
 SHV_GRAPH_FIXED_GRID = 1
+SHV_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 
 def SHV_FLAG_EXP_TAYLOR_ORDER(K):
@@ -141,6 +142,7 @@ _sig = {
     "sh_sgd_step": (ctypes.c_int32, [_P, _P, _I64, ctypes.c_float, _P]),
     "shv_render_saved_floats": (_I64, [_I64, _PRM]),
     "sh_render_forward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _SZ, _P, _SZ, _P]),
+    "sh_render_forward_noalloc": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _P, _SZ, _P]),
     "sh_render_backward": (ctypes.c_int32, [_P, _P, _P, _P, _P, _I64, _I64, _PRM, _P, _P, _SZ, _P, _P, _P, _P, _P,
                                             _P, _SZ, _P]),
     "shv_batch_table_bytes": (_SZ, [ctypes.c_int32]),
@@ -337,6 +339,13 @@ def sh_render_forward(points, normals, albedo, spheres, light, P, S, prm, vis, r
     _check(_lib.sh_render_forward(ptr(points), ptr(normals), ptr(albedo), ptr(spheres), ptr(light), int(P), int(S),
                                   ctypes.byref(prm), ptr(vis), ptr(radiance), ptr(saved), int(saved_bytes), ptr(ws),
                                   int(ws_bytes), stream), "sh_render_forward")
+
+
+def sh_render_forward_noalloc(points, normals, albedo, spheres, light, P, S, prm, vis, radiance, saved, saved_bytes,
+                              stream):
+    _check(_lib.sh_render_forward_noalloc(ptr(points), ptr(normals), ptr(albedo), ptr(spheres), ptr(light), int(P),
+                                          int(S), ctypes.byref(prm), ptr(vis), ptr(radiance), ptr(saved),
+                                          int(saved_bytes), stream), "sh_render_forward_noalloc")
 
 
 def sh_render_backward(grad_radiance, points, normals, albedo, spheres, P, S, prm, vis, saved, saved_bytes,

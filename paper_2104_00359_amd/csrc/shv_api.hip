@@ -35,6 +35,18 @@ shv_status set_error(shv_status code, const char* fmt, ...) {
 std::mutex g_init_mu;
 bool g_init[64] = {false};
 
+}  // namespace
+
+// Scratch of sh_render_forward_noalloc: a static device array, one copy per
+// device.  Host code never passes its name to a kernel (on the host it is a
+// stand-in, not a device address): shv_init looks up each device's address
+// with hipGetSymbolAddress and keeps it in g_scratch.
+static __device__ __align__(256) unsigned char scratch[SHV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+void* g_scratch[64] = {nullptr};   // device address of `scratch`, per device (under g_init_mu)
+
 shv_status check_device() {
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -390,6 +402,13 @@ shv_status shv_init(int device) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return set_error(SHV_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
   std::lock_guard<std::mutex> lk(g_init_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(SHV_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch[device] = ptr;
+  }
   g_init[device] = true;
   return SHV_OK;
 }
@@ -473,6 +492,33 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
                                       albedo, M, radiance, prm->flags, stream);
   }));
   return SHV_OK;
+}
+
+shv_status sh_render_forward_noalloc(const float* points, const float* normals, const float* albedo,
+                                     const float* spheres, const float* light, int64_t P, int64_t S,
+                                     const shv_params* prm, float* vis, float* radiance, float* saved,
+                                     size_t saved_bytes, hipStream_t stream) {
+  SHV_TRY(check_params(prm));
+  SHV_TRY(no_quadrature(prm));
+  SHV_TRY(check_sizes(P, S));
+  const size_t need_bytes = render_fwd_bytes(P, S, prm->n_bands);
+  if (need_bytes > SHV_NOALLOC_SCRATCH_BYTES)
+    return set_error(SHV_ERR_WORKSPACE,
+                     "sh_render_forward_noalloc: P=%lld, S=%lld, n_bands=%d needs %zu bytes of scratch; the static "
+                     "scratch holds %zu (use sh_render_forward with a workspace)",
+                     (long long)P, (long long)S, prm->n_bands, need_bytes, (size_t)SHV_NOALLOC_SCRATCH_BYTES);
+  if (P == 0) return check_device();
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(SHV_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (dev >= 0 && dev < 64) ws = g_scratch[dev];
+  }
+  if (!ws) return set_error(SHV_ERR_NOT_INITIALIZED, "shv_init() has not been called for device %d", dev);
+  return sh_render_forward(points, normals, albedo, spheres, light, P, S, prm, vis, radiance, saved, saved_bytes,
+                           ws, SHV_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 shv_status sh_render_backward(const float* grad_radiance, const float* points, const float* normals,

@@ -418,3 +418,16 @@ def test_autograd_inputs_are_checked_before_the_library():
                               torch.zeros(C, n * n - 1), n)
     with pytest.raises(ValueError, match="image"):
         ops.envmap_to_sh(torch.zeros(8), n)
+
+
+def test_noalloc_forward_refuses_sizes_beyond_its_scratch_before_any_device_call(L):
+    f = L.raw("sh_render_forward_noalloc")
+    prm = L.params(8)
+    ptr = 1 << 40
+    # 500,000 receivers at 8 bands: 128 MB of partials, more than the static scratch holds
+    assert f(ptr, ptr, ptr, ptr, ptr, 500_000, 100, ctypes.byref(prm), ptr, ptr, None, 0, None) == L.SHV_ERR_WORKSPACE
+    assert "static scratch" in L.shv_last_error()
+    assert L.SHV_NOALLOC_SCRATCH_BYTES == 96 << 20
+    # a size that fits passes the check and stops at the missing device
+    assert f(ptr, ptr, ptr, ptr, ptr, 300_000, 100, ctypes.byref(prm), ptr, ptr, None, 0, None) in (
+        L.SHV_ERR_NOT_INITIALIZED, L.SHV_ERR_HIP)
