@@ -73,7 +73,8 @@ typedef int32_t shv_status;
  * quadrature and product flags select a different way of forming V. */
 #define SHV_FLAG_EXP_ONE_WAVE 1u   /* exponential: one receiver per lane, one wave per 64 receivers */
 #define SHV_FLAG_EXP_FOUR_WAVES 2u /* exponential: each receiver's squarings spread over 4 waves
-                                      (the default; both layouts give identical bits) */
+                                      (without a layout flag the library picks by band count and
+                                      size; both layouts give identical bits) */
 #define SHV_FLAG_EXP_QUADRATURE 4u /* a different exponential (this flag changes the result): the
                                       projection of the pointwise exponential, V = exp(c) sum_q w_q
                                       exp(Fhat~(w_q)) y(w_q), over the product rule of degree 8n - 1
@@ -437,10 +438,12 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
 
 /* Block counts of the batched launches.  pair[n]: the pair launches of the
  * scenes with n bands; exp[0][n] / exp[1][n]: the exponential launches of
- * those scenes using the one-wave / four-wave layout (the layout each scene's
- * single-scene call would pick from P and flags); finalize: the closing
- * reductions of all scenes.  Index 0 is unused and must be 0.  A group with
- * 0 blocks is not launched. */
+ * those scenes using the one-wave / four-wave layout (the layout the flags
+ * select, else one receiver per lane up to 6 bands and four waves per 64
+ * receivers at 7 and 8; a single-scene call takes one receiver per lane up to
+ * 6 bands only from 65,536 receivers; both layouts give identical bits);
+ * finalize: the closing reductions of all scenes.  Index 0 is unused and
+ * must be 0.  A group with 0 blocks is not launched. */
 typedef struct shv_batch_grid {
   int64_t pair[SHV_MAX_BANDS_API + 1];
   int64_t exp[2][SHV_MAX_BANDS_API + 1];

@@ -1109,7 +1109,7 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     const shv::Split sp = shv::choose_split(in.P, in.S);
     b.nchunks = sp.nchunks;
     b.chunk = sp.chunk;
-    b.four_waves = shv::exp_four_waves(in.P, prm->flags) ? 1 : 0;
+    b.four_waves = shv::exp_four_waves(nb, in.P, prm->flags, true) ? 1 : 0;
     b.pair_tiles = shv::pair_blocks(in.P);
     b.exp_blocks = b.four_waves ? (in.P + 63) / 64 : shv::point_blocks(in.P);
     // receiver range of this call (whole scene by default)

@@ -189,10 +189,16 @@ hipError_t launch_batch_finalize(const void* table, int64_t blocks, hipStream_t 
   return hipGetLastError();
 }
 
-bool exp_four_waves(int64_t P, uint32_t flags) {
+bool exp_four_waves(int nb, int64_t P, uint32_t flags, bool batched) {
   if (flags & SHV_FLAG_EXP_ONE_WAVE) return false;
-  (void)P;
-  return true;  // four waves per 64 receivers: measured faster at every receiver count
+  if (flags & SHV_FLAG_EXP_FOUR_WAVES) return true;
+  // Up to 6 bands a receiver's whole squaring fits one lane's registers, and
+  // one receiver per lane (no LDS exchange, no barriers) is faster than four
+  // waves per 64 receivers; a launch then has 4x fewer blocks, so a single
+  // scene takes it only from 256 blocks (65,536 receivers) up.  At 7 and 8
+  // bands the four-wave layout is faster for the adjoint (both layouts give
+  // identical bits).
+  return !(nb <= 6 && (batched || P >= 65536));
 }
 
 // ---------------------------------------------------------------------------

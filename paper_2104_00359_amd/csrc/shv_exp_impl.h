@@ -612,7 +612,7 @@ template <int NB, bool SHADE>
 hipError_t exp_fwd_nb(const float* Fpart, int nchunks, int64_t P, float eps, int k, float* vis, float* saved,
                       const float* nrm, const float* alb, const float* M, float* rad, uint32_t flags, hipStream_t st) {
   const ShadeArgs sa{nrm, alb, M, rad, nullptr, nullptr, nullptr};
-  if (exp_four_waves(P, flags)) {
+  if (exp_four_waves(NB, P, flags, false)) {
     k_exp_fwd4<NB, SHADE><<<(unsigned)((P + 63) / 64), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, k, vis, saved, sa);
   } else {
     k_exp_fwd<NB, SHADE><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(Fpart, nchunks, P, eps, k, vis, saved, sa);
@@ -625,7 +625,7 @@ hipError_t exp_bwd_nb(const float* gIn, const float* vis, const float* saved, in
                       const float* nrm, const float* alb, const float* M, float* gN, float* gA, float* Lpart,
                       uint32_t flags, hipStream_t st) {
   const ShadeArgs sa{nrm, alb, M, nullptr, gN, gA, Lpart};
-  if (exp_four_waves(P, flags)) {
+  if (exp_four_waves(NB, P, flags, false)) {
     k_exp_bwd4<NB, SHADE><<<(unsigned)((P + 63) / 64), SHV_BLOCK, 0, st>>>(gIn, vis, saved, P, eps, k, W, sa);
   } else {
     k_exp_bwd<NB, SHADE><<<(unsigned)point_blocks(P), SHV_BLOCK, 0, st>>>(gIn, vis, saved, P, eps, k, W, sa);

@@ -147,7 +147,9 @@ hipError_t batch_exp_fwd_nb(const void* table, bool four, int64_t blocks, hipStr
 template <int NB>
 hipError_t batch_exp_bwd_nb(const void* table, bool four, int64_t blocks, hipStream_t st);
 
-bool exp_four_waves(int64_t P, uint32_t flags);
+// Exponential layout of a launch (true: four waves per 64 receivers; false:
+// one receiver per lane): the flags' choice, else by band count and size.
+bool exp_four_waves(int nb, int64_t P, uint32_t flags, bool batched);
 
 // Rasteriser (the camera as in shv_camera).  rec is scratch of raster_record_bytes(T); bins of
 // raster_bin_bytes (forward); part of 12 T floats (per-face corner cotangents, backward).

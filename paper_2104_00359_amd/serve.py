@@ -93,12 +93,14 @@ class StepGraph:
     graph of the library (shv_graph_create), captured once when the executor
     starts, never on the serving path.
 
-    The graph holds the pair and four-wave exponential launches of the band
-    counts in ``bands`` and the closing reductions; each launch sets every
-    node to the exact block count its step needs, so one graph serves steps
-    of any size.  A step the graph does not hold (another band count, the
-    one-wave layout, more than ``max_scenes`` ranges) is launched eagerly
-    instead and counted in ``eager_steps``."""
+    The graph holds the pair launches and the exponential launches of the
+    band counts in ``bands`` (in the layout batched launches take by default:
+    one receiver per lane up to 6 bands, four waves per 64 receivers above)
+    and the closing reductions; each launch sets every node to the exact
+    block count its step needs, so one graph serves steps of any size.  A
+    step the graph does not hold (another band count or layout, more than
+    ``max_scenes`` ranges) is launched eagerly instead and counted in
+    ``eager_steps``."""
 
     def __init__(self, device, bands=(4, 6, 8), max_scenes: int = 1024):
         self.device = device
@@ -106,7 +108,7 @@ class StepGraph:
         groups = _lib.shv_batch_grid()
         for n in bands:
             groups.pair[int(n)] = 1
-            groups.exp[1][int(n)] = 1
+            groups.exp[0 if int(n) <= 6 else 1][int(n)] = 1
         groups.finalize = 1
         self.handle = _lib.shv_graph_create(groups, self.max_scenes)
         self.graph_steps = 0

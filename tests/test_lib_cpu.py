@@ -136,9 +136,9 @@ def _fake_scene(L, P, S, n, k=4, flags=0, base=1 << 40):
 
 
 def test_batch_table_packing_and_grid(L):
-    """Host-side packing: block counts per group follow the single-scene
-    launch shapes (exponential: 64 receivers per block in the four-wave
-    layout, the default, and 256 in the one-wave layout selected by flags)."""
+    """Host-side packing: block counts per group (exponential: 64 receivers
+    per block in the four-wave layout, the default at 7 and 8 bands, and 256
+    in the one-wave layout, the default up to 6 bands or selected by flags)."""
     scenes = [_fake_scene(L, 3000, 40, 8), _fake_scene(L, 70000, 20, 4, flags=L.SHV_FLAG_EXP_ONE_WAVE),
               _fake_scene(L, 777, 37, 8),
               _fake_scene(L, 0, 5, 5), _fake_scene(L, 5000, 100, 8, flags=L.SHV_FLAG_EXP_ONE_WAVE)]
@@ -152,6 +152,12 @@ def test_batch_table_packing_and_grid(L):
     assert exp_one[8] == (5000 + 255) // 256
     assert exp_one[4] == (70000 + 255) // 256 and exp_four[4] == 0
     assert exp_four[5] == 0 and exp_one[5] == 0 and np.ctypeslib.as_array(g.pair)[5] == 0
+    six = [_fake_scene(L, 3000, 40, 6), _fake_scene(L, 3000, 40, 6, flags=L.SHV_FLAG_EXP_FOUR_WAVES)]
+    buf6 = (ctypes.c_uint8 * L.shv_batch_table_bytes(2))()
+    L.shv_batch_table_build(six, buf6)
+    g6 = L.shv_batch_table_grid(buf6)
+    assert np.ctypeslib.as_array(g6.exp)[0][6] == (3000 + 255) // 256
+    assert np.ctypeslib.as_array(g6.exp)[1][6] == (3000 + 63) // 64
     pair = np.ctypeslib.as_array(g.pair)
     assert pair[0] == 0 and pair[8] >= (3000 + 63) // 64 + (777 + 63) // 64 + (5000 + 63) // 64
     assert g.finalize > 0
@@ -184,12 +190,18 @@ def test_batch_receiver_range_validation(L):
         r = _fake_scene(L, 1000, 10, 4)
         r.range_begin, r.range_end = begin, end
         L.shv_batch_table_build([r], buf)
-    r = _fake_scene(L, 1000, 10, 4)
+    r = _fake_scene(L, 1000, 10, 4, flags=L.SHV_FLAG_EXP_FOUR_WAVES)
     r.range_begin, r.range_end, r.defer_reductions = 256, 1000, 1
     L.shv_batch_table_build([r], buf)
     g = L.shv_batch_table_grid(buf)
     assert g.finalize == 0
     assert np.ctypeslib.as_array(g.exp)[1][4] == (1000 + 63) // 64 - 256 // 64
+    r = _fake_scene(L, 1000, 10, 4)                   # 4 bands, batched: one receiver per lane by default
+    r.range_begin, r.range_end = 256, 1000
+    L.shv_batch_table_build([r], buf)
+    g = L.shv_batch_table_grid(buf)
+    assert np.ctypeslib.as_array(g.exp)[0][4] == (1000 + 255) // 256 - 256 // 256
+    assert np.ctypeslib.as_array(g.exp)[1][4] == 0
 
 
 def _attach_host(L, sc, K):
