@@ -189,6 +189,18 @@ def pair_fwd_bytes_per_receiver(n: int, nchunks: int) -> int:
     return 4 * (3 * nchunks + n * n * nchunks)
 
 
+def exp_shade_bwd_bytes(n: int, k: int) -> int:
+    """Algorithmic HBM bytes per receiver of the fused exponential + shading
+    adjoint: it reads the radiance cotangent, V, the saved c and E_0 ..
+    E_{k-1}, the normal and the albedo, and writes W (the cotangent of F'),
+    the normal and albedo gradients and its share of the per-tile lighting
+    partials (N floats per 64 receivers)."""
+    N = n * n
+    reads = 4 * (1 + N + (1 + k * N) + 3 + 1)
+    writes = 4 * (N + 3 + 1) + 4 * N / 64
+    return int(round(reads + writes))
+
+
 def kernel_work(name: str, n: int, k: int, P: int, S: int, channels: int = 1, pixels: int = 0, order: int = 0):
     """(flops, unit count) of one launch of kernel ``name`` (``channels``
     for the multi-channel shading kernels, ``pixels`` = C H W for the
