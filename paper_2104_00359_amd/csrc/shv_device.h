@@ -137,6 +137,29 @@ __device__ __forceinline__ float sel0(bool ok, float v, float other = 0.0f) { re
 
 // Sum over the 64 lanes of a wave; every lane receives the total.  Fixed
 // butterfly order, so the result is deterministic.
+// v + (v moved by the DPP control CTRL) in the rows of ROWS (a lane whose
+// source lies outside its row adds 0; lanes of other rows add 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int m = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true);
+  return v + __int_as_float(m);
+}
+
+// Sum of v over the wave's 64 lanes, complete in lane 63 (the other lanes
+// hold partial sums), with DPP moves only, no LDS: row_shr 1, 2, 4, 8 leave
+// each 16-lane row's sum in its lane 15; row_bcast 15 adds row 0's sum to
+// row 1 and row 2's to row 3, and row_bcast 31 adds lane 31 (rows 0 + 1) to
+// row 3.  A fixed order of additions, so the result is deterministic.
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v = dpp_add<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xF>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   v += __shfl_xor(v, 1, 64);
   v += __shfl_xor(v, 2, 64);

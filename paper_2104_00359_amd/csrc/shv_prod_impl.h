@@ -198,8 +198,8 @@ __device__ __forceinline__ void prod_bwd_group(ProdBwdShared<NB>& sh, int lane, 
       gpx -= gvx;
       gpy -= gvy;
       gpz -= gvz;
-      const float4 tot = make_float4(wave_sum(gvx), wave_sum(gvy), wave_sum(gvz), wave_sum(gr));
-      if (lane == 0) gs_row[s] = tot;
+      const float4 tot = make_float4(wave_sum_last(gvx), wave_sum_last(gvy), wave_sum_last(gvz), wave_sum_last(gr));
+      if (lane == 63) gs_row[s] = tot;
     }
     blocker_vec<NB>(geo, A);
     SqGroup<NB, G>::adj(Vb, A, T);  // group G of 2 (Vb * h)
