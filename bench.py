@@ -313,20 +313,47 @@ def measured_traffic(workload, kernel):
     return None
 
 
+LAST_STEPS = {}
+
+
 def timed(step, stream, warmup, steps):
-    """Average milliseconds per step over ``steps`` steps after ``warmup``,
-    with nothing else in the timed region (no profiling)."""
+    """Average milliseconds per step over ``steps`` steps after ``warmup``
+    (host clock, synchronised on both sides).  Nothing else runs in the timed
+    region except one HIP event record per step on the stream (events created
+    beforehand), whose spacing gives the per-step GPU times kept in
+    LAST_STEPS (median, 10th / 90th percentile, min, max)."""
+    import numpy as np
     import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     with torch.cuda.stream(stream):
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        evs[0].record(stream)
+        for i in range(steps):
             step()
+            evs[i + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+    LAST_STEPS.clear()
+    LAST_STEPS.update({"median": float(np.median(per)), "p10": float(np.percentile(per, 10)),
+                       "p90": float(np.percentile(per, 90)), "min": float(per.min()), "max": float(per.max())})
     return (t1 - t0) * 1e3 / steps
+
+
+def untimed_steps(step, stream, min_steps, min_seconds):
+    """Steps for an untimed leg: at least ``min_steps``, and enough for about
+    ``min_seconds`` of GPU work (measured on one step)."""
+    import torch
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    return max(int(min_steps), int(min_seconds / max(dt, 1e-6)) + 1)
 
 
 def profile_window(step, stream, steps):
@@ -338,7 +365,12 @@ def profile_window(step, stream, steps):
     from paper_2104_00359_amd import _lib
     with torch.cuda.stream(stream):
         torch.cuda.synchronize()
-        _lib.shv_profile_enable(True, capacity=64 * steps + 64)
+        _lib.shv_profile_enable(True, capacity=1024)      # one step first, to count its launches
+        step()
+        _lib.shv_profile_enable(False)
+        torch.cuda.synchronize()
+        per_step = sum(c for c, _ in _lib.shv_profile_report().values())
+        _lib.shv_profile_enable(True, capacity=per_step * steps + 64)
         for _ in range(steps):
             step()
         _lib.shv_profile_enable(False)
@@ -346,11 +378,14 @@ def profile_window(step, stream, steps):
     return _lib.shv_profile_report()
 
 
+PROFILE_SECONDS = 0.75   # GPU work of the per-kernel window (it also takes the GPU past its clock transients)
+
+
 def timed_and_profiled(step, stream, args):
     """(ms per step of the unprofiled timed steps, per-kernel report of the
-    separate window, steps in that window).  The window runs first, untimed
-    (it also brings the GPU to its working clocks)."""
-    n = args.profile_steps or max(args.steps // 4, 5)
+    separate window, steps in that window).  The window runs first, untimed,
+    for at least PROFILE_SECONDS of GPU work."""
+    n = args.profile_steps or untimed_steps(step, stream, max(args.steps // 4, 5), PROFILE_SECONDS)
     prof = profile_window(step, stream, n)
     return timed(step, stream, args.warmup, args.steps), prof, n
 
@@ -427,6 +462,7 @@ def bench_single(args, workload=None, with_cpu=True):
             _lib.sh_visibility_backward(gV, vis, pts, P, sph, S, prm, saved, sb, gP, gS, ws, nb, st)
 
     ms, prof, nprof = timed_and_profiled(step, stream, args)
+    step_ms = dict(LAST_STEPS)
     copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
     order = (flags >> 8) & 15 if flags & _lib.SHV_FLAG_EXP_TAYLOR else 0
@@ -443,6 +479,7 @@ def bench_single(args, workload=None, with_cpu=True):
         "config": {"workload": desc, "receivers": P, "spheres": S, "n_bands": n, "n_squarings": k, "eps": 3.0,
                    "entry_points": path, "visibility": mode},
         "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels), "profiled_steps": nprof,
+        "step_ms": step_ms,
     }
 
 
@@ -526,9 +563,10 @@ def bench_batched(args):
         def step():
             _lib.shv_graph_launch(graph, records, st)
         mode = "shv_graph_launch: table copy + one graph of all batched phases per step"
-    # The untimed legs run first (they also bring the GPU to its working
-    # clocks); then the warm-up and the timed steps.
-    nprof = args.profile_steps or max(args.steps // 4, 5)
+    # The untimed legs run first, for at least PROFILE_SECONDS of GPU work
+    # (they also take the GPU past the clock transients of its first second
+    # under load); then the warm-up and the timed steps.
+    nprof = args.profile_steps or untimed_steps(eager, stream, max(args.steps // 4, 5), PROFILE_SECONDS)
     prof = profile_window(eager, stream, nprof)
     extras = {}
     if not args.no_extras:
@@ -542,14 +580,22 @@ def bench_batched(args):
                                         o["vis"], o["saved"], _lib.nbytes(o["saved"]), o["grad_points"],
                                         o["grad_normals"], o["grad_albedo"], o["grad_spheres"], o["grad_light"],
                                         o["ws"], wsb, st)
-        nseq = max(args.steps // 5, 3)
+        nseq = max(args.steps // 5, 10)
         ms_seq = timed(sequential, stream, 2, nseq)
-        ms_eager = timed(eager, stream, 2, max(args.steps // 5, 3))
+        ms_eager = timed(eager, stream, 2, max(args.steps // 5, 10))
         extras["sequential"] = {"ms_per_step": ms_seq, "value": pairs / (ms_seq * 1e-3), "steps": nseq,
                                 "what": "64 x (sh_render_forward + sh_render_backward), eager"}
         extras["batched_eager"] = {"ms_per_step": ms_eager, "value": pairs / (ms_eager * 1e-3),
                                    "what": "sh_solve_batched, eager launches"}
+    if graph is not None:
+        # A new graph's first few launches are slower now and then (a few ms
+        # each, measured); the steady state is what a serving loop sees, so an
+        # untimed leg of graph launches comes before the warm-up.
+        ngl = untimed_steps(step, stream, 30, 0.25)
+        extras["graph_first_launches"] = {"steps": ngl, "ms_per_step": timed(step, stream, 0, ngl),
+                                       "step_ms": dict(LAST_STEPS)}
     ms = timed(step, stream, args.warmup, args.steps)
+    step_ms = dict(LAST_STEPS)
     copy_calibration(args, dev, stream)
     kernels = kernel_table(prof)
     desc = [(b.n_bands, k, b.P, b.S) for b in bufs]
@@ -565,6 +611,7 @@ def bench_batched(args):
                    "scenes": 64, "pairs_per_step": pairs, "receivers": sum(b.P for b in bufs),
                    "n_squarings": k, "eps": 3.0, "launch": mode},
         "roofline": roof, "cpu_baseline": cpu, "kernels": finish_kernels(kernels), "profiled_steps": nprof,
+        "step_ms": step_ms,
     }
     out.update(extras)
     if "sequential" in out:
@@ -580,7 +627,7 @@ def bench_batched(args):
                         **{m: {key: r[key] for key in ("throughput_rps", "pairs_per_s", "p50_ms", "p99_ms",
                                                       "completed", "unfinished", "failed")} for m, r in res.items()}}
         body = bench_single(args, "body", with_cpu=False)
-        out["body"] = {key: body[key] for key in ("value", "ms_per_step", "roofline", "kernels")}
+        out["body"] = {key: body[key] for key in ("value", "ms_per_step", "step_ms", "roofline", "kernels")}
         out["body"]["workload"] = body["config"]["workload"]
     return out
 

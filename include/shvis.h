@@ -501,6 +501,8 @@ shv_status sh_solve_batched(const void* table_device, const shv_batch_grid* grid
  * graph object is not thread-safe: one thread launches it at a time.
  * shv_graph_create and shv_graph_destroy allocate and free (device table,
  * pinned staging, the graph); shv_graph_launch allocates nothing.
+ * A new graph's first few launches (up to about a dozen) are slower now and
+ * then (a few ms); steady-state launches cost what the eager calls cost.
  * shv_graph_destroy waits for the graph's last launch to finish. */
 #define SHV_GRAPH_FIXED_GRID 1u
 typedef struct shv_graph shv_graph;
