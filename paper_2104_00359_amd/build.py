@@ -2,7 +2,8 @@
 
 Steps: generate the constant tables and unrolled SH-product code
 (csrc/gen_tables.py), compile each HIP translation unit to an object in
-parallel, link a shared library next to this file.
+parallel, link a shared library next to this file; also build the VALU
+issue-rate probe (csrc/valu_rate_probe.hip) next to it.
 """
 from __future__ import annotations
 
@@ -76,6 +77,8 @@ def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> st
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    # The VALU issue-rate probe (a measurement tool, not part of the library).
+    _run([HIPCC, *HIPFLAGS, os.path.join(CSRC, "valu_rate_probe.hip"), "-o", os.path.join(HERE, "valu_rate_probe")])
     return LIB
 
 
