@@ -444,9 +444,20 @@ struct Bwd4Shared {
   float HbX[32][64]; // y_k cotangents on the transfer support
 };
 
+// LDS of the four-wave adjoint.  The shading adjoint and the set-up of the
+// squarings use X (V and Vbar), the partial sums, the lighting tile and the
+// staged M; the squarings' adjoint then reuses all of it for two
+// double-buffered exchanges (E_j by the parity of j, and each step's group
+// outputs), so a step needs one barrier and the block no more LDS.
+template <int NB>
+struct Bwd4Loop {
+  float E[2][NB * NB][64];
+  float T[2][NB * NB][64];
+};
+
 template <int NB, int G, bool SHADE>
 __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Shared& sh, LightTile& LT, float* Ms,
-                                              int64_t bx,
+                                              Bwd4Loop<NB>& LB, int64_t bx,
                                               int lane, int64_t p, bool ok, const float* __restrict__ gIn,
                                               const float* __restrict__ vis, const float* __restrict__ saved,
                                               int64_t P, float eps, int k, float* __restrict__ Wout,
@@ -531,9 +542,10 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     if (sa.Lpart) tile_light_partial<NB>(LT, sa.Lpart + bx * N);
   }
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    Eb[i] = ec * X[1][i][lane];
-    E[i] = X[0][i][lane] / ec;  // E_0 when k = 0; overwritten otherwise
+  for (int i = 0; i < N; ++i) Eb[i] = ec * X[1][i][lane];
+  if (k == 0) {  // E_0 = V / exp(c) when there is no squaring; the loop below loads E_j otherwise
+#pragma unroll
+    for (int i = 0; i < N; ++i) E[i] = X[0][i][lane] / ec;
   }
   const float cbar = ((sh.Cb[0][lane] + sh.Cb[1][lane]) + sh.Cb[2][lane]) + sh.Cb[3][lane];
   // This wave's group of E_j is loaded one step ahead, so the loads are in
@@ -545,38 +557,61 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
     for (int i = 0; i < N; ++i)
       if (group_of<NB>(i) == G) pre[i] = sel0(ok, src[(int64_t)i * P]);
   }
-  for (int j = k - 1; j >= 0; --j) {
-    __syncthreads();  // everyone has read X[0] / X[1] of the previous step
+  __syncthreads();  // every wave has read X and the partials: the loop buffers overlay them from here
+  if (k > 0) {
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) X[0][i][lane] = pre[i];
-    if (j > 0) {
-      const float* src = saved + (int64_t)(1 + (j - 1) * N) * P + q;
+      if (group_of<NB>(i) == G) LB.E[(k - 1) & 1][i][lane] = pre[i];
+    if (k > 1) {
+      const float* src = saved + (int64_t)(1 + (k - 2) * N) * P + q;
 #pragma unroll
       for (int i = 0; i < N; ++i)
         if (group_of<NB>(i) == G) pre[i] = sel0(ok, src[(int64_t)i * P]);
     }
     __syncthreads();
+  }
+  // Step j reads E_j from LB.E[j & 1] (complete since the previous barrier),
+  // stores its group of E_{j-1} into the other buffer (last read at step
+  // j + 1, before that barrier), and exchanges its outputs through
+  // LB.T[j & 1] (last read at step j + 2): one barrier per step.
+  for (int j = k - 1; j >= 0; --j) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) E[i] = X[0][i][lane];
+    for (int i = 0; i < N; ++i) E[i] = LB.E[j & 1][i][lane];
+    if (j > 0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (group_of<NB>(i) == G) LB.E[(j - 1) & 1][i][lane] = pre[i];
+      if (j > 1) {
+        const float* src = saved + (int64_t)(1 + (j - 2) * N) * P + q;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          if (group_of<NB>(i) == G) pre[i] = sel0(ok, src[(int64_t)i * P]);
+      }
+    }
     SqGroup<NB, G>::adj(Eb, E, T);
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (group_of<NB>(i) == G) X[1][i][lane] = T[i];
+      if (group_of<NB>(i) == G) LB.T[j & 1][i][lane] = T[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < N; ++i) Eb[i] = X[1][i][lane];
+    for (int i = 0; i < N; ++i) Eb[i] = LB.T[j & 1][i][lane];
   }
   if (!ok) return;
   exp_epilogue<NB>(E, Eb, cbar, eps, k, P, p, Wout, [](int i) { return group_of<NB>(i) == G; });
 }
 
 template <int NB>
-struct Exp4BwdShared {
+struct Exp4BwdSetup {
   float X[2][NB * NB][64];
   Bwd4Shared sh;
   LightTile LT;
   float Ms[MSupp<NB>::SIZE];  // staged M (fused shading adjoint)
+};
+
+template <int NB>
+union Exp4BwdShared {
+  Exp4BwdSetup<NB> s;  // the shading adjoint and the set-up of the squarings
+  Bwd4Loop<NB> loop;   // the adjoint squarings (overlays s: a barrier separates them)
 };
 
 template <int NB, bool SHADE>
@@ -588,11 +623,11 @@ __device__ __forceinline__ void exp_bwd4_item(const float* __restrict__ gIn, con
   const int64_t p = bx * 64 + lane;
   const bool ok = p < P;
   switch (wave) {
-    case 0: exp_bwd_group<NB, 0, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
-    case 1: exp_bwd_group<NB, 1, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
-    case 2: exp_bwd_group<NB, 2, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 0: exp_bwd_group<NB, 0, SHADE>(S.s.X, S.s.sh, S.s.LT, S.s.Ms, S.loop, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 1: exp_bwd_group<NB, 1, SHADE>(S.s.X, S.s.sh, S.s.LT, S.s.Ms, S.loop, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
+    case 2: exp_bwd_group<NB, 2, SHADE>(S.s.X, S.s.sh, S.s.LT, S.s.Ms, S.loop, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa); break;
     default:
-      exp_bwd_group<NB, 3, SHADE>(S.X, S.sh, S.LT, S.Ms, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa);
+      exp_bwd_group<NB, 3, SHADE>(S.s.X, S.s.sh, S.s.LT, S.s.Ms, S.loop, bx, lane, p, ok, gIn, vis, saved, P, eps, k, Wout, sa);
       break;
   }
 }
@@ -660,7 +695,7 @@ __global__ __launch_bounds__(SHV_BLOCK, FOUR ? 2 : 1) void k_batch_exp_bwd(const
   const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, nullptr, S.grad_normals, S.grad_albedo, S.grad_light ? S.lp : nullptr};
   if constexpr (FOUR) exp_bwd4_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, sh);
-  else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.LT, sh.Ms);
+  else exp_bwd1_item<NB, true>(S.grad_radiance, S.vis, S.saved, S.P, S.eps, S.k, S.W, sa, bx, &sh.s.LT, sh.s.Ms);
 }
 
 template <int NB>
