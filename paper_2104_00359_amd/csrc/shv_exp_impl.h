@@ -100,6 +100,33 @@ SHV_GOF(7)
 SHV_GOF(8)
 #undef SHV_GOF
 
+// The output-group table as a host-and-device constant expression.
+template <int NB>
+__host__ __device__ constexpr int group_entry(int i);
+#define SHV_GENT(n) \
+  template <>       \
+  __host__ __device__ constexpr int group_entry<n>(int i) { return SHV_GRP_##n[i]; }
+SHV_GENT(1)
+SHV_GENT(2)
+SHV_GENT(3)
+SHV_GENT(4)
+SHV_GENT(5)
+SHV_GENT(6)
+SHV_GENT(7)
+SHV_GENT(8)
+#undef SHV_GENT
+
+// The coefficients of output group G in index order: v[0 .. n - 1].
+template <int NB, int G>
+struct GroupRows {
+  int v[NB * NB];
+  int n;
+  constexpr GroupRows() : v{}, n(0) {
+    for (int j = 0; j < NB * NB; ++j)
+      if (group_entry<NB>(j) == G) v[n++] = j;
+  }
+};
+
 // LAMBDA[l][|m|] of coefficient i (constant-folded after unrolling).
 __device__ __forceinline__ float coef_lambda(int i) {
   int l = 0;
@@ -204,19 +231,25 @@ __device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, i
     __syncthreads();
   }
   const int64_t p = bx * SHV_BLOCK + threadIdx.x;
-  if (p >= P) return;
+  // Without shading a lane past the end leaves at once.  The shading's matrix
+  // steps need every lane of the wave: there only waves wholly past the end
+  // leave (no barrier follows), and tail lanes run receiver 0 and store
+  // nothing.
+  if (SHADE ? bx * SHV_BLOCK + (threadIdx.x & ~63) >= P : p >= P) return;
+  const bool ok = p < P;
+  const int64_t q = ok ? p : 0;
   float E[N], O[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) E[i] = Fpart[(int64_t)i * P + p];
+  for (int i = 0; i < N; ++i) E[i] = Fpart[(int64_t)i * P + q];
   for (int c = 1; c < nchunks; ++c) {
-    const float* src = Fpart + (int64_t)c * N * P + p;
+    const float* src = Fpart + (int64_t)c * N * P + q;
 #pragma unroll
     for (int i = 0; i < N; ++i) E[i] += src[(int64_t)i * P];
   }
   const float c = exp_prologue<NB>(E, eps, k);
-  if (saved) saved[p] = c;
+  if (saved && ok) saved[p] = c;
   for (int j = 0; j < k; ++j) {
-    if (saved) {
+    if (saved && ok) {
       float* dst = saved + (int64_t)(1 + j * N) * P + p;
 #pragma unroll
       for (int i = 0; i < N; ++i) dst[(int64_t)i * P] = E[i];
@@ -229,13 +262,14 @@ __device__ __forceinline__ void exp_fwd1_item(const float* __restrict__ Fpart, i
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     E[i] = ec * E[i];
-    vis[(int64_t)i * P + p] = E[i];
+    if (ok) vis[(int64_t)i * P + p] = E[i];
   }
   if constexpr (SHADE) {
     float H[N], Hb[N], nx, ny, nz, ux, uy, uz;
-    load_normal(sa.nrm, P, p, true, nx, ny, nz);
+    load_normal(sa.nrm, P, p, ok, nx, ny, nz);
     transfer<NB>(nx, ny, nz, H, ux, uy, uz);
-    sa.rad[p] = sa.alb[p] * shade_value<NB, false>(E, H, Ms, 0.0f, Hb);
+    const float s = shade_value<NB, false>(E, H, Ms, 0.0f, Hb);
+    if (ok) sa.rad[p] = sa.alb[p] * s;
   }
 }
 
@@ -300,9 +334,8 @@ __device__ __forceinline__ void exp_bwd1_item(const float* __restrict__ gIn, con
         tile_light_partial<NB>(LT, sa.Lpart + tile * N);
       }
     }
-    if (!ok) return;  // no barriers below
-#pragma unroll
-    for (int j = 0; j < N; ++j) Eb[j] = vbar_entry<NB>(j, H, Ms, w);
+    vbar_rows<NB, N>([](int r) { return r; }, H, Ms, w, Eb);
+    if (!ok) return;  // no barriers or matrix steps below
   } else {
 #pragma unroll
     for (int i = 0; i < N; ++i) Eb[i] = gIn[(int64_t)i * P + p];
@@ -509,13 +542,14 @@ __device__ __forceinline__ void exp_bwd_group(float (*X)[NB * NB][64], Bwd4Share
         }
       }
     }
+    constexpr GroupRows<NB, G> GR{};
+    float vb[GR.n > 0 ? GR.n : 1];  // a group may be empty at 1 or 2 bands
+    if constexpr (GR.n > 0) vbar_rows<NB, GR.n>([GR](int r) { return GR.v[r]; }, H, Ms, w, vb);
     float part = 0.0f;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (group_of<NB>(j) != G) continue;
-      const float vb = vbar_entry<NB>(j, H, Ms, w);
-      part = fmaf(vb, V[j], part);
-      X[1][j][lane] = vb;
+    for (int r = 0; r < GR.n; ++r) {
+      part = fmaf(vb[r], V[GR.v[r]], part);
+      X[1][GR.v[r]][lane] = vb[r];
     }
     sh.Cb[G][lane] = part;
     if (G == 2) tile_put_v<NB>(LT, lane, V);

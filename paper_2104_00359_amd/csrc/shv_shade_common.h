@@ -13,6 +13,14 @@
 //   * the lighting gradient is formed per tile of 64 receivers: Q_jk summed
 //     over the tile's receivers in order, contracted with C, and the tile
 //     partials summed in tile order afterwards.
+//
+// The dense sums over M (t = M^T V, Vbar = w M H, and the tile GEMM Q) run on
+// the matrix cores as chains of FP32 MFMA steps.  Each step of
+// v_mfma_f32_4x4x1f32 and of v_mfma_f32_16x16x4f32 (one K index after the
+// other) is one fused multiply-add rounded once, so a chain gives the bits of
+// the fmaf chain that adds the same terms in the same order (checked on the
+// device over 64-step chains: every bit equal); the orders above are those
+// chains' step orders.
 #pragma once
 
 #include "shv_device.h"
@@ -139,25 +147,62 @@ __device__ __forceinline__ float transfer(float nx, float ny, float nz, float (&
   return inv;
 }
 
-// Partial g of sum_k H_k t_k over support columns kk = g, g + 4, ...; also
-// Hb_k = w t_k A_l for those columns (the cotangent of y_k(n_hat)).  Ms is
-// the staged copy of M (stage_M).
-template <int NB, int G, bool ADJ, bool ACC = false>
-__device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const float (&H)[NB * NB],
-                                               const float* Ms, float w, float (&Hb)[NB * NB]) {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One v_mfma_f32_4x4x1f32 step.  The wave's lanes form 16 blocks of four
+// (lanes 4b .. 4b + 3); accumulator i of lane 4b + c gains coef(lane 4b + i)
+// * own(lane 4b + c).  With own the lane's operand of its receiver and coef
+// the coefficient that output slot (lane & 3) needs, each lane's four
+// accumulators are four sums over its own receiver.  All 64 lanes must be
+// active: a lane's coefficient feeds its whole block.
+__device__ __forceinline__ f32x4 mfma_own4(float coef, float own, f32x4 acc) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(coef, own, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.0f, 0.0f, 0.0f, 0.0f}; }
+
+// t[ch][c] = sum_j M_jk V_j over j in index order for the wave group's
+// support columns kk = 4c + G (c < NC) of CH channels (channel ch's staged M
+// at Ms + ch * SZ); vj(j) gives the lane's V_j.  Columns c = 4q .. 4q + 3 form
+// one four-slot chain.
+template <int NB, int G, int CH, typename VF>
+__device__ __forceinline__ void col_sums(VF vj, const float* Ms, float (&t)[CH][MSupp<NB>::CPG]) {
   constexpr int N = NB * NB;
   constexpr int CPG = MSupp<NB>::CPG;
-  constexpr int NC = (MTab<NB>::HS - G + 3) / 4;  // this group's columns kk = G, G + 4, ...
-  // t_kk = sum_j M_jk V_j, j in index order for every column; the group's
-  // columns of one row are contiguous in Ms (vector LDS reads)
-  float t[CPG];
+  constexpr int SZ = MSupp<NB>::SIZE;
+  constexpr int NC = (MTab<NB>::HS - G + 3) / 4;
+  constexpr int NQ = NC > 0 ? (NC + 3) / 4 : 1;  // a group has no column at 1 band
+  const int slot = threadIdx.x & 3;
+  int col[NQ];  // this lane's column in chain q (clamped into the row; that slot is then unused)
 #pragma unroll
-  for (int c = 0; c < CPG; ++c) t[c] = 0.0f;
+  for (int q = 0; q < NQ; ++q) col[q] = G * N * CPG + (4 * q + slot < CPG ? 4 * q + slot : CPG - 1);
+  f32x4 acc[CH][NQ];
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
+  for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) t[c] = fmaf(Ms[MSupp<NB>::at(j, 4 * c + G)], V[j], t[c]);
+    for (int q = 0; q < NQ; ++q) acc[ch][q] = zero4();
+  if constexpr (NC > 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const float v = vj(j);
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[ch][q] = mfma_own4(Ms[ch * SZ + col[q] + j * CPG], v, acc[ch][q]);
+    }
   }
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+    for (int c = 0; c < CPG; ++c) t[ch][c] = c < NC ? acc[ch][c >> 2][c & 3] : 0.0f;
+}
+
+// Partial g of sum_k H_k t_k over support columns kk = g, g + 4, ... from the
+// column sums t of col_sums; also Hb_k = w t_k A_l for those columns (the
+// cotangent of y_k(n_hat)).
+template <int NB, int G, bool ADJ, bool ACC = false>
+__device__ __forceinline__ float shade_from_cols(const float (&t)[MSupp<NB>::CPG], const float (&H)[NB * NB], float w,
+                                                 float (&Hb)[NB * NB]) {
   float s = 0.0f;
   int kk = 0;
 #pragma unroll
@@ -177,45 +222,103 @@ __device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const 
   return s;
 }
 
-// V^T M H in the canonical order (and the y_k cotangents when ADJ).
+// Partial g of sum_k H_k t_k (t_k = sum_j M_jk V_j) over support columns
+// kk = g, g + 4, ..., with the Hb of shade_from_cols.  Ms is the staged copy
+// of M (stage_M).  Called by all 64 lanes of the wave.
+template <int NB, int G, bool ADJ, bool ACC = false>
+__device__ __forceinline__ float shade_partial(const float (&V)[NB * NB], const float (&H)[NB * NB],
+                                               const float* Ms, float w, float (&Hb)[NB * NB]) {
+  float t[1][MSupp<NB>::CPG];
+  col_sums<NB, G, 1>([&](int j) { return V[j]; }, Ms, t);
+  return shade_from_cols<NB, G, ADJ, ACC>(t[0], H, w, Hb);
+}
+
+// V^T M H in the canonical order (and the y_k cotangents when ADJ), all four
+// column groups in one pass over j (their chains interleave).  Called by all
+// 64 lanes of the wave.
 template <int NB, bool ADJ>
 __device__ __forceinline__ float shade_value(const float (&V)[NB * NB], const float (&H)[NB * NB],
-                                             const float* M, float w, float (&Hb)[NB * NB]) {
+                                             const float* Ms, float w, float (&Hb)[NB * NB]) {
+  constexpr int N = NB * NB;
+  constexpr int CPG = MSupp<NB>::CPG;
+  constexpr int NQ = (CPG + 3) / 4;
   if (ADJ) {
 #pragma unroll
-    for (int i = 0; i < NB * NB; ++i) Hb[i] = 0.0f;
+    for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
   }
-  const float s0 = shade_partial<NB, 0, ADJ>(V, H, M, w, Hb);
-  const float s1 = shade_partial<NB, 1, ADJ>(V, H, M, w, Hb);
-  const float s2 = shade_partial<NB, 2, ADJ>(V, H, M, w, Hb);
-  const float s3 = shade_partial<NB, 3, ADJ>(V, H, M, w, Hb);
+  const int slot = threadIdx.x & 3;
+  int col[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) col[q] = 4 * q + slot < CPG ? 4 * q + slot : CPG - 1;
+  f32x4 acc[4][NQ];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[g][q] = zero4();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[g][q] = mfma_own4(Ms[(g * N + j) * CPG + col[q]], V[j], acc[g][q]);
+  }
+  float t[4][CPG];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int c = 0; c < CPG; ++c) t[g][c] = acc[g][c >> 2][c & 3];
+  const float s0 = shade_from_cols<NB, 0, ADJ>(t[0], H, w, Hb);
+  const float s1 = shade_from_cols<NB, 1, ADJ>(t[1], H, w, Hb);
+  const float s2 = shade_from_cols<NB, 2, ADJ>(t[2], H, w, Hb);
+  const float s3 = shade_from_cols<NB, 3, ADJ>(t[3], H, w, Hb);
   return ((s0 + s1) + s2) + s3;
 }
 
-// As shade_value<NB, true>, but adding this channel's y_k cotangents to Hb
-// (several colour channels that share V and H, Eq. 8 per channel).
-template <int NB>
-__device__ __forceinline__ float shade_value_acc(const float (&V)[NB * NB], const float (&H)[NB * NB],
-                                                 const float* M, float w, float (&Hb)[NB * NB]) {
-  const float s0 = shade_partial<NB, 0, true, true>(V, H, M, w, Hb);
-  const float s1 = shade_partial<NB, 1, true, true>(V, H, M, w, Hb);
-  const float s2 = shade_partial<NB, 2, true, true>(V, H, M, w, Hb);
-  const float s3 = shade_partial<NB, 3, true, true>(V, H, M, w, Hb);
-  return ((s0 + s1) + s2) + s3;
-}
-
-// Vbar_j = w sum_k M_jk H_k over the support (k in index order; Ms staged).
-template <int NB>
-__device__ __forceinline__ float vbar_entry(int j, const float (&H)[NB * NB], const float* Ms, float w) {
-  float t = 0.0f;
-  int kk = 0;
+// Vbar_j = w sum_k M_jk H_k over the support (k in index order; Ms staged)
+// for the R rows j = row(0), ..., row(R - 1): out[r] for row(r).  Four rows
+// form one four-slot chain, and up to four chains share a pass over the
+// support.  Called by all 64 lanes of the wave.
+template <int NB, int R, typename RowF>
+__device__ __forceinline__ void vbar_rows(RowF row, const float (&H)[NB * NB], const float* Ms, float w,
+                                          float (&out)[R]) {
+  constexpr int N = NB * NB;
+  constexpr int CPG = MSupp<NB>::CPG;
+  constexpr int NQ = (R + 3) / 4;
+  const int slot = threadIdx.x & 3;
 #pragma unroll
-  for (int l = 0; l < NB; ++l) {
-    if (!h_support(l)) continue;
+  for (int q0 = 0; q0 < NQ; q0 += 4) {
+    constexpr int PASS = 4;
+    int base[PASS];
+    f32x4 acc[PASS];
 #pragma unroll
-    for (int m = -l; m <= l; ++m) t = fmaf(Ms[MSupp<NB>::at(j, kk++)], H[idx(l, m)], t);
+    for (int u = 0; u < PASS; ++u) {
+      const int q = q0 + u < NQ ? q0 + u : NQ - 1;
+      int j = row(4 * q);
+#pragma unroll
+      for (int sl = 1; sl < 4; ++sl)
+        if (4 * q + sl < R) j = slot == sl ? row(4 * q + sl) : j;
+      base[u] = j * CPG;
+      acc[u] = zero4();
+    }
+    int kk = 0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      if (!h_support(l)) continue;
+#pragma unroll
+      for (int m = -l; m <= l; ++m) {
+        const int off = (kk & 3) * N * CPG + (kk >> 2);  // MSupp::at(j, kk) - j * CPG
+        ++kk;
+#pragma unroll
+        for (int u = 0; u < PASS; ++u)
+          if (q0 + u < NQ) acc[u] = mfma_own4(Ms[base[u] + off], H[idx(l, m)], acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PASS; ++u)
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl)
+        if (4 * (q0 + u) + sl < R) out[4 * (q0 + u) + sl] = w * acc[u][sl];
   }
-  return w * t;
 }
 
 // Normal cotangent from Hb (tangential gradient of the SH polynomial / |n|).
@@ -239,8 +342,9 @@ struct alignas(16) LightTile {
 };
 
 // Called by all 256 threads of a block once the tile is filled and synced:
-// Q[j][kk] = sum_x Vt[x][j] Ht[x][kk] (x in order; thread (jj, kq) owns
-// j = 2jj, 2jj+1 and kk = 4kq .. 4kq+3), then Lbar partial
+// Q[j][kk] = sum_x Vt[x][j] Ht[x][kk] (x in order) as 16 x 16 output tiles of
+// v_mfma_f32_16x16x4f32 chains (tile t to wave t mod 4; each step adds four
+// receivers, one K index after the other), then the Lbar partial
 // out[i] = sum_{(j,kk)} C_{i j k} Q[j][kk] (4 strided partials per i).
 // Ends with a barrier, so the tile may be refilled afterwards.  Q is staged
 // in the V rows unless a separate Qbuf (N x 32 floats) is given, in which
@@ -249,34 +353,41 @@ template <int NB>
 __device__ __forceinline__ void tile_light_partial(LightTile& T, float* __restrict__ out, float* Qbuf = nullptr) {
   constexpr int N = NB * NB;
   constexpr int HS = MTab<NB>::HS;
+  constexpr int RT = (N + 15) / 16, CT = (HS + 15) / 16;  // output tiles (rows j, columns kk)
+  constexpr int TPW = (RT * CT + 3) / 4;                    // tiles per wave
   const int tid = threadIdx.x;
-  const int jj = tid & 31, kq = tid >> 5;
-  float q[8];
+  const int wave = tid >> 6, lane = tid & 63;
+  const int r16 = lane & 15, kq = lane >> 4;
+  f32x4 acc[TPW];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q[i] = 0.0f;
-  if (2 * jj < N && 4 * kq < HS) {
-#pragma unroll 8
-    for (int x = 0; x < 64; ++x) {
-      const float2 v = *reinterpret_cast<const float2*>(&T.Vt[x * kTileVS + 2 * jj]);
-      const float4 h = *reinterpret_cast<const float4*>(&T.Ht[x * kTileHS + 4 * kq]);
-      q[0] = fmaf(v.x, h.x, q[0]);
-      q[1] = fmaf(v.x, h.y, q[1]);
-      q[2] = fmaf(v.x, h.z, q[2]);
-      q[3] = fmaf(v.x, h.w, q[3]);
-      q[4] = fmaf(v.y, h.x, q[4]);
-      q[5] = fmaf(v.y, h.y, q[5]);
-      q[6] = fmaf(v.y, h.z, q[6]);
-      q[7] = fmaf(v.y, h.w, q[7]);
+  for (int u = 0; u < TPW; ++u) {
+    acc[u] = zero4();
+    const int t = wave + 4 * u;
+    if (t < RT * CT) {  // uniform over the wave
+      // A row j0 + r16 and B column k0 + r16 stay inside the tile's pitches
+      // (j < 64 <= kTileVS, kk < 32 <= kTileHS); rows and columns past N and
+      // HS only reach outputs that are not stored.
+      const int j0 = 16 * (t / CT), k0 = 16 * (t % CT);
+#pragma unroll 4
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int x = 4 * s4 + kq;
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(T.Vt[x * kTileVS + j0 + r16], T.Ht[x * kTileHS + k0 + r16],
+                                                      acc[u], 0, 0, 0);
+      }
     }
   }
   __syncthreads();
   float* Qs = Qbuf ? Qbuf : T.Vt;  // N x 32
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int u = 0; u < TPW; ++u) {
+    const int t = wave + 4 * u;
+    if (t < RT * CT) {
+      const int kk = 16 * (t % CT) + r16;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = 2 * jj + a, kk = 4 * kq + c;
-      if (j < N && kk < HS) Qs[j * 32 + kk] = q[a * 4 + c];
+      for (int i = 0; i < 4; ++i) {
+        const int j = 16 * (t / CT) + 4 * kq + i;  // output row of accumulator i
+        if (j < N && kk < HS) Qs[j * 32 + kk] = acc[u][i];
+      }
     }
   }
   __syncthreads();

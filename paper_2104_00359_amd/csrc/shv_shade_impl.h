@@ -75,41 +75,14 @@ struct ShadeCh4Shared {
 // Wave G's column group of every channel's shading value: shade_partial's
 // sums (each column over j in index order, then the group's columns in
 // order), for all channels in one pass over the rows, with V_j read from the
-// LDS exchange (Xl[j * 64]) as it is consumed rather than held in registers.
+// LDS exchange (X[j][lane]) as it is consumed rather than held in registers.
 template <int NB, int G, int CH>
 __device__ __forceinline__ void shade_ch_fwd_group(ShadeCh4Shared<NB, CH>& sh, const float (&H)[NB * NB], int lane) {
   constexpr int N = NB * NB;
-  constexpr int CPG = MSupp<NB>::CPG;
-  constexpr int SZ = MSupp<NB>::SIZE;
-  constexpr int NC = (MTab<NB>::HS - G + 3) / 4;
-  float t[CH][CPG];
+  float t[CH][MSupp<NB>::CPG], Hb[N];
+  col_sums<NB, G, CH>([&](int j) { return sh.X[j][lane]; }, sh.Ms, t);
 #pragma unroll
-  for (int c = 0; c < CH; ++c)
-#pragma unroll
-    for (int cc = 0; cc < CPG; ++cc) t[c][cc] = 0.0f;
-#pragma unroll 8
-  for (int j = 0; j < N; ++j) {
-    const float v = sh.X[j][lane];
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc) t[c][cc] = fmaf(sh.Ms[c * SZ + MSupp<NB>::at(j, 4 * cc + G)], v, t[c][cc]);
-  }
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    float s = 0.0f;
-    int kk = 0;
-#pragma unroll
-    for (int l = 0; l < NB; ++l) {
-      if (!h_support(l)) continue;
-#pragma unroll
-      for (int m = -l; m <= l; ++m) {
-        const int col = kk++;
-        if ((col & 3) == G) s = fmaf(H[idx(l, m)], t[c][col >> 2], s);
-      }
-    }
-    sh.Bx[c][G][lane] = s;
-  }
+  for (int c = 0; c < CH; ++c) sh.Bx[c][G][lane] = shade_from_cols<NB, G, false>(t[c], H, 0.0f, Hb);
 }
 
 template <int NB, int CH>
@@ -152,17 +125,16 @@ struct ShadeCh4BwdShared {
   float Ms[CH * MSupp<NB>::SIZE];
   float Sx[CH][4][64];         // shading partials per channel and column group
   union {
-    float HbX[32][64];         // y_k cotangents (summed over channels) on the transfer support
-    float Q[NB * NB * 32];     // later: the lighting GEMM's Q (apart from the V rows, which survive)
+    float HbX[32][64];         // shading blocks: y_k cotangents (summed over channels) on the transfer support
+    float Q[NB * NB * 32];     // lighting blocks: the tile GEMM's Q (the V rows survive)
   };
-  float HsX[32][64];           // H on the transfer support
   float W[CH][64];             // w = Bbar a per channel and receiver
 };
 
 // Wave G's part of the adjoint: its column group of the shading value and of
-// the y_k cotangents (summed over channels), its column group of H kept in
-// LDS, and the V cotangent rows j = G (mod 4), each summed over the channels
-// in channel order.
+// the y_k cotangents (summed over channels; all channels' column sums in one
+// pass, so their matrix chains interleave), and the V cotangent rows
+// j = G (mod 4), each summed over the channels in channel order.
 template <int NB, int G, int CH>
 __device__ __forceinline__ void shade_ch_bwd_group(ShadeCh4BwdShared<NB, CH>& sh, int lane, int64_t p, bool ok,
                                                    int64_t P, const float* __restrict__ nrm,
@@ -170,42 +142,50 @@ __device__ __forceinline__ void shade_ch_bwd_group(ShadeCh4BwdShared<NB, CH>& sh
   constexpr int N = NB * NB;
   constexpr int SZ = MSupp<NB>::SIZE;
   const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
-  float V[N], H[N], Hb[N], ux, uy, uz;
-#pragma unroll
-  for (int i = 0; i < N; ++i) V[i] = sh.LT.Vt[lane * kTileVS + i];
+  float H[N], Hb[N], ux, uy, uz;
   transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
 #pragma unroll
   for (int i = 0; i < N; ++i) Hb[i] = 0.0f;
-#pragma nounroll
-  for (int c = 0; c < CH; ++c)
-    sh.Sx[c][G][lane] = shade_partial<NB, G, true, true>(V, H, sh.Ms + c * SZ, sh.W[c][lane], Hb);
+  {
+    float t[CH][MSupp<NB>::CPG];
+    col_sums<NB, G, CH>([&](int j) { return sh.LT.Vt[lane * kTileVS + j]; }, sh.Ms, t);  // V_j read as consumed
+#pragma unroll
+    for (int c = 0; c < CH; ++c) sh.Sx[c][G][lane] = shade_from_cols<NB, G, true, true>(t[c], H, sh.W[c][lane], Hb);
+  }
   int kk = 0;
 #pragma unroll
   for (int l = 0; l < NB; ++l) {
     if (!h_support(l)) continue;
 #pragma unroll
     for (int m = -l; m <= l; ++m) {
-      if ((kk & 3) == G) {
-        sh.HbX[kk][lane] = Hb[idx(l, m)];
-        sh.HsX[kk][lane] = H[idx(l, m)];
-      }
+      if ((kk & 3) == G) sh.HbX[kk][lane] = Hb[idx(l, m)];
       ++kk;
     }
   }
-  if (ok && gV) {
+  constexpr int R = (N - G + 3) / 4;  // rows j = G, G + 4, ... (none for some waves at 1 band)
+  if constexpr (R > 0) {
+    if (!gV) return;  // uniform: the matrix steps need every lane
+    float acc[R], vb[R];
+    vbar_rows<NB, R>([](int r) { return G + 4 * r; }, H, sh.Ms, sh.W[0][lane], acc);
 #pragma nounroll
-    for (int j = G; j < N; j += 4) {
-      float acc = vbar_entry<NB>(j, H, sh.Ms, sh.W[0][lane]);
-#pragma nounroll
-      for (int c = 1; c < CH; ++c) acc += vbar_entry<NB>(j, H, sh.Ms + c * SZ, sh.W[c][lane]);
-      gV[(int64_t)j * P + p] = acc;
+    for (int c = 1; c < CH; ++c) {
+      vbar_rows<NB, R>([](int r) { return G + 4 * r; }, H, sh.Ms + c * SZ, sh.W[c][lane], vb);
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += vb[r];
+    }
+    if (ok) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) gV[(int64_t)(G + 4 * r) * P + p] = acc[r];
     }
   }
 }
 
 // Adjoint of k_shade_ch_fwd.  gB, gA [CH][P]; gV [N][P] and gN [3][P] summed
 // over the channels; Lpart [CH][ceil(P / 64)][N]: one lighting-gradient
-// partial per block (tile of 64 receivers) and channel.
+// partial per tile of 64 receivers and channel.  A tile's work is split over
+// blocks (grid.y = 1 + CH when Lpart is wanted): y = 0 the shading adjoint
+// (abar, Vbar, nbar), y = 1 + c channel c's lighting-gradient GEMM, so more
+// and shorter blocks share the chip at sizes that do not fill it.
 template <int NB, int CH>
 __global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_bwd(const float* __restrict__ gB,
                                                                const float* __restrict__ vis,
@@ -216,19 +196,42 @@ __global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_bwd(const float* __re
                                                                float* __restrict__ gA, float* __restrict__ Lpart) {
   constexpr int N = NB * NB;
   constexpr int SZ = MSupp<NB>::SIZE;
-  constexpr int HS = MTab<NB>::HS;
   __shared__ ShadeCh4BwdShared<NB, CH> sh;
   const int G = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t tile = blockIdx.x;
   const int64_t p = tile * 64 + lane;
   const bool ok = p < P;
   const int64_t q = ok ? p : 0;  // valid receiver for the loads of tail lanes
+  const bool light = blockIdx.y > 0;  // uniform
   load_rows_by_wave<N>(vis, P, p, ok, G, sh.LT.Vt, 1, kTileVS, lane);
+  if (!light) {
 #pragma unroll
-  for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x);
+    for (int c = 0; c < CH; ++c) stage_M<NB>(M + c * N * N, sh.Ms + c * SZ, threadIdx.x);
+  }
   if (G == 0) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) sh.W[c][lane] = sel0(ok, gB[c * P + q] * alb[c * P + q]);
+  }
+  if (light) {
+    float H[N], ux, uy, uz;
+    transfer<NB>(sel0(ok, nrm[q]), sel0(ok, nrm[P + q]), sel0(ok, nrm[2 * P + q], 1.0f), H, ux, uy, uz);
+    __syncthreads();  // W and the V rows in place
+    const int c = (int)blockIdx.y - 1;
+    // w H rows of channel c, wave G writing the support columns kk = G (mod 4)
+    const float w = sh.W[c][lane];
+    int kk = 0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      if (!h_support(l)) continue;
+#pragma unroll
+      for (int m = -l; m <= l; ++m) {
+        if ((kk & 3) == G) sh.LT.Ht[lane * kTileHS + kk] = w * H[idx(l, m)];
+        ++kk;
+      }
+    }
+    __syncthreads();
+    tile_light_partial<NB>(sh.LT, Lpart + (c * ((P + 63) / 64) + tile) * N, sh.Q);
+    return;
   }
   __syncthreads();
   switch (G) {
@@ -261,17 +264,6 @@ __global__ __launch_bounds__(SHV_BLOCK, 2) void k_shade_ch_bwd(const float* __re
     gN[p] = gx;
     gN[P + p] = gy;
     gN[2 * P + p] = gz;
-  }
-  if (!Lpart) return;  // uniform
-  // Q overlays HbX: wave 1 has read HbX before it reaches the first barrier
-  // below, and Q is written only after the GEMM's own barrier.
-  const int64_t tiles = (P + 63) / 64;
-#pragma nounroll
-  for (int c = 0; c < CH; ++c) {
-    // w H rows of this channel (the V rows are already in place)
-    for (int kk = G; kk < HS; kk += 4) sh.LT.Ht[lane * kTileHS + kk] = sh.W[c][lane] * sh.HsX[kk][lane];
-    __syncthreads();
-    tile_light_partial<NB>(sh.LT, Lpart + (c * tiles + tile) * N, sh.Q);
   }
 }
 
@@ -362,7 +354,7 @@ hipError_t shade_ch_fwd_nb(const float* vis, const float* nrm, const float* alb,
 template <int NB>
 hipError_t shade_ch_bwd_nb(const float* gB, const float* vis, const float* nrm, const float* alb, const float* M,
                            int channels, int64_t P, float* gV, float* gN, float* gA, float* Lpart, hipStream_t st) {
-  const unsigned g = (unsigned)pair_blocks(P);
+  const dim3 g((unsigned)pair_blocks(P), Lpart ? 1u + (unsigned)channels : 1u);
   switch (channels) {
 #define SHV_CH_BWD(c) \
   case c: k_shade_ch_bwd<NB, c><<<g, SHV_BLOCK, 0, st>>>(gB, vis, nrm, alb, M, P, gV, gN, gA, Lpart); break;
