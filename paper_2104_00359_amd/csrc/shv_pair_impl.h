@@ -59,10 +59,17 @@ __device__ __forceinline__ PairGeom pair_geom(float px, float py, float pz, floa
 
 // The sphere chunk is needed during the sphere loop, X only after it: they
 // share the storage (a barrier separates them), so staging the spheres costs
-// the forward no LDS at 4 or more bands.
+// the forward no LDS at 4 or more bands.  The waves' partial sums are
+// exchanged half of the coefficients at a time, which halves X and lets more
+// blocks share a CU.
+template <int NB>
+struct PairFwdHalf {
+  static constexpr int N = NB * NB;
+  static constexpr int H = (N + 1) / 2;  // coefficients per exchange
+};
 template <int NB>
 union PairFwdShared {
-  float X[SHV_WAVES_PER_BLOCK - 1][NB * NB][64];
+  float X[SHV_WAVES_PER_BLOCK - 1][PairFwdHalf<NB>::H][64];
   float4 sph[SHV_MAX_CHUNK];
 };
 
@@ -129,20 +136,26 @@ __device__ __forceinline__ void pair_fwd_item(const float* __restrict__ pts, int
       }
     }
   }
-  __syncthreads();  // every wave is done with the staged spheres (X shares their storage)
-  if (wave > 0) {
+  // Coefficient i of the block is ((acc_0 + acc_1) + acc_2) + acc_3 over the
+  // waves, formed by wave 0 in two exchanges of half the coefficients.
+  constexpr int H = PairFwdHalf<NB>::H;
+  float* out = Fpart + (int64_t)by * N * P + p;
 #pragma unroll
-    for (int i = 0; i < N; ++i) X[wave - 1][i][lane] = acc[i];
-  }
-  __syncthreads();
-  if (wave == 0 && ok) {
-    float* out = Fpart + (int64_t)by * N * P + p;
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();  // the spheres (h = 0) or the previous half (h = 1) are no longer read
+    if (wave > 0) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      float v = acc[i];
+      for (int i = h * H; i < N && i < (h + 1) * H; ++i) X[wave - 1][i - h * H][lane] = acc[i];
+    }
+    __syncthreads();
+    if (wave == 0 && ok) {
 #pragma unroll
-      for (int w = 0; w < SHV_WAVES_PER_BLOCK - 1; ++w) v += X[w][i][lane];
-      out[(int64_t)i * P] = v;
+      for (int i = h * H; i < N && i < (h + 1) * H; ++i) {
+        float v = acc[i];
+#pragma unroll
+        for (int w = 0; w < SHV_WAVES_PER_BLOCK - 1; ++w) v += X[w][i - h * H][lane];
+        out[(int64_t)i * P] = v;
+      }
     }
   }
   // Side job for the fused render path, spread over the first chunk's blocks:
