@@ -490,13 +490,15 @@ shv_status sh_solve_batched(const void* table_device, const shv_batch_grid* grid
  *   - refuses, with SHV_ERR_UNSUPPORTED before anything is enqueued, a batch
  *     that needs a group the graph does not hold (or, with
  *     SHV_GRAPH_FIXED_GRID, more blocks in a group than captured),
- *   - sets every graph launch to the exact block count the table needs (1
- *     block, which exits at once, for a group with no work this time), unless
- *     SHV_GRAPH_FIXED_GRID keeps the captured counts (blocks past a group's
- *     work exit at once),
+ *   - disables the graph's launches of groups with no work this time (a
+ *     disabled launch keeps its place in the graph's order and runs nothing)
+ *     and enables the others again, and sets each enabled launch to the exact
+ *     block count the table needs, unless SHV_GRAPH_FIXED_GRID keeps the
+ *     captured counts (blocks past a group's work exit at once),
  *   - enqueues on `stream`: a wait for the graph's previous launch (so
  *     launches on different streams are ordered), the copy of the table into
- *     the graph's device buffer, and the graph.
+ *     the graph's device buffer, and the graph (nothing at all for an empty
+ *     batch).
  * Results are bit-identical to sh_solve_batched on the same table.  The
  * graph object is not thread-safe: one thread launches it at a time.
  * shv_graph_create and shv_graph_destroy allocate and free (device table,

@@ -1287,6 +1287,7 @@ struct shv_graph {
     int lay;
     hipGraphNode_t node;
     hipKernelNodeParams params;
+    bool enabled = true;  // disabled while a launch's batch has no work in the node's group
   };
   std::vector<Node> nodes;
   const void* arg_table = nullptr;      // storage of the kernels' one argument
@@ -1479,16 +1480,24 @@ shv_status shv_graph_launch(shv_graph* g, const shv_scene* scenes, int32_t n_sce
   if (need_grid.finalize > 0 && (g->captured.finalize <= 0 || (fixed && need_grid.finalize > g->captured.finalize)))
     return set_error(SHV_ERR_UNSUPPORTED, "batch needs %lld finalize blocks; the graph holds %lld",
                      (long long)need_grid.finalize, (long long)g->captured.finalize);
-  if (!fixed) {
-    for (auto& n : g->nodes) {
-      const int64_t want = grid_entry(need_grid, n.kind, n.nb, n.lay);
-      const unsigned blocks = (unsigned)std::max<int64_t>(want, 1);
-      if (n.params.gridDim.x != blocks) {
-        n.params.gridDim = dim3(blocks, 1, 1);
-        SHV_HIP(hipGraphExecKernelNodeSetParams(g->exec, n.node, &n.params), "hipGraphExecKernelNodeSetParams");
-      }
+  // Nodes of groups without work are disabled (a disabled node is an empty
+  // node: it keeps its place in the chain and launches nothing), the others
+  // are set to their exact block counts unless the grids are fixed.
+  bool any = false;
+  for (auto& n : g->nodes) {
+    const int64_t want = grid_entry(need_grid, n.kind, n.nb, n.lay);
+    const bool on = want > 0;
+    if (on != n.enabled) {
+      SHV_HIP(hipGraphNodeSetEnabled(g->exec, n.node, on ? 1u : 0u), "hipGraphNodeSetEnabled");
+      n.enabled = on;
+    }
+    any = any || on;
+    if (on && !fixed && n.params.gridDim.x != (unsigned)want) {
+      n.params.gridDim = dim3((unsigned)want, 1, 1);
+      SHV_HIP(hipGraphExecKernelNodeSetParams(g->exec, n.node, &n.params), "hipGraphExecKernelNodeSetParams");
     }
   }
+  if (!any) return SHV_OK;  // an empty batch: nothing to enqueue
   if (g->launched) SHV_HIP(hipStreamWaitEvent(stream, g->done, 0), "hipStreamWaitEvent");
   const size_t bytes = shv::batch_table_bytes(n_scenes);
   SHV_HIP(hipMemcpyAsync(g->table_dev, g->staging[slot], bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync");

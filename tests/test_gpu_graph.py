@@ -2,7 +2,9 @@
 HIP graph behind the C ABI (shv_graph_create / _launch / _destroy): every
 launch equals the eager batched calls bit for bit, over several launches with
 eager work between them, for batches larger and smaller than the one the
-graph was captured with, on two streams, and with fixed captured grids."""
+graph was captured with, for batches without some of its band counts (their
+nodes disabled, then enabled again), on two streams, and with fixed captured
+grids."""
 import ctypes
 
 import numpy as np
@@ -20,6 +22,7 @@ KEYS = ["V", "B", "grad_points", "grad_normals", "grad_albedo", "grad_spheres", 
 FIRST = [(40, 6000, 80, 8), (41, 2500, 40, 6), (42, 900, 200, 4), (43, 7000, 16, 4)]
 BIGGER = [(60, 9000, 120, 8), (61, 5000, 60, 6), (62, 3100, 210, 4), (63, 20000, 32, 8), (64, 300, 5, 6)]
 SMALLER = [(70, 700, 30, 8), (71, 256, 64, 4)]
+ONLY8 = [(75, 3000, 50, 8), (76, 1100, 90, 8)]
 
 
 def _scenes(spec):
@@ -83,7 +86,8 @@ def test_graph_launches_equal_eager_bitwise(fixed):
     from paper_2104_00359_amd import _lib, batch, ops
     dev = torch.device("cuda", 0)
     ops.ensure_init(dev)
-    batches = {name: _scenes(spec) for name, spec in (("first", FIRST), ("bigger", BIGGER), ("smaller", SMALLER))}
+    batches = {name: _scenes(spec) for name, spec in (("first", FIRST), ("bigger", BIGGER), ("smaller", SMALLER),
+                                                       ("only8", ONLY8))}
     refs = {name: run_batched(sc) for name, sc in batches.items()}
     bufs = {name: _buffers(sc) for name, sc in batches.items()}
     grids = {name: batch.Table([b.record() for b in bufs[name]], dev).grid for name in bufs}
@@ -97,7 +101,7 @@ def test_graph_launches_equal_eager_bitwise(fixed):
     try:
         s1 = torch.cuda.Stream(device=dev)
         s2 = torch.cuda.Stream(device=dev)
-        order = ["first", "first", "bigger", "smaller", "first", "bigger"]
+        order = ["first", "first", "bigger", "smaller", "only8", "first", "only8", "bigger"]
         for i, name in enumerate(order):
             _clobber(bufs[name])
             st = s1 if i % 2 == 0 else s2        # consecutive launches alternate streams
