@@ -53,8 +53,8 @@ def test_noalloc_forward_equals_workspace_forward_on_two_calls():
         print(f"call {name}", flush=True)
         a = _forward(L, sc, True, with_saved)
         b = _forward(L, sc, False, with_saved)
-        for key in a:
-            assert np.array_equal(a[key], b[key]), f"{name}: {key}"
+        for key in a:   # bit patterns: the state's row padding is never written and keeps the NaN fill
+            assert np.array_equal(a[key].view(np.uint32), b[key].view(np.uint32)), f"{name}: {key}"
         assert np.isfinite(a["B"]).all()
 
 
