@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--rates", default="100,200,500,1000,2000,5000",
                     help="serve: Poisson arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=4.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--seed", type=int, default=7, help="serve: seed of the arrivals and the request mix")
     ap.add_argument("--chunk-pairs", type=int, default=32 << 20, help="serve: pair bound of a request range")
     ap.add_argument("--step-pairs", type=int, default=128 << 20, help="serve: pair bound of a step")
     ap.add_argument("--modes", default="continuous,one_at_a_time",
@@ -499,7 +500,8 @@ def serve_leg(args, rate, duration, modes):
     large = [batch.scene_buffers(scenegen.large_request_scene(500 + i), dev) for i in range(4)]
     free, _ = torch.cuda.mem_get_info(dev)
     budget = int(free - (16 << 30))
-    pick_rng = np.random.default_rng(7)
+    seed = getattr(args, "seed", 7)
+    pick_rng = np.random.default_rng(seed)
     n_max = int(rate * duration * 1.5 + 100)
     is_large = pick_rng.random(n_max) < 0.1
     which = np.where(is_large, pick_rng.integers(0, 4, n_max), pick_rng.integers(0, 64, n_max))
@@ -520,7 +522,7 @@ def serve_leg(args, rate, duration, modes):
             ex = serve.GpuExecutor(dev, single_scene=True, graphs=False)
             sched = serve.Scheduler(ex, budget, chunk_pairs=None, max_active=1, max_inflight=1, keep_results=False)
         sched.start()
-        r = serve.run_load(sched, make_request, rate, duration, warmup=0.5, seed=7, drain=15.0)
+        r = serve.run_load(sched, make_request, rate, duration, warmup=0.5, seed=seed, drain=15.0)
         sched.stop(timeout=30)
         torch.cuda.synchronize()
         if ex.graph is not None:
@@ -653,7 +655,7 @@ def bench_serve(args):
         "value": best["throughput_rps"] if best else None, "unit": "requests/s", "n_gpus": 1,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "90% requests from the 64-scene distribution (P 5k..50k, S 32..256, n 4/6/8), "
-                               "10% large (P 262144, S 512, n 8); Poisson arrivals, seed 7",
+                               f"10% large (P 262144, S 512, n 8); Poisson arrivals, seed {args.seed}",
                    "duration_s": args.duration, "warmup_s": 0.5, "chunk_pairs": args.chunk_pairs,
                    "step_pairs": args.step_pairs, "memory_budget_gb": round(budget / 2**30, 1),
                    "mean_pairs_per_request": mean_pairs},
