@@ -160,6 +160,46 @@ __device__ __forceinline__ float wave_sum_last(float v) {
   return v;
 }
 
+// The value of v in the lane that DPP control CTRL selects (0 where that lane
+// lies outside the row).
+template <int CTRL>
+__device__ __forceinline__ float dpp_from(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// v[l] + v[l ^ 16] and v[l] + v[l ^ 32] in every lane l, by gfx950's
+// permlane swaps of v with itself (the two results hold v[l] and its partner
+// in some order; the sum is the same bits either way).
+__device__ __forceinline__ float xor16_add(float v) {
+  const int i = __float_as_int(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(i, i, false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_add(float v) {
+  const int i = __float_as_int(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(i, i, false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
+// Totals over the wave of four per-lane values, transposed: lane l returns
+// the total of value (l & 3) (a, b, c, d in that order), complete in lanes
+// 12..15 of every row (so in lanes 60..63).  Lanes l and l ^ 1 first split the
+// four values between them (even lanes keep a and c), lanes l and l ^ 2 then
+// split the two sums, so each lane carries one value from there on: quads of a
+// row by row_shr 4 and 8, rows by the xor-16 and xor-32 swaps.  A fixed order
+// of additions, about 17 instructions for the four sums.
+__device__ __forceinline__ float wave_sum4(float a, float b, float c, float d) {
+  const int lane = threadIdx.x & 63;
+  const bool odd = (lane & 1) != 0, hi = (lane & 2) != 0;
+  const float u = (odd ? b : a) + dpp_from<0xB1>(odd ? a : b);  // quad_perm [1,0,3,2]: lane l ^ 1
+  const float v = (odd ? d : c) + dpp_from<0xB1>(odd ? c : d);
+  float w = (hi ? v : u) + dpp_from<0x4E>(hi ? u : v);           // quad_perm [2,3,0,1]: lane l ^ 2
+  w += dpp_from<0x114>(w);                                        // row_shr:4
+  w += dpp_from<0x118>(w);                                        // row_shr:8
+  w = xor16_add(w);
+  return xor32_add(w);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   v += __shfl_xor(v, 1, 64);
   v += __shfl_xor(v, 2, 64);

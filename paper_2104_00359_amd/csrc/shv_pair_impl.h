@@ -14,10 +14,11 @@
 //   dLoss/dt  = 2 pi sum_lm W_lm P_l(t) r_l^|m| T_m         (g_l' = 2 pi P_l)
 //   dLoss/ds  = grad of sum_lm W_lm g_l r_l^|m| T_m, projected on the tangent
 //   plane, then chained through s = v/|v|, t = sqrt(1 - r^2/|v|^2), v = c - x.
-// Receiver gradients stay in registers; sphere gradients are summed over the
-// wave (DPP row shifts and broadcasts, no LDS), written per sphere to LDS by
-// the wave that owns the sphere, and stored as per-block partials reduced by
-// a second deterministic pass.
+// Receiver gradients stay in registers; a sphere's four gradient values are
+// summed over the wave together (a transposed reduction: DPP moves and
+// gfx950's permlane swaps, no LDS), written per sphere to LDS by the wave
+// that owns the sphere, and stored as per-block partials reduced by a second
+// deterministic pass.
 //
 // Layout: one receiver per lane.  A block holds 64 receivers and 4 waves;
 // grid.y splits the sphere set into chunks and the block's chunk is split
@@ -230,7 +231,7 @@ __device__ __forceinline__ void pair_adjoint(const PairGeom& G, const float (&W)
   gvz = (Gz - sd * G.z) * G.inv;
   gr = 0.0f;
   if (G.t > 0.0f) {
-    const float k = Gt * G.rs / G.t * G.inv;  // dLoss/dt * (-dt/dr)
+    const float k = Gt * G.rs * fast_rcp(G.t) * G.inv;  // dLoss/dt * (-dt/dr); t > 0 here
     const float kd = k * G.rs;                // dLoss/dt * dt/d|v|
     gvx = fmaf(kd, G.x, gvx);
     gvy = fmaf(kd, G.y, gvy);
@@ -280,8 +281,8 @@ __device__ __forceinline__ void pair_bwd_item(const float* __restrict__ Wg, cons
     gpx -= gvx;
     gpy -= gvy;
     gpz -= gvz;
-    const float4 tot = make_float4(wave_sum_last(gvx), wave_sum_last(gvy), wave_sum_last(gvz), wave_sum_last(gr));
-    if (lane == 63) red[s - s0] = tot;  // each sphere of the chunk belongs to one wave
+    const float tot = wave_sum4(gvx, gvy, gvz, gr);  // total of (gvx, gvy, gvz, gr)[lane & 3]
+    if (lane >= 60) reinterpret_cast<float*>(red)[(s - s0) * 4 + (lane & 3)] = tot;  // one wave per sphere
   }
   if (wave > 0) {
     gpx_w[wave - 1][0][lane] = gpx;
