@@ -282,12 +282,15 @@ def roofline(kernels, steps, work):
 
 
 def kernel_source_hash():
-    """SHA-256 over the kernel sources and the C header: measured counter data
-    is only quoted for the build it was taken on."""
+    """SHA-256 over the library's kernel sources and the C header: measured
+    counter data is only quoted for the build it was taken on.  The probes
+    (``*_probe.hip``) are measurement tools outside the library and are left
+    out."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2104_00359_amd", "csrc")
-    for f in sorted(x for x in os.listdir(d) if x.endswith((".h", ".hip")) or x == "gen_tables.py"):
+    for f in sorted(x for x in os.listdir(d)
+                    if (x.endswith((".h", ".hip")) and not x.endswith("_probe.hip")) or x == "gen_tables.py"):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())

@@ -79,6 +79,8 @@ def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> st
     os.replace(tmp, LIB)
     # The VALU issue-rate probe (a measurement tool, not part of the library).
     _run([HIPCC, *HIPFLAGS, os.path.join(CSRC, "valu_rate_probe.hip"), "-o", os.path.join(HERE, "valu_rate_probe")])
+    # The FP32 MFMA probe: rounding, lane layout and issue rate (also a measurement tool).
+    _run([HIPCC, *HIPFLAGS, os.path.join(CSRC, "mfma_probe.hip"), "-o", os.path.join(HERE, "mfma_probe")])
     return LIB
 
 
