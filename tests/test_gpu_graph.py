@@ -144,3 +144,28 @@ def test_graph_refuses_a_batch_it_does_not_hold():
             assert _lib.raw("shv_graph_launch")(g, arr, 9, None) == _lib.SHV_ERR_INVALID_ARG   # > max_scenes
         finally:
             _lib.shv_graph_destroy(g)
+
+
+def test_graph_launch_of_an_empty_batch_enqueues_nothing():
+    """An empty batch disables every node and enqueues nothing (no error, no
+    output touched); the next batch enables its groups again and matches the
+    eager calls bit for bit."""
+    from paper_2104_00359_amd import _lib, batch, ops
+    dev = torch.device("cuda", 0)
+    ops.ensure_init(dev)
+    scenes = _scenes(SMALLER)
+    ref = run_batched(scenes)
+    bufs = _buffers(scenes)
+    g = _lib.shv_graph_create(batch.Table([b.record() for b in bufs], dev).grid, 8)
+    try:
+        st = torch.cuda.current_stream().cuda_stream
+        _clobber(bufs)
+        _lib.shv_graph_launch(g, [], st)
+        torch.cuda.synchronize()
+        assert torch.isnan(bufs[0].out["radiance"]).all()
+        _lib.shv_graph_launch(g, [b.record() for b in bufs], st)
+        torch.cuda.synchronize()
+        _same(bufs, ref, "after an empty batch")
+    finally:
+        torch.cuda.synchronize()
+        _lib.shv_graph_destroy(g)
