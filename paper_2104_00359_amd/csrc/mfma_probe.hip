@@ -16,6 +16,12 @@
 //    one instruction (4x4x1 MFMA, 16x16x4 MFMA, or a plain FMA for
 //    comparison); the best of ten timed launches gives FP32 TFLOP/s
 //    (2 flops per multiply-add).
+// 3. One wave alone.  A single wave runs 1, 2, 4 or 8 interleaved dependent
+//    chains of the same instructions; the shader clock read before and after
+//    gives the cycles per instruction (the best of five launches; the loop
+//    is unrolled eight times, so its compare and branch come once per 8 C
+//    instructions): the dependent latency with one chain, the one-wave issue
+//    interval with eight.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -73,6 +79,69 @@ __global__ __launch_bounds__(256) void k_rate(float* out, float a0, float b0, in
 #pragma unroll
   for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3] + f[i];
   if (s == 12345.678f) out[0] = s;  // keeps the chains live
+}
+
+template <int C, int OP>
+__global__ __launch_bounds__(64) void k_one_wave(float* out, long long* cyc, float a0, float b0, int iters) {
+  const float a = a0 + threadIdx.x * 1e-9f, b = b0 - threadIdx.x * 1e-9f;
+  f32x4 acc[C];
+  float f[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f[i] = threadIdx.x * 1e-3f + i;
+  }
+  const long long t0 = clock64(), w0 = wall_clock64();
+  for (int it = 0; it < iters; it += 8) {  // iters is a multiple of 8
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        if (OP == 0) acc[i] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc[i], 0, 0, 0);
+        if (OP == 1) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+        if (OP == 2) f[i] = fmaf(f[i], a, b);
+      }
+    }
+  }
+  const long long t1 = clock64(), w1 = wall_clock64();
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < C; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3] + f[i];
+  out[threadIdx.x] = s;  // keeps the chains live (out holds one float per lane)
+  if (threadIdx.x == 0) {
+    cyc[0] = t1 - t0;
+    cyc[1] = w1 - w0;
+  }
+}
+
+// Shader-clock cycles per instruction; *ghz gets the shader clock's rate
+// against the constant-rate wall clock over the same launch.
+template <int C, int OP>
+static double one_wave_cycles(float* out, long long* cyc, double* ghz) {
+  const int iters = 4096;
+  long long best = -1, wall = 0;
+  for (int rep = 0; rep < 5; ++rep) {
+    k_one_wave<C, OP><<<1, 64>>>(out, cyc, 1.0001f, 0.9999f, iters);
+    long long h[2] = {0, 0};
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(h, cyc, 16, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    if (best < 0 || h[0] < best) {
+      best = h[0];
+      wall = h[1];
+    }
+  }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) == hipSuccess && khz > 0 && wall > 0)
+    *ghz = (double)best / ((double)wall / (khz * 1e3) * 1e9);
+  return (double)best / ((double)iters * C);
+}
+
+template <int OP>
+static void one_wave_line(float* out, long long* cyc, const char* name) {
+  double ghz = 0;
+  const double c1 = one_wave_cycles<1, OP>(out, cyc, &ghz), c2 = one_wave_cycles<2, OP>(out, cyc, &ghz);
+  const double c4 = one_wave_cycles<4, OP>(out, cyc, &ghz), c8 = one_wave_cycles<8, OP>(out, cyc, &ghz);
+  printf("one_wave_%s_cycles_per_instruction chains 1 %.1f  2 %.1f  4 %.1f  8 %.1f  (shader clock %.2f GHz)\n", name,
+         c1, c2, c4, c8, ghz);
 }
 
 template <int OP>
@@ -139,5 +208,14 @@ int main() {
   printf("mfma_4x4x1_tflops %.1f\n", rate<0>(dout, iters, 4.0));     // 4 multiply-adds per lane per instruction
   printf("mfma_16x16x4_tflops %.1f\n", rate<1>(dout, iters, 16.0));  // 16 per lane per instruction
   printf("valu_fma_tflops %.1f\n", rate<2>(dout, iters, 1.0));
+  long long* dcyc = nullptr;
+  float* dwave = nullptr;  // one float per lane of the single wave
+  if (hipMalloc(&dcyc, 2 * sizeof(long long)) != hipSuccess || hipMalloc(&dwave, 64 * sizeof(float)) != hipSuccess) {
+    printf("allocation failed\n");
+    return 1;
+  }
+  one_wave_line<0>(dwave, dcyc, "mfma_4x4x1");
+  one_wave_line<1>(dwave, dcyc, "mfma_16x16x4");
+  one_wave_line<2>(dwave, dcyc, "valu_fma");
   return 0;
 }
