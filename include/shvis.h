@@ -436,8 +436,10 @@ size_t shv_batch_table_bytes(int32_t n_scenes);
 shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void* table,
                                  size_t table_bytes);
 
-/* Block counts of the batched launches.  pair[n]: the pair launches of the
- * scenes with n bands; exp[0][n] / exp[1][n]: the exponential launches of
+/* Block counts of the batched launches.  pair_fwd[n] / pair_bwd[n]: the pair
+ * forward / pair adjoint launches of the scenes with n bands (the adjoint
+ * splits the spheres into more chunks than the forward, so it has more
+ * blocks); exp[0][n] / exp[1][n]: the exponential launches of
  * those scenes using the one-wave / four-wave layout (the layout the flags
  * select, else one receiver per lane up to 6 bands and four waves per 64
  * receivers at 7 and 8; a single-scene call takes one receiver per lane up to
@@ -445,7 +447,8 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
  * finalize: the closing reductions of all scenes.  Index 0 is unused and
  * must be 0.  A group with 0 blocks is not launched. */
 typedef struct shv_batch_grid {
-  int64_t pair[SHV_MAX_BANDS_API + 1];
+  int64_t pair_fwd[SHV_MAX_BANDS_API + 1];
+  int64_t pair_bwd[SHV_MAX_BANDS_API + 1];
   int64_t exp[2][SHV_MAX_BANDS_API + 1];
   int64_t finalize;
 } shv_batch_grid;
@@ -480,8 +483,9 @@ shv_status sh_solve_batched(const void* table_device, const shv_batch_grid* grid
  * shv_graph_create captures sh_solve_batched into a HIP graph once, over a
  * device copy of the work table that the graph object owns (room for
  * max_scenes scenes).  groups selects the launch groups the graph holds:
- * every entry of groups that is > 0 (pair[n], exp[layout][n], finalize) puts
- * that group's launch into the graph, captured with that block count.  Each
+ * every entry of groups that is > 0 (pair_fwd[n], pair_bwd[n],
+ * exp[layout][n], finalize) puts that group's launch into the graph,
+ * captured with that block count.  Each
  * shv_graph_launch then
  *   - packs the table of `scenes` on the host (the checks of
  *     shv_batch_table_build, errors name the scene) into one of four pinned

@@ -104,7 +104,8 @@ def camera(P, width, height):
 
 class shv_batch_grid(ctypes.Structure):
     """Block counts of the batched launches (see the C header)."""
-    _fields_ = [("pair", ctypes.c_int64 * 9), ("exp", (ctypes.c_int64 * 9) * 2), ("finalize", ctypes.c_int64)]
+    _fields_ = [("pair_fwd", ctypes.c_int64 * 9), ("pair_bwd", ctypes.c_int64 * 9), ("exp", (ctypes.c_int64 * 9) * 2),
+                ("finalize", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p

@@ -190,7 +190,7 @@ struct VisBwdWs {
 };
 
 size_t fwd_bytes(int64_t P, int64_t S, int nb, FwdWs* o = nullptr) {
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::fwd_split(P, S);
   const size_t fpart = align_up((size_t)sp.nchunks * nb * nb * (size_t)P * 4);
   if (o) o->fpart = 0;
   return fpart;
@@ -235,7 +235,7 @@ size_t shade_bytes(int64_t P, int nb, ShadeWs* o = nullptr) {
   return m + lp;
 }
 size_t visbwd_bytes(int64_t P, int64_t S, int nb, VisBwdWs* o = nullptr) {
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::bwd_split(P, S);
   const size_t N = (size_t)nb * nb;
   const size_t w = align_up(N * (size_t)P * 4);
   const size_t gp = align_up((size_t)sp.nchunks * 3 * (size_t)P * 4);
@@ -258,7 +258,7 @@ struct RenderBwdWs {
 // sphere and lighting partials must outlive later ranges' forwards until the
 // closing reductions, so they start after the forward's region.
 size_t render_bwd_bytes(int64_t P, int64_t S, int nb, RenderBwdWs* o = nullptr) {
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::bwd_split(P, S);
   const size_t N = (size_t)nb * nb;
   const size_t w = align_up(N * (size_t)P * 4);
   const size_t base = std::max(w, fwd_bytes(P, S, nb));
@@ -483,7 +483,7 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
   float* Fpart = (float*)ws;
   const int64_t N = (int64_t)nb * nb;
   float* M = saved ? saved + (1 + (int64_t)prm->n_squarings * N) * P : (float*)((char*)ws + fwd_bytes(P, S, nb));
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::fwd_split(P, S);
   SHV_TRY(launch("pair_fwd", stream, [&] {
     return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, light, M, stream);
   }));
@@ -558,7 +558,7 @@ shv_status sh_render_backward(const float* grad_radiance, const float* points, c
   float* gs = (float*)((char*)ws + L.gs);
   float* lp = (float*)((char*)ws + L.lp);
   const float* M = saved + (1 + (int64_t)prm->n_squarings * N) * P;
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::bwd_split(P, S);
   SHV_TRY(launch("exp_shade_bwd", stream, [&] {
     return shv::launch_render_exp_bwd(nb, grad_radiance, vis, saved, P, prm->eps, prm->n_squarings, W, normals,
                                       albedo, M, grad_normals, grad_albedo, grad_light ? lp : nullptr, prm->flags,
@@ -605,7 +605,7 @@ shv_status sh_visibility_forward(const float* points, int64_t P, const float* sp
   SHV_TRY(check_ws(ws, ws_bytes, base + (quadrature(prm) ? quad_bytes(nb, P) : 0)));
   SHV_TRY(check_device());
   float* Fpart = (float*)ws;
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::fwd_split(P, S);
   SHV_TRY(launch("pair_fwd", stream, [&] {
     return shv::launch_pair_fwd(nb, points, P, spheres, (int)S, sp, Fpart, nullptr, nullptr, stream);
   }));
@@ -1002,7 +1002,7 @@ shv_status sh_visibility_backward(const float* grad_vis, const float* vis, const
   float* W = (float*)((char*)ws + L.W);
   float* gp = (float*)((char*)ws + L.gp);
   float* gs = (float*)((char*)ws + L.gs);
-  const shv::Split sp = shv::choose_split(P, S);
+  const shv::Split sp = shv::bwd_split(P, S);
   if (quadrature(prm)) {
     SHV_TRY(launch("exp_quad_bwd", stream, [&] {
       return shv::launch_exp_quad_bwd(nb, grad_vis, vis, saved, P, prm->eps, W, (float*)((char*)ws + base),
@@ -1106,9 +1106,11 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     b.k = prm->n_squarings;
     b.eps = prm->eps;
     b.flags = prm->flags;
-    const shv::Split sp = shv::choose_split(in.P, in.S);
-    b.nchunks = sp.nchunks;
-    b.chunk = sp.chunk;
+    const shv::Split spf = shv::fwd_split(in.P, in.S), spb = shv::bwd_split(in.P, in.S);
+    b.nchunks_f = spf.nchunks;
+    b.chunk_f = spf.chunk;
+    b.nchunks_b = spb.nchunks;
+    b.chunk_b = spb.chunk;
     b.four_waves = shv::exp_four_waves(nb, in.P, prm->flags, true) ? 1 : 0;
     b.pair_tiles = shv::pair_blocks(in.P);
     b.exp_blocks = b.four_waves ? (in.P + 63) / 64 : shv::point_blocks(in.P);
@@ -1132,14 +1134,17 @@ shv_status shv_batch_table_build(const shv_scene* scenes, int32_t n_scenes, void
     b.fin_pts = (need_pair && in.grad_points) ? (int32_t)((3 * in.P + SHV_BLOCK - 1) / SHV_BLOCK) : 0;
     b.fin_cols_s = b.grad_spheres ? (int32_t)(4 * in.S) : 0;
     b.fin_cols_l = in.grad_light ? (int32_t)N : 0;
-    b.n_pair = in.P > 0 ? b.range_tiles * sp.nchunks : 0;
+    b.n_pair_f = in.P > 0 ? b.range_tiles * spf.nchunks : 0;
+    b.n_pair_b = in.P > 0 ? b.range_tiles * spb.nchunks : 0;
     b.n_exp = in.P > 0 ? (r1 + eb - 1) / eb - b.exp_block0 : 0;
     b.n_fin = in.defer_reductions ? 0 : (int64_t)b.fin_pts + (b.fin_cols_s + 15) / 16 + (b.fin_cols_l + 15) / 16;
     const int lay = b.four_waves;
-    b.off_pair = h.total_pair[nb];
+    b.off_pair_f = h.total_pair_f[nb];
+    b.off_pair_b = h.total_pair_b[nb];
     b.off_exp = h.total_exp[lay][nb];
     b.off_fin = tf;
-    h.total_pair[nb] += b.n_pair;
+    h.total_pair_f[nb] += b.n_pair_f;
+    h.total_pair_b[nb] += b.n_pair_b;
     h.total_exp[lay][nb] += b.n_exp;
     tf += b.n_fin;
     h.grp_count[nb] += 1;
@@ -1170,7 +1175,8 @@ shv_status shv_batch_table_grid(const void* table, shv_batch_grid* grid) {
   const shv::BatchHeader& h = *(const shv::BatchHeader*)table;
   shv_batch_grid g{};
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
-    g.pair[nb] = h.total_pair[nb];
+    g.pair_fwd[nb] = h.total_pair_f[nb];
+    g.pair_bwd[nb] = h.total_pair_b[nb];
     g.exp[0][nb] = h.total_exp[0][nb];
     g.exp[1][nb] = h.total_exp[1][nb];
   }
@@ -1183,10 +1189,10 @@ static shv_status check_grid(const shv_batch_grid* g) {
   SHV_TRY(need(g, "grid"));
   const int64_t lim = 0x7fffffff;
   auto bad = [&](int64_t x) { return x < 0 || x > lim; };
-  if (g->pair[0] || g->exp[0][0] || g->exp[1][0])
+  if (g->pair_fwd[0] || g->pair_bwd[0] || g->exp[0][0] || g->exp[1][0])
     return set_error(SHV_ERR_INVALID_ARG, "grid entries for 0 bands must be 0");
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb)
-    if (bad(g->pair[nb]) || bad(g->exp[0][nb]) || bad(g->exp[1][nb]))
+    if (bad(g->pair_fwd[nb]) || bad(g->pair_bwd[nb]) || bad(g->exp[0][nb]) || bad(g->exp[1][nb]))
       return set_error(SHV_ERR_INVALID_ARG, "grid entry for %d bands outside [0, 2^31)", nb);
   if (bad(g->finalize)) return set_error(SHV_ERR_INVALID_ARG, "finalize grid outside [0, 2^31)");
   return SHV_OK;
@@ -1212,7 +1218,7 @@ static const char* batch_name(int phase, int nb, int lay) {
 static shv_status batched_phase(int phase, const shv_batch_grid* g, const void* table, hipStream_t stream) {
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb) {
     if (phase == 0 || phase == 3) {
-      const int64_t blocks = g->pair[nb];
+      const int64_t blocks = phase == 0 ? g->pair_fwd[nb] : g->pair_bwd[nb];
       if (blocks > 0)
         SHV_TRY(launch(batch_name(phase, nb, 1), stream,
                        [&] { return shv::launch_batch_nb(nb, phase, false, table, blocks, stream); }));
@@ -1298,7 +1304,8 @@ namespace {
 
 int64_t grid_entry(const shv_batch_grid& g, int kind, int nb, int lay) {
   if (kind == 4) return g.finalize;
-  if (kind == 0 || kind == 3) return g.pair[nb];
+  if (kind == 0) return g.pair_fwd[nb];
+  if (kind == 3) return g.pair_bwd[nb];
   return g.exp[lay][nb];
 }
 
@@ -1337,8 +1344,9 @@ shv_status graph_capture(shv_graph* g) {
     for (int phase = 0; phase < 4 && st == SHV_OK; ++phase) {
       for (int nb = 1; nb <= SHV_MAX_BANDS_API && st == SHV_OK; ++nb) {
         if (phase == 0 || phase == 3) {
-          if (cap.pair[nb] > 0) {
-            st = launch("graph", cs, [&] { return shv::launch_batch_nb(nb, phase, false, g->table_dev, cap.pair[nb], cs); });
+          const int64_t blocks = phase == 0 ? cap.pair_fwd[nb] : cap.pair_bwd[nb];
+          if (blocks > 0) {
+            st = launch("graph", cs, [&] { return shv::launch_batch_nb(nb, phase, false, g->table_dev, blocks, cs); });
             order.push_back({phase, nb, 0, nullptr, {}});
           }
           continue;
@@ -1415,7 +1423,8 @@ shv_status shv_graph_create(const shv_batch_grid* groups, int32_t max_scenes, ui
   if (flags & ~SHV_GRAPH_FIXED_GRID) return set_error(SHV_ERR_INVALID_ARG, "unknown graph flags 0x%x", flags);
   bool any = groups->finalize > 0;
   for (int nb = 1; nb <= SHV_MAX_BANDS_API; ++nb)
-    any = any || groups->pair[nb] > 0 || groups->exp[0][nb] > 0 || groups->exp[1][nb] > 0;
+    any = any || groups->pair_fwd[nb] > 0 || groups->pair_bwd[nb] > 0 || groups->exp[0][nb] > 0 ||
+          groups->exp[1][nb] > 0;
   if (!any) return set_error(SHV_ERR_INVALID_ARG, "groups selects no launch");
   SHV_TRY(check_device());
   shv_graph* g = new shv_graph();
@@ -1467,14 +1476,19 @@ shv_status shv_graph_launch(shv_graph* g, const shv_scene* scenes, int32_t n_sce
   SHV_TRY(shv_batch_table_grid(g->staging[slot], &need_grid));
   const bool fixed = (g->flags & SHV_GRAPH_FIXED_GRID) != 0;
   // every group with work must be in the graph (and fit it with fixed grids)
+  struct Group {
+    const char* name;
+    int kind, lay;  // as in grid_entry
+  };
+  static const Group kGroups[4] = {
+      {"pair forward", 0, 0}, {"one-wave exponential", 1, 0}, {"four-wave exponential", 1, 1}, {"pair adjoint", 3, 0}};
   for (int nb = 0; nb <= SHV_MAX_BANDS_API; ++nb) {
-    for (int kind = 0; kind < 3; ++kind) {
-      const int64_t want = kind == 0 ? need_grid.pair[nb] : need_grid.exp[kind - 1][nb];
-      const int64_t have = kind == 0 ? g->captured.pair[nb] : g->captured.exp[kind - 1][nb];
+    for (const Group& gr : kGroups) {
+      const int64_t want = grid_entry(need_grid, gr.kind, nb, gr.lay);
+      const int64_t have = grid_entry(g->captured, gr.kind, nb, gr.lay);
       if (want > 0 && (have <= 0 || (fixed && want > have)))
         return set_error(SHV_ERR_UNSUPPORTED, "batch needs %lld blocks in the %s group of %d bands; the graph holds %lld",
-                         (long long)want, kind == 0 ? "pair" : (kind == 1 ? "one-wave exponential" : "four-wave exponential"),
-                         nb, (long long)have);
+                         (long long)want, gr.name, nb, (long long)have);
     }
   }
   if (need_grid.finalize > 0 && (g->captured.finalize <= 0 || (fixed && need_grid.finalize > g->captured.finalize)))

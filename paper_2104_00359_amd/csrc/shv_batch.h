@@ -47,15 +47,17 @@ struct BatchScene {
   int32_t nb, k;
   float eps;
   uint32_t flags;
-  int32_t nchunks, chunk;      // sphere split of the pair kernels
+  int32_t nchunks_f, chunk_f;  // sphere split of the pair forward
+  int32_t nchunks_b, chunk_b;  // sphere split of the pair adjoint
   int32_t four_waves;          // exponential layout
   int32_t fin_pts, fin_cols_s, fin_cols_l;  // closing reductions: point blocks, sphere / lighting columns
   int64_t pair_tiles;          // ceil(P / 64): receiver tiles of the whole scene
   int64_t exp_blocks;          // exponential blocks of the whole scene
   int64_t tile0, range_tiles;  // receiver tiles of this call's range
   int64_t exp_block0;          // first exponential block of the range
-  int64_t n_pair, n_exp, n_fin;        // items per phase
-  int64_t off_pair;            // first pair item within the band count's item space
+  int64_t n_pair_f, n_pair_b, n_exp, n_fin;  // items per phase
+  int64_t off_pair_f;          // first pair-forward item within the band count's item space
+  int64_t off_pair_b;          // first pair-adjoint item within the band count's item space
   int64_t off_exp;             // first exponential item within the (layout, band count) item space
   int64_t off_fin;             // first item of the closing reductions (all scenes)
 };
@@ -63,7 +65,8 @@ struct BatchScene {
 struct BatchHeader {
   int32_t n_scenes;
   int64_t total_fin;
-  int64_t total_pair[SHV_MAX_BANDS_API + 1];     // pair items per band count
+  int64_t total_pair_f[SHV_MAX_BANDS_API + 1];   // pair-forward items per band count
+  int64_t total_pair_b[SHV_MAX_BANDS_API + 1];   // pair-adjoint items per band count
   int32_t grp_begin[SHV_MAX_BANDS_API + 1];      // slice of `order` per band count
   int32_t grp_count[SHV_MAX_BANDS_API + 1];
   int64_t total_exp[2][SHV_MAX_BANDS_API + 1];   // exponential items per (layout, band count)
@@ -102,8 +105,12 @@ struct BatchView {
     return sc[g[lo]];
   }
 
-  __device__ const BatchScene& scene_of(int nb, int64_t item) const {
-    return find(order + h->grp_begin[nb], h->grp_count[nb], item, [](const BatchScene& s) { return s.off_pair; });
+  __device__ const BatchScene& scene_of_pair_fwd(int nb, int64_t item) const {
+    return find(order + h->grp_begin[nb], h->grp_count[nb], item, [](const BatchScene& s) { return s.off_pair_f; });
+  }
+
+  __device__ const BatchScene& scene_of_pair_bwd(int nb, int64_t item) const {
+    return find(order + h->grp_begin[nb], h->grp_count[nb], item, [](const BatchScene& s) { return s.off_pair_b; });
   }
 
   __device__ const BatchScene& scene_of_exp(int four, int nb, int64_t item) const {

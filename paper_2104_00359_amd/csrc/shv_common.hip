@@ -11,11 +11,12 @@
 
 namespace shv {
 
-Split choose_split(int64_t P, int64_t S) {
+// About target_waves waves over the chunks, at least 8 spheres per wave, at
+// most SHV_MAX_CHUNK spheres per chunk.
+static Split split_for(int64_t P, int64_t S, int64_t target_waves) {
   Split sp{1, (int)(S > 0 ? S : 1)};
   if (S <= 0) return sp;
   const int64_t waves = 4 * pair_blocks(P);  // 4 waves per 64-receiver tile
-  const int64_t target_waves = 4096;  // 4 waves per SIMD on 256 CUs x 4 SIMDs
   int64_t n = waves > 0 ? (target_waves + waves - 1) / waves : 1;
   const int64_t max_by_size = (S + 31) / 32;  // keep >= 8 spheres per wave
   if (n > max_by_size) n = max_by_size;
@@ -27,6 +28,15 @@ Split choose_split(int64_t P, int64_t S) {
   sp.nchunks = (int)((S + chunk - 1) / chunk);
   return sp;
 }
+
+// Forward: two waves per SIMD on 256 CUs x 4 SIMDs.  Each chunk writes N
+// floats per receiver that the exponential forward reads back; against the
+// adjoint's target this halves the chunks of scenes under 32,768 receivers
+// (2% off the 64-scene batched step; a 20,000-receiver scene's pair forward
+// loses about what its exponential forward gains).
+Split fwd_split(int64_t P, int64_t S) { return split_for(P, S, 2048); }
+// Adjoint: four waves per SIMD (its receiver partials are 3 floats).
+Split bwd_split(int64_t P, int64_t S) { return split_for(P, S, 4096); }
 
 int64_t point_blocks(int64_t P) { return (P + SHV_BLOCK - 1) / SHV_BLOCK; }
 int64_t pair_blocks(int64_t P) { return (P + 63) / 64; }
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_finalize(const char* __rest
   const BatchScene S = in_global(v.scene_of_fin(item));
   if (!S.grad_radiance) return;  // uniform: scene packed without a cotangent
   const int b = (int)(item - S.off_fin);
-  finalize_item(S.gp, S.nchunks, S.P, S.fin_pts ? S.grad_points : nullptr, S.fin_pts, S.gs, (int)S.pair_tiles,
+  finalize_item(S.gp, S.nchunks_b, S.P, S.fin_pts ? S.grad_points : nullptr, S.fin_pts, S.gs, (int)S.pair_tiles,
                 S.fin_cols_s, S.grad_spheres, S.lp, (int)S.pair_tiles, S.fin_cols_l, S.grad_light, b, buf);
 }
 

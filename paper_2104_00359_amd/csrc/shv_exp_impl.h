@@ -714,8 +714,8 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_exp_fwd(const char* __restr
   const BatchScene S = in_global(v.scene_of_exp(FOUR, NB, item));
   const int64_t bx = S.exp_block0 + (item - S.off_exp);
   const ShadeArgs sa{S.normals, S.albedo, S.M, S.radiance, nullptr, nullptr, nullptr};
-  if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
-  else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, &sh.X[0][0][0]);
+  if constexpr (FOUR) exp_fwd4_item<NB, true>(S.Fpart, S.nchunks_f, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, sh);
+  else exp_fwd1_item<NB, true>(S.Fpart, S.nchunks_f, S.P, S.eps, S.k, S.vis, S.saved, sa, bx, &sh.X[0][0][0]);
 }
 
 template <int NB, bool FOUR>

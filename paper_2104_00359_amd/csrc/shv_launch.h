@@ -11,13 +11,16 @@ namespace shv {
 
 // Split of the sphere set into chunks for the pair kernels ("split-S"): the
 // log-visibility is a sum over spheres (Sec. 3.3.2), so partial sums from
-// sphere chunks add up.  A pure function of (P, S): the same scene is always
-// reduced in the same order.
+// sphere chunks add up, and so do the receiver gradients of the adjoint.
+// Pure functions of (P, S): the same scene is always reduced in the same
+// order.  The forward's chunk partials are N floats per receiver that go
+// through HBM, the adjoint's 3, so the forward takes fewer, longer chunks.
 struct Split {
   int nchunks;
   int chunk;
 };
-Split choose_split(int64_t P, int64_t S);
+Split fwd_split(int64_t P, int64_t S);  // pair forward: partials of F'
+Split bwd_split(int64_t P, int64_t S);  // pair adjoint: receiver-gradient partials
 
 int64_t point_blocks(int64_t P);  // ceil(P / 256)
 int64_t pair_blocks(int64_t P);   // ceil(P / 64): pair-kernel blocks (rows of the sphere partials)

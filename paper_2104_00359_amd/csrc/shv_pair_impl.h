@@ -338,12 +338,12 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_fwd(const char* __rest
   __shared__ PairFwdShared<NB> sh;
   const BatchView v(table);
   const int64_t item = blockIdx.x;
-  if (item >= v.h->total_pair[NB]) return;
-  const BatchScene S = in_global(v.scene_of(NB, item));
-  const int64_t local = item - S.off_pair;
+  if (item >= v.h->total_pair_f[NB]) return;
+  const BatchScene S = in_global(v.scene_of_pair_fwd(NB, item));
+  const int64_t local = item - S.off_pair_f;
   const int64_t tile = local % S.range_tiles;
   const int by = (int)(local / S.range_tiles);
-  pair_fwd_item<NB>(S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.Fpart, S.light,
+  pair_fwd_item<NB>(S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk_f, S.Fpart, S.light,
                     S.M, S.tile0 + tile, by, tile, S.range_tiles, sh);
 }
 
@@ -352,13 +352,13 @@ __global__ __launch_bounds__(SHV_BLOCK) void k_batch_pair_bwd(const char* __rest
   __shared__ PairBwdShared sh;
   const BatchView v(table);
   const int64_t item = blockIdx.x;
-  if (item >= v.h->total_pair[NB]) return;
-  const BatchScene S = in_global(v.scene_of(NB, item));
+  if (item >= v.h->total_pair_b[NB]) return;
+  const BatchScene S = in_global(v.scene_of_pair_bwd(NB, item));
   if (!S.grad_radiance || (!S.grad_points && !S.grad_spheres)) return;  // uniform: nothing to do
-  const int64_t local = item - S.off_pair;
+  const int64_t local = item - S.off_pair_b;
   const int64_t bx = S.tile0 + local % S.range_tiles;
   const int by = (int)(local / S.range_tiles);
-  pair_bwd_item<NB>(S.W, S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk, S.gp,
+  pair_bwd_item<NB>(S.W, S.points, S.P, reinterpret_cast<const float4*>(S.spheres), (int)S.S, S.chunk_b, S.gp,
                     reinterpret_cast<float4*>(S.gs), bx, by, sh);
 }
 

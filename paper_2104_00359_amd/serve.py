@@ -107,7 +107,8 @@ class StepGraph:
         self.max_scenes = int(max_scenes)
         groups = _lib.shv_batch_grid()
         for n in bands:
-            groups.pair[int(n)] = 1
+            groups.pair_fwd[int(n)] = 1
+            groups.pair_bwd[int(n)] = 1
             groups.exp[0 if int(n) <= 6 else 1][int(n)] = 1
         groups.finalize = 1
         self.handle = _lib.shv_graph_create(groups, self.max_scenes)

@@ -139,7 +139,7 @@ def test_graph_replay_and_new_batch_in_same_table():
     eager2 = run_batched(second)
     bufs2 = [batch.scene_buffers(sc, dev) for sc in second]
     rb2 = batch.RenderBatch(bufs2, dev)
-    for name in ("pair", "exp"):
+    for name in ("pair_fwd", "pair_bwd", "exp"):
         a, b = np.ctypeslib.as_array(getattr(rb2.grid, name)), np.ctypeslib.as_array(getattr(rb.grid, name))
         assert np.all(a <= b), name
     assert rb2.grid.finalize <= rb.grid.finalize

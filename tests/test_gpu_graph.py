@@ -60,7 +60,8 @@ def _groups(*grids):
     g = _lib.shv_batch_grid()
     for gr in grids:
         for n in range(9):
-            g.pair[n] = max(g.pair[n], gr.pair[n])
+            g.pair_fwd[n] = max(g.pair_fwd[n], gr.pair_fwd[n])
+            g.pair_bwd[n] = max(g.pair_bwd[n], gr.pair_bwd[n])
             g.exp[0][n] = max(g.exp[0][n], gr.exp[0][n])
             g.exp[1][n] = max(g.exp[1][n], gr.exp[1][n])
         g.finalize = max(g.finalize, gr.finalize)
@@ -95,7 +96,7 @@ def test_graph_launches_equal_eager_bitwise(fixed):
     # fixed grids: captured with room for every batch below
     groups = _groups(grids["first"]) if not fixed else _groups(*grids.values())
     if not fixed:
-        assert any(grids["bigger"].pair[n] > grids["first"].pair[n] for n in range(9))
+        assert any(grids["bigger"].pair_bwd[n] > grids["first"].pair_bwd[n] for n in range(9))
     flags = _lib.SHV_GRAPH_FIXED_GRID if fixed else 0
     g = _lib.shv_graph_create(groups, 16, flags)
     try:

@@ -151,15 +151,33 @@ def test_batch_table_packing_and_grid(L):
     assert exp_four[8] == (3000 + 63) // 64 + (777 + 63) // 64
     assert exp_one[8] == (5000 + 255) // 256
     assert exp_one[4] == (70000 + 255) // 256 and exp_four[4] == 0
-    assert exp_four[5] == 0 and exp_one[5] == 0 and np.ctypeslib.as_array(g.pair)[5] == 0
+    assert exp_four[5] == 0 and exp_one[5] == 0 and np.ctypeslib.as_array(g.pair_fwd)[5] == 0
     six = [_fake_scene(L, 3000, 40, 6), _fake_scene(L, 3000, 40, 6, flags=L.SHV_FLAG_EXP_FOUR_WAVES)]
     buf6 = (ctypes.c_uint8 * L.shv_batch_table_bytes(2))()
     L.shv_batch_table_build(six, buf6)
     g6 = L.shv_batch_table_grid(buf6)
     assert np.ctypeslib.as_array(g6.exp)[0][6] == (3000 + 255) // 256
     assert np.ctypeslib.as_array(g6.exp)[1][6] == (3000 + 63) // 64
-    pair = np.ctypeslib.as_array(g.pair)
-    assert pair[0] == 0 and pair[8] >= (3000 + 63) // 64 + (777 + 63) // 64 + (5000 + 63) // 64
+    # pair items: receiver tiles x sphere chunks, the forward aiming at 2,048
+    # waves and the adjoint at 4,096 (4 waves per tile), at least 8 spheres
+    # per wave and at most 512 spheres per chunk
+    def chunks(P, S, target):
+        waves = 4 * ((P + 63) // 64)
+        c = min(-(-target // waves), -(-S // 32))
+        c = max(c, -(-S // 512), 1)
+        return -(-S // -(-S // c))
+    eight = [(3000, 40), (777, 37), (5000, 100)]
+    pf, pb = np.ctypeslib.as_array(g.pair_fwd), np.ctypeslib.as_array(g.pair_bwd)
+    assert pf[0] == 0 and pb[0] == 0
+    assert pf[8] == sum((P + 63) // 64 * chunks(P, S, 2048) for P, S in eight)
+    assert pb[8] == sum((P + 63) // 64 * chunks(P, S, 4096) for P, S in eight)
+    assert pf[4] == (70000 + 63) // 64 and pb[4] == (70000 + 63) // 64
+    # a 20,000 x 128 scene: 2 forward chunks, 4 adjoint chunks
+    body = (ctypes.c_uint8 * L.shv_batch_table_bytes(1))()
+    L.shv_batch_table_build([_fake_scene(L, 20000, 128, 8)], body)
+    gb = L.shv_batch_table_grid(body)
+    assert chunks(20000, 128, 2048) == 2 and chunks(20000, 128, 4096) == 4
+    assert gb.pair_fwd[8] == 313 * 2 and gb.pair_bwd[8] == 313 * 4
     assert g.finalize > 0
     assert L.shv_batch_table_bytes(-1) == 0
 
@@ -384,11 +402,11 @@ def test_graph_arguments_rejected_before_any_device_call(L):
     assert f(ctypes.byref(empty), 16, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG      # no launch selected
     assert "no launch" in L.shv_last_error()
     g = L.shv_batch_grid()
-    g.pair[8] = 4
+    g.pair_fwd[8] = 4
     assert f(ctypes.byref(g), 0, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG           # max_scenes
     assert f(ctypes.byref(g), 16, 6, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG          # unknown flags
     assert f(ctypes.byref(g), 16, 0, None) == L.SHV_ERR_INVALID_ARG
-    g.pair[0] = 1
+    g.pair_bwd[0] = 1
     assert f(ctypes.byref(g), 16, 0, ctypes.byref(out)) == L.SHV_ERR_INVALID_ARG          # 0 bands
     assert out.value is None
     assert L.raw("shv_graph_launch")(None, None, 0, None) == L.SHV_ERR_INVALID_ARG
