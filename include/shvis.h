@@ -354,7 +354,7 @@ shv_status sh_render_forward(const float* points, const float* normals, const fl
  * it runs on until the process ends.  Needs shv_init(device) first (which
  * looks the array up on that device).  A call whose scratch would exceed the
  * array (nchunks N P + N^2 floats, nchunks = the sphere chunks of the pair
- * stage: one for P >= 65536 and S <= 512, so up to 393,216 receivers at
+ * forward: one for P >= 32768 and S <= 512, so up to 393,216 receivers at
  * n = 8) is refused with SHV_ERR_WORKSPACE before anything is launched.  No
  * part of the array needs to start at zero: every call writes what it reads.
  * Calls on one device share the array: two calls that overlap in time on the
