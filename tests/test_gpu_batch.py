@@ -26,6 +26,7 @@ MIX = [
     (18, 2000, 64, 7, 3, 2, ("grad_points", "grad_spheres", "grad_normals")),
     (19, 1000, 10, 2, 0, 0, ("grad_light",)),
     (20, 4100, 300, 8, 4, 0, ()),
+    (21, 20000, 128, 8, 4, 0, ()),   # 2 forward and 4 adjoint sphere chunks
 ]
 
 
@@ -183,14 +184,15 @@ def test_receiver_ranges_reproduce_whole_scene_bitwise():
     from paper_2104_00359_amd import batch, ops
     dev = torch.device("cuda", 0)
     ops.ensure_init(dev)
-    cases = [(80, 70000, 30, 6), (81, 5000, 100, 8), (82, 1000, 20, 4)]
+    # scene 3 has 2 forward and 4 adjoint sphere chunks
+    cases = [(80, 70000, 30, 6), (81, 5000, 100, 8), (82, 1000, 20, 4), (83, 20000, 128, 8)]
     scenes = [scenegen.scene_random_shell(s, P, S, n) for s, P, S, n in cases]
     refs = [run_render(sc, sc["grad_radiance"]) for sc in scenes]
     bufs = [batch.scene_buffers(sc, dev) for sc in scenes]
     for b in bufs:
         b.allocate(dev)
-    cuts = {0: [0, 256, 20480, 40960, 70000], 1: [0, 2048, 2304, 5000], 2: [0, 1000]}
-    calls = [[(0, 0), (1, 0)], [(0, 1), (2, 0)], [(0, 2), (1, 1)], [(1, 2), (0, 3)]]
+    cuts = {0: [0, 256, 20480, 40960, 70000], 1: [0, 2048, 2304, 5000], 2: [0, 1000], 3: [0, 4096, 12288, 20000]}
+    calls = [[(0, 0), (1, 0), (3, 0)], [(0, 1), (2, 0)], [(0, 2), (1, 1), (3, 1)], [(1, 2), (0, 3), (3, 2)]]
     stream = torch.cuda.current_stream()
     for call in calls:
         recs = []

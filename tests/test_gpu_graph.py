@@ -22,7 +22,7 @@ KEYS = ["V", "B", "grad_points", "grad_normals", "grad_albedo", "grad_spheres", 
 FIRST = [(40, 6000, 80, 8), (41, 2500, 40, 6), (42, 900, 200, 4), (43, 7000, 16, 4)]
 BIGGER = [(60, 9000, 120, 8), (61, 5000, 60, 6), (62, 3100, 210, 4), (63, 20000, 32, 8), (64, 300, 5, 6)]
 SMALLER = [(70, 700, 30, 8), (71, 256, 64, 4)]
-ONLY8 = [(75, 3000, 50, 8), (76, 1100, 90, 8)]
+ONLY8 = [(75, 3000, 50, 8), (76, 1100, 90, 8), (77, 20000, 128, 8)]  # the last: 2 forward, 4 adjoint chunks
 
 
 def _scenes(spec):
