@@ -54,6 +54,12 @@ def test_saved_and_workspace_sizes(L):
     assert 0 < a <= b and a <= c and a % 256 == 0
     # V-sized scratch at least (the adjoint's weights live there)
     assert a >= 64 * 20000 * 4
+    # exactly the render backward's carving at 20,000 x 128: the forward's
+    # chunk partials (2 chunks x N x P), then the receiver-gradient partials
+    # (4 adjoint chunks x 3 x P), the per-tile sphere partials (313 tiles x S
+    # float4) and lighting partials (313 tiles x N), each region 256-aligned
+    tiles = (20000 + 63) // 64
+    assert a == 2 * 64 * 20000 * 4 + 4 * 3 * 20000 * 4 + tiles * 128 * 16 + tiles * 64 * 4
     assert L.shv_workspace_bytes(10, 10, L.params(9)) == 0
     assert L.shv_workspace_bytes(0, 0, prm) >= 0
 
